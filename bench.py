@@ -1,0 +1,188 @@
+#!/usr/bin/env python3
+"""Throughput of bulk xorgens generation on one MI355X.
+
+Workload (one step): 1024 independent streams (stream i seeded from 42 + i),
+2^20 outputs each as uint32, then 2^20 more each as FP32 uniforms in [0, 1)
+by the top-24-bit mapping; each written contiguously (stream-major) to HBM by
+one plain launch per type.  A step produces 2^31 random numbers.  The streams
+advance across steps, so every step generates new numbers.
+
+Prints one JSON line: RN/s of the whole job, the roofline of the uint32
+kernel (HBM write bound, per-launch duration from HIP events on the launch
+stream), and the CPU oracle timed on the host's cores on one full step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+STREAMS = 1024
+N = 1 << 20
+SEED = 42
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_u32.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1108_0486_amd", "csrc", "xg_kernels.hip")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per uint32 launch from the committed rocprofv3 counter runs,
+    or None when they are absent or were taken on another kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(threads: int):
+    """The oracle on one full step of the workload (u32 and f32 of all 1024
+    streams), in slices of 64 streams to bound host memory."""
+    import numpy as np
+    from oracle import oracle as O
+
+    slice_ = 64
+    t0 = time.perf_counter()
+    total = 0
+    for first in range(0, STREAMS, slice_):
+        st = O.OracleStreams(SEED, slice_, first=first)
+        st.u32(N, threads=threads)
+        st.f32(N, threads=threads)
+        total += 2 * slice_ * N
+    dt = time.perf_counter() - t0
+    del np
+    return {"value": total / dt, "unit": "RN/s", "cores": threads, "kind": "oracle",
+            "sample": "one full step: 1024 streams x (2^20 uint32 + 2^20 FP32), plain sequential C oracle, "
+                      "one POSIX thread per share of streams (includes per-slice seeding, %.1f s)" % dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--waves-per-block", type=int, default=None)
+    ap.add_argument("--unroll", type=int, default=None)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(streams are independent and would shard by stream id with no exchange)", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    gs = XorgensStreams(STREAMS, seed=SEED, device=dev)
+    if args.waves_per_block or args.unroll:
+        wpb, un = gs.plain_tune()
+        gs.set_plain_tune(args.waves_per_block or wpb, args.unroll or un)
+    out_u = torch.empty((STREAMS, N), dtype=torch.int32, device=dev)
+    out_f = torch.empty((STREAMS, N), dtype=torch.float32, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        gs.u32(N, out=out_u, stream=stream)
+        gs.f32(N, out=out_f, stream=stream)
+    torch.cuda.synchronize()
+
+    K = args.steps
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(K):
+        ev[k][0].record(stream)
+        gs.u32(N, out=out_u, stream=stream)
+        ev[k][1].record(stream)
+        ev[k][2].record(stream)
+        gs.f32(N, out=out_f, stream=stream)
+        ev[k][3].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    u32_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
+    f32_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / K
+    rn_per_step = 2 * STREAMS * N
+    ms_per_step = wall * 1e3 / K
+    bytes_per_launch = 4 * STREAMS * N
+    achieved = bytes_per_launch / (u32_ms * 1e-3) / 1e9
+
+    # Practical write ceiling on the same buffer: torch's own fill kernel.
+    fill_ms = []
+    for _ in range(5):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        out_u.fill_(7)
+        b.record(stream)
+        torch.cuda.synchronize()
+        fill_ms.append(a.elapsed_time(b))
+    fill_gbs = bytes_per_launch / (sorted(fill_ms)[2] * 1e-3) / 1e9
+
+    traffic = measured_traffic()
+    threads = max(1, min(16, os.cpu_count() or 1))
+    cpu = None if args.no_cpu_baseline else cpu_baseline(threads)
+
+    wpb, un = gs.plain_tune()
+    line = {
+        "metric": "RN/s (32-bit) and % of HBM write BW",
+        "value": rn_per_step / (ms_per_step * 1e-3),
+        "unit": "RN/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "bulk uniform generation: 1024 xorgens streams (seed 42 + i) x 2^20 outputs, "
+                        "uint32 then FP32 [0,1) (top-24-bit), one plain launch per type, stream-major in HBM",
+            "streams": STREAMS,
+            "outputs_per_stream_per_type": N,
+            "rn_per_step": rn_per_step,
+            "params": "(r,s,a,b,c,d)=(128,65,15,14,12,17), w=32, omega=0x9E3779B9, gamma=16",
+            "launch": {"waves_per_block": wpb, "unroll": un},
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "kernel": "k_generate<u32> (xg_generate_u32)",
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "avg_launch_ms": u32_ms,
+        },
+        "kernels_ms": {"u32": u32_ms, "f32": f32_ms},
+        "f32_GBs": bytes_per_launch / (f32_ms * 1e-3) / 1e9,
+        "fill_ceiling_GBs": fill_gbs,
+        "frac_of_fill_ceiling": achieved / fill_gbs,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,231 @@
+/*
+ * xg.h -- C ABI of libxg: many independent xorgens streams generated on an
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The generator is xorgens as used by xorgensGP (Nandapalan, Brent, Murray &
+ * Rendell, arXiv:1108.0486):
+ *   - Section 2: x_i = x_{i-r}(I + L^a)(I + R^b) xor x_{i-s}(I + L^c)(I + R^d)
+ *     with (r,s,a,b,c,d) = (128,65,15,14,12,17) on 32-bit words; the r = 128
+ *     words form a circular buffer and x_i replaces x_{i-r};
+ *   - Section 1.5: Weyl sequence W_k = W_{k-1} + omega (mod 2^32) and the output
+ *     of Eq. (1), out_k = x_k + (W_k xor (W_k >> gamma)) (mod 2^32), with
+ *     omega = 0x9E3779B9 (the odd integer nearest 2^31 (sqrt 5 - 1)) and
+ *     gamma = 16;
+ *   - Section 2: many independent subsequences, one per group of threads;
+ *     up to 64 consecutive words of one stream are computed at once (the
+ *     terms x_k .. x_{k+C-1} need only older words while C <= s = 65).
+ *
+ * Conventions shared by every entry point:
+ *   - Pointers named d_* are device pointers owned by the caller.  The
+ *     library never allocates, frees or synchronises device memory; each
+ *     generating call only enqueues kernels on `stream` (a hipStream_t passed
+ *     as void*; NULL is the null stream) and returns.
+ *   - Invalid arguments are rejected synchronously with a negative status;
+ *     then nothing is enqueued and no state changes.  A launch failure
+ *     reported by the HIP runtime right after the launch gives XG_EHIP.
+ *     Faults inside a kernel surface at the caller's next synchronisation.
+ *   - Calls that touch the same streams must be ordered by the caller (same
+ *     HIP stream, or events).  Calls on disjoint stream ranges may overlap.
+ *   - All sizes count elements (4-byte words), not bytes, unless named *_bytes.
+ *   - No C++ exception crosses this interface.
+ *
+ * Stream state (device memory, XG_STATE_WORDS 32-bit words per stream, 528 B):
+ *   words [0, 128)   ring[t] = x_{pos-128+t}, the last 128 words of the x-part
+ *   word  128        W_{pos-1}, the last Weyl value used
+ *   word  129        reserved, 0
+ *   words 130, 131   pos, the number of words consumed since seeding
+ *                    (uint64, little endian)
+ * A stream's state is a plain value: copying those 528 bytes out and back is a
+ * checkpoint and a resume.
+ */
+#ifndef XG_H
+#define XG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t xg_status;
+
+#define XG_OK        0
+#define XG_EINVAL   (-1)  /* null pointer, zero or out-of-range argument, bad dtype */
+#define XG_ERANGE   (-2)  /* stream range outside the context, or a size overflow  */
+#define XG_EALIGN   (-3)  /* device pointer not 4-byte (outputs) or 16-byte (state) aligned */
+#define XG_EHIP     (-4)  /* the HIP runtime reported an error */
+#define XG_ENOTSUP  (-5)  /* the current device is not gfx950 */
+#define XG_ENOMEM   (-6)  /* a host-side allocation failed */
+#define XG_EBUSY    (-7)  /* workspace too small for the request table */
+
+#define XG_STATE_WORDS 132u
+
+/* Output types of a request. */
+#define XG_U32     0u  /* out_k as uint32 */
+#define XG_F32     1u  /* (out_k >> 8) * 2^-24 as float, in [0, 1 - 2^-24]; exact */
+#define XG_NORMAL  2u  /* float standard normals by Box-Muller (see xg_generate_normal) */
+
+typedef struct xg_ctx xg_ctx;
+
+/* Bytes of device state for num_streams streams (num_streams * 528). */
+size_t xg_state_bytes(uint64_t num_streams);
+
+/* Seeds num_streams streams into d_state and creates a host-side handle.
+ * Stream i is seeded from seed + i (mod 2^64), as the paper seeds block b with
+ * consecutive values (Section 4).  The paper defers the seeding method to the
+ * xorgens sources; this library's method: SplitMix64 from the stream's seed
+ * yields 129 values whose high 32 bits fill x_{-128} .. x_{-1} and W; a ring
+ * that is all zero gets x_{-1} = 1; then 512 generator steps are discarded and
+ * pos is set to 0.
+ *   out          receives the handle (owned by the caller; free with xg_destroy)
+ *   d_state      device buffer of at least xg_state_bytes(num_streams) bytes,
+ *                16-byte aligned; the handle keeps the pointer, never the memory
+ *   state_bytes  size of d_state in bytes
+ *   num_streams  1 .. 2^32 - 1
+ * Errors: XG_EINVAL, XG_ERANGE (state_bytes too small), XG_EALIGN,
+ * XG_ENOTSUP, XG_ENOMEM, XG_EHIP.  On error *out is NULL. */
+xg_status xg_init_streams(xg_ctx **out, void *d_state, size_t state_bytes,
+                          uint64_t num_streams, uint64_t seed, void *stream);
+
+/* Wraps an already seeded state buffer (for example one restored from a
+ * checkpoint) in a new handle without touching it.  Same arguments and errors
+ * as xg_init_streams, minus the seed. */
+xg_status xg_attach_streams(xg_ctx **out, void *d_state, size_t state_bytes,
+                            uint64_t num_streams);
+
+/* Frees the host handle; never touches d_state.  NULL is accepted. */
+void xg_destroy(xg_ctx *ctx);
+
+/* Number of streams and state pointer of a handle (0 / NULL for NULL). */
+uint64_t xg_num_streams(const xg_ctx *ctx);
+void *xg_state_ptr(const xg_ctx *ctx);
+
+/* Launch shape of a kernel.  Any shape gives the same output bits;
+ * xg_autotune_batch picks the fastest for a batch. */
+typedef struct {
+    uint32_t waves_per_block;  /* streams served at once by one workgroup: 1, 2, 4, 8, 16 */
+    uint32_t unroll;           /* 64-word chunks per thread per loop trip: 1, 2, 4, 8 */
+    uint32_t blocks_per_cu;    /* persistent workgroups per compute unit: 1 .. 32 */
+    uint32_t reserved;         /* 0 */
+} xg_tune;
+
+/* Launch shape of the plain launches of this handle (waves_per_block and
+ * unroll are used; blocks_per_cu is ignored).  The default is
+ * {1, 4, 1, 0}.  Output bits do not depend on it.
+ * Errors: XG_EINVAL (NULL pointer or a shape outside the ranges of xg_tune). */
+xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune);
+xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune);
+
+/* The plain launch: streams first .. first + count - 1 each produce n values
+ * from their current position, written stream-major:
+ *     d_out[(i - first) * n + t] = value t of stream i,   t < n,
+ * then each stream's state advances by n words.  One wavefront serves one
+ * stream; d_out must hold count * n elements and be 4-byte aligned (16-byte
+ * alignment gives the fastest stores).
+ * Errors: XG_EINVAL (NULL ctx, NULL d_out with n > 0, count == 0), XG_ERANGE
+ * (first + count > num_streams, or count * n overflows), XG_EALIGN, XG_EHIP.
+ * n == 0 is valid (d_out may then be NULL): nothing is enqueued or written. */
+xg_status xg_generate_u32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                          uint32_t *d_out, void *stream);
+xg_status xg_generate_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                          float *d_out, void *stream);
+
+/* Standard normals by the Box-Muller transform on consecutive pairs of
+ * outputs (o_{2m}, o_{2m+1}) of the call: u1 = ((o_{2m} >> 8) + 1) 2^-24 in
+ * (0, 1], u2 = (o_{2m+1} >> 8) 2^-24 in [0, 1), rho = sqrt(-2 ln u1),
+ * z_{2m} = rho cos(2 pi u2), z_{2m+1} = rho sin(2 pi u2), in FP32 (sine and
+ * cosine of pi * (2 u2), so the angle is reduced exactly).  Each stream
+ * consumes 2 * ceil(n / 2) words; for odd n the last sine value is dropped.
+ * Same layout and errors as xg_generate_u32. */
+xg_status xg_generate_normal(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                             float *d_out, void *stream);
+
+/* Fused generate-and-consume: each stream draws n normals exactly as
+ * xg_generate_normal would (the same values, never written to memory) and
+ * reduces them in-kernel to
+ *     d_sums[2 (i - first)]     = sum of z      (FP32)
+ *     d_sums[2 (i - first) + 1] = sum of z^2    (FP32)
+ * with compensated per-lane sums and a pairwise reduction across the
+ * wavefront.  The streams advance by 2 * ceil(n / 2) words.
+ * Same errors as xg_generate_u32 (d_sums holds 2 * count floats). */
+xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                            float *d_sums, void *stream);
+
+/* ---- batched requests ------------------------------------------------------ */
+
+/* One request: n values of type dtype from stream `stream`'s current
+ * position, written at d_out + out_offset (in 4-byte elements).  flags is 0. */
+typedef struct {
+    uint64_t stream;
+    uint64_t n;
+    uint64_t out_offset;
+    uint32_t dtype;
+    uint32_t flags;
+} xg_request;
+
+
+/* Device workspace of a batch: a work counter and an error flag (256 B). */
+size_t xg_batch_workspace_bytes(void);
+
+/* Orders a request table for the batched kernel (host memory only).
+ * Requests on one stream keep their relative order and form one group that a
+ * single wavefront serves in that order; groups are sorted by total words,
+ * largest first, so the dynamic queue balances uneven lengths.
+ *   h_reqs      num_reqs requests (host)
+ *   h_sorted    receives the ordered requests (host, num_reqs entries)
+ *   h_groups    receives num_groups + 1 offsets into h_sorted (host, at least
+ *               num_reqs + 1 entries); group g is h_sorted[h_groups[g] ..
+ *               h_groups[g + 1])
+ *   num_groups  receives the number of groups
+ *   num_streams requests must name streams below this
+ *   out_elems   capacity of the output buffer in elements: every request's
+ *               [out_offset, out_offset + n) must fit
+ * Errors: XG_EINVAL (NULL pointer, dtype or flags invalid), XG_ERANGE (stream
+ * or output range out of bounds), XG_ENOMEM. */
+xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_streams,
+                        uint64_t out_elems, xg_request *h_sorted, uint32_t *h_groups,
+                        uint32_t *num_groups);
+
+/* Serves a planned table in one persistent launch (preceded by a small kernel
+ * that clears the workspace, so the pair can be captured in a HIP graph and
+ * replayed).  Wavefronts take groups from a device-side atomic queue.
+ *   d_reqs, d_groups  device copies of xg_plan_batch's output (num_reqs
+ *                     requests, num_groups + 1 offsets)
+ *   num_groups        groups in the table
+ *   d_out             output buffer of out_elems elements
+ *   tune              launch shape (NULL: a default shape)
+ *   d_work            xg_batch_workspace_bytes() bytes of device memory
+ * A request or group that fails the device-side bounds check (stream, dtype,
+ * output range, group offsets) is skipped and sets the error word
+ * (((uint32_t *)d_work)[1]) to 1; every wavefront still reaches the exit.
+ * Errors: XG_EINVAL, XG_ERANGE, XG_EALIGN, XG_EHIP. */
+xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
+                            const uint32_t *d_groups, uint32_t num_groups, void *d_out,
+                            uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream);
+
+/* Times candidate launch shapes of xg_generate_batch on the given table and
+ * returns the fastest in *best (median of `reps` timed runs per shape after
+ * one warm-up).  It works on a scratch copy of the state:
+ *   d_scratch_state  xg_state_bytes(num_streams of ctx) bytes, overwritten
+ *   d_scratch_out    out_elems elements, overwritten
+ * so the streams of ctx do not advance.  Synchronises `stream`.
+ * times_ms, if non-NULL, receives up to max_times (shape, time) records as
+ * consecutive groups of 5 floats: waves_per_block, unroll, blocks_per_cu, ms,
+ * 0.  *num_times receives their count.
+ * Errors: those of xg_generate_batch, XG_EHIP. */
+xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
+                            const uint32_t *d_groups, uint32_t num_groups,
+                            void *d_scratch_out, uint64_t out_elems,
+                            void *d_scratch_state, void *d_work, int reps, xg_tune *best,
+                            float *times_ms, uint32_t max_times, uint32_t *num_times,
+                            void *stream);
+
+/* Human-readable name of a status. */
+const char *xg_strerror(xg_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XG_H */

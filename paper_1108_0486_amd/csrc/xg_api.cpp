@@ -1,0 +1,326 @@
+// C-ABI layer of libxg (include/xg.h): argument validation, stream handles,
+// the host-side batch planner and the batch autotuner.  Every generating call
+// validates synchronously, then only enqueues kernels on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "xg.h"
+#include "xg_internal.h"
+
+struct xg_ctx {
+  uint32_t *d_state;
+  uint64_t num_streams;
+  int device;
+  int num_cus;
+  xg::Shape plain;
+};
+
+namespace {
+
+constexpr uint64_t kMaxStreams = 0xFFFFFFFFull;
+
+xg_status current_gfx950(int *device, int *num_cus) {
+  int d = 0;
+  if (hipGetDevice(&d) != hipSuccess) return XG_EHIP;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, d) != hipSuccess) return XG_EHIP;
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return XG_ENOTSUP;
+  *device = d;
+  *num_cus = prop.multiProcessorCount;
+  return XG_OK;
+}
+
+xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num_streams) {
+  if (!out) return XG_EINVAL;
+  *out = nullptr;
+  if (!d_state || num_streams == 0 || num_streams > kMaxStreams) return XG_EINVAL;
+  if (state_bytes / XG_STATE_WORDS / 4 < num_streams) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(d_state) % 16 != 0) return XG_EALIGN;
+  int dev = 0, cus = 0;
+  const xg_status st = current_gfx950(&dev, &cus);
+  if (st != XG_OK) return st;
+  xg_ctx *c = new (std::nothrow) xg_ctx;
+  if (!c) return XG_ENOMEM;
+  c->d_state = static_cast<uint32_t *>(d_state);
+  c->num_streams = num_streams;
+  c->device = dev;
+  c->num_cus = cus;
+  c->plain = xg::Shape{1, 4, 1};
+  *out = c;
+  return XG_OK;
+}
+
+xg_status check_ctx_device(const xg_ctx *ctx) {
+  int d = -1;
+  if (hipGetDevice(&d) != hipSuccess) return XG_EHIP;
+  return d == ctx->device ? XG_OK : XG_EINVAL;
+}
+
+// Validates a plain launch over streams [first, first + count) with
+// per_stream_elems elements of output each (out may be NULL when n == 0).
+xg_status check_range(const xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                      const void *out, uint64_t per_stream_elems) {
+  if (!ctx || count == 0) return XG_EINVAL;
+  if (first > ctx->num_streams || count > ctx->num_streams - first) return XG_ERANGE;
+  if (n == 0) return XG_OK;
+  if (!out) return XG_EINVAL;
+  if (count > (UINT64_MAX / 4) / per_stream_elems) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(out) % 4 != 0) return XG_EALIGN;
+  return check_ctx_device(ctx);
+}
+
+xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, void *out,
+                void *stream) {
+  const uint64_t per_stream = kind == xg::kMoments ? 2 : n;
+  xg_status st = check_range(ctx, first, count, n, out, per_stream);
+  if (st != XG_OK || n == 0) return st;
+  const hipError_t e = xg::launch_generate(kind, ctx->plain, ctx->d_state, first, count, n, out,
+                                           static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
+bool tune_to_shape(const xg_tune *t, xg::Shape *s) {
+  if (!t) return false;
+  *s = xg::Shape{t->waves_per_block, t->unroll, t->blocks_per_cu};
+  return t->reserved == 0 && xg::shape_valid(*s);
+}
+
+// Relative cost of a request in the planner's balance: words consumed, with
+// normals weighted for their transcendental work.
+uint64_t request_cost(const xg_request &r) {
+  if (r.dtype == XG_NORMAL) return 4 * (r.n + (r.n & 1));
+  return r.n;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t xg_state_bytes(uint64_t num_streams) {
+  if (num_streams > kMaxStreams) return 0;
+  return (size_t)num_streams * XG_STATE_WORDS * 4;
+}
+
+xg_status xg_init_streams(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num_streams,
+                          uint64_t seed, void *stream) {
+  xg_status st = make_ctx(out, d_state, state_bytes, num_streams);
+  if (st != XG_OK) return st;
+  const hipError_t e = xg::launch_init((*out)->d_state, num_streams, seed, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    delete *out;
+    *out = nullptr;
+    return XG_EHIP;
+  }
+  return XG_OK;
+}
+
+xg_status xg_attach_streams(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num_streams) {
+  return make_ctx(out, d_state, state_bytes, num_streams);
+}
+
+void xg_destroy(xg_ctx *ctx) { delete ctx; }
+
+uint64_t xg_num_streams(const xg_ctx *ctx) { return ctx ? ctx->num_streams : 0; }
+
+void *xg_state_ptr(const xg_ctx *ctx) { return ctx ? ctx->d_state : nullptr; }
+
+xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune) {
+  if (!ctx || !tune) return XG_EINVAL;
+  xg::Shape s{tune->waves_per_block, tune->unroll, 1};
+  if (!xg::shape_valid(s)) return XG_EINVAL;
+  ctx->plain = s;
+  return XG_OK;
+}
+
+xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune) {
+  if (!ctx || !tune) return XG_EINVAL;
+  tune->waves_per_block = ctx->plain.waves_per_block;
+  tune->unroll = ctx->plain.unroll;
+  tune->blocks_per_cu = 1;
+  tune->reserved = 0;
+  return XG_OK;
+}
+
+xg_status xg_generate_u32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, uint32_t *d_out,
+                          void *stream) {
+  return plain(ctx, xg::kU32, first, count, n, d_out, stream);
+}
+
+xg_status xg_generate_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, float *d_out,
+                          void *stream) {
+  return plain(ctx, xg::kF32, first, count, n, d_out, stream);
+}
+
+xg_status xg_generate_normal(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, float *d_out,
+                             void *stream) {
+  return plain(ctx, xg::kNormal, first, count, n, d_out, stream);
+}
+
+xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, float *d_sums,
+                            void *stream) {
+  return plain(ctx, xg::kMoments, first, count, n, d_sums, stream);
+}
+
+size_t xg_batch_workspace_bytes(void) { return 256; }
+
+xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_streams,
+                        uint64_t out_elems, xg_request *h_sorted, uint32_t *h_groups,
+                        uint32_t *num_groups) {
+  if (!h_sorted || !h_groups || !num_groups || (num_reqs && !h_reqs)) return XG_EINVAL;
+  *num_groups = 0;
+  for (uint32_t i = 0; i < num_reqs; ++i) {
+    const xg_request &r = h_reqs[i];
+    if (r.dtype > XG_NORMAL || r.flags != 0) return XG_EINVAL;
+    if (r.stream >= num_streams) return XG_ERANGE;
+    if (r.out_offset > out_elems || r.n > out_elems - r.out_offset) return XG_ERANGE;
+  }
+  try {
+    // Group requests by stream, keeping arrival order inside a group.
+    std::unordered_map<uint64_t, uint32_t> group_of;
+    std::vector<std::vector<uint32_t>> members;
+    std::vector<uint64_t> cost;
+    group_of.reserve(num_reqs * 2 + 1);
+    for (uint32_t i = 0; i < num_reqs; ++i) {
+      auto it = group_of.find(h_reqs[i].stream);
+      uint32_t g;
+      if (it == group_of.end()) {
+        g = (uint32_t)members.size();
+        group_of.emplace(h_reqs[i].stream, g);
+        members.emplace_back();
+        cost.push_back(0);
+      } else {
+        g = it->second;
+      }
+      members[g].push_back(i);
+      cost[g] += request_cost(h_reqs[i]);
+    }
+    // Largest group first (longest-processing-time order for the dynamic queue).
+    std::vector<uint32_t> order(members.size());
+    for (uint32_t g = 0; g < order.size(); ++g) order[g] = g;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](uint32_t a, uint32_t b) { return cost[a] > cost[b]; });
+    uint32_t k = 0;
+    for (uint32_t j = 0; j < order.size(); ++j) {
+      h_groups[j] = k;
+      for (uint32_t i : members[order[j]]) h_sorted[k++] = h_reqs[i];
+    }
+    h_groups[order.size()] = k;
+    *num_groups = (uint32_t)order.size();
+  } catch (const std::bad_alloc &) {
+    return XG_ENOMEM;
+  }
+  return XG_OK;
+}
+
+xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
+                            const uint32_t *d_groups, uint32_t num_groups, void *d_out,
+                            uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream) {
+  if (!ctx || !d_reqs || !d_groups || !d_out || !d_work) return XG_EINVAL;
+  if (num_groups > num_reqs) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_groups) % 4 ||
+      reinterpret_cast<uintptr_t>(d_out) % 4 || reinterpret_cast<uintptr_t>(d_work) % 4)
+    return XG_EALIGN;
+  xg::Shape shape{4, 4, 8};
+  if (tune && !tune_to_shape(tune, &shape)) return XG_EINVAL;
+  xg_status st = check_ctx_device(ctx);
+  if (st != XG_OK) return st;
+  if (num_groups == 0) return XG_OK;
+  const hipError_t e = xg::launch_batch(shape, ctx->num_cus, ctx->d_state, ctx->num_streams, d_reqs,
+                                        num_reqs, d_groups, num_groups,
+                                        static_cast<uint32_t *>(d_out), out_elems,
+                                        static_cast<uint32_t *>(d_work),
+                                        static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
+xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
+                            const uint32_t *d_groups, uint32_t num_groups, void *d_scratch_out,
+                            uint64_t out_elems, void *d_scratch_state, void *d_work, int reps,
+                            xg_tune *best, float *times_ms, uint32_t max_times,
+                            uint32_t *num_times, void *stream) {
+  if (!ctx || !best || !d_scratch_state || reps < 1 || reps > 100) return XG_EINVAL;
+  if (num_times) *num_times = 0;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t state_bytes = xg_state_bytes(ctx->num_streams);
+  xg_ctx scratch = *ctx;
+  scratch.d_state = static_cast<uint32_t *>(d_scratch_state);
+  if (reinterpret_cast<uintptr_t>(d_scratch_state) % 16) return XG_EALIGN;
+
+  static const uint32_t kWpb[] = {1, 2, 4, 8, 16};
+  static const uint32_t kUnroll[] = {1, 2, 4, 8};
+  static const uint32_t kBpc[] = {1, 2, 4, 8, 16, 32};
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+    if (t0) (void)hipEventDestroy(t0);
+    return XG_EHIP;
+  }
+  float best_ms = -1.f;
+  xg_status result = XG_OK;
+  uint32_t recorded = 0;
+  for (uint32_t wpb : kWpb) {
+    for (uint32_t un : kUnroll) {
+      for (uint32_t bpc : kBpc) {
+        if (wpb * bpc > 32) continue;  // more waves than a compute unit holds
+        const xg_tune cand{wpb, un, bpc, 0};
+        std::vector<float> ms;
+        for (int rep = 0; rep <= reps && result == XG_OK; ++rep) {
+          if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
+            result = XG_EHIP;
+            break;
+          }
+          if (hipEventRecord(t0, s) != hipSuccess) { result = XG_EHIP; break; }
+          result = xg_generate_batch(&scratch, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out,
+                                     out_elems, &cand, d_work, stream);
+          if (result != XG_OK) break;
+          if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
+            result = XG_EHIP;
+            break;
+          }
+          float t = 0.f;
+          if (hipEventElapsedTime(&t, t0, t1) != hipSuccess) { result = XG_EHIP; break; }
+          if (rep > 0) ms.push_back(t);  // rep 0 is the warm-up
+        }
+        if (result != XG_OK) break;
+        std::sort(ms.begin(), ms.end());
+        const float med = ms[ms.size() / 2];
+        if (times_ms && recorded < max_times) {
+          float *rec = times_ms + 5 * recorded;
+          rec[0] = (float)wpb; rec[1] = (float)un; rec[2] = (float)bpc; rec[3] = med; rec[4] = 0.f;
+          ++recorded;
+        }
+        if (best_ms < 0.f || med < best_ms) {
+          best_ms = med;
+          *best = cand;
+        }
+      }
+      if (result != XG_OK) break;
+    }
+    if (result != XG_OK) break;
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  if (num_times) *num_times = recorded;
+  return result;
+}
+
+const char *xg_strerror(xg_status status) {
+  switch (status) {
+    case XG_OK: return "ok";
+    case XG_EINVAL: return "invalid argument";
+    case XG_ERANGE: return "stream or size out of range";
+    case XG_EALIGN: return "misaligned device pointer";
+    case XG_EHIP: return "HIP runtime error";
+    case XG_ENOTSUP: return "current device is not gfx950";
+    case XG_ENOMEM: return "host allocation failed";
+    case XG_EBUSY: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,476 @@
+// HIP kernels of libxg for gfx950 (MI355X): xorgens streams, one wavefront per
+// stream, 64 consecutive words per wavefront step.
+//
+// Method (arXiv:1108.0486):
+//   Section 2       x_i = x_{i-128} A  xor  x_{i-65} B,
+//                   A = (I + L^15)(I + R^14), B = (I + L^12)(I + R^17), 32-bit words;
+//   Section 1.5     W_k = W_{k-1} + omega,  out_k = x_k + (W_k xor (W_k >> 16))  (Eq. (1));
+//   Section 2       x_k .. x_{k+C-1} depend only on words older than x_k while
+//                   C <= s = 65, so one 64-lane wavefront computes 64 words per step.
+//
+// Register-resident ring.  Lane j of a wavefront owns word j of every 64-word
+// chunk.  For the chunk starting at position p the wavefront holds
+//   prev[j] = x_{p-128+j}   (chunk p-128 .. p-65)
+//   cur[j]  = x_{p-64+j}    (chunk p-64  .. p-1)
+// and computes x_{p+j} = A(prev[j]) xor B(x_{p+j-65}).  Here x_{p+j-65} is
+// cur[j-1] for j >= 1 and prev[63] for j = 0: B(cur) is rotated up by one lane
+// with a DPP wave rotate, and lane 0 takes B(prev[63]), which is lane 0 of the
+// previous chunk's rotation.  The 128-word ring thus never leaves VGPRs inside
+// the hot loop; each chunk costs about 14 VALU operations per lane and one
+// coalesced 256-byte store.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xg_internal.h"
+
+namespace xg {
+namespace {
+
+constexpr uint32_t kOmega = 0x9E3779B9u;       // odd integer nearest 2^31 (sqrt 5 - 1)
+constexpr uint32_t kChunkOmega = 64u * kOmega;  // Weyl advance per chunk (mod 2^32)
+constexpr uint64_t kGolden64 = 0x9E3779B97F4A7C15ull;
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// x (I + L^12)(I + R^17): the operator applied to x_{i-s}.
+__device__ __forceinline__ uint32_t op_lag_s(uint32_t v) {
+  v ^= v << 12;
+  return v ^ (v >> 17);
+}
+
+// Lane j receives lane j-1's value, lane 0 receives lane 63's (DPP wave_ror:1;
+// every lane has a valid source, so bound_ctrl never applies).
+__device__ __forceinline__ uint32_t lanes_rotate_up(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
+}
+
+// a xor b xor c in one gfx950 v_bitop3_b32 (truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint32_t temper_weyl(uint32_t w) { return w ^ (w >> 16); }
+
+struct Ring {
+  uint32_t prev;   // x_{p-128+j}
+  uint32_t cur;    // x_{p-64+j}
+  uint32_t rprev;  // lane 0: B(x_{p-65}); other lanes: unused
+};
+
+__device__ __forceinline__ Ring ring_from(uint32_t prev, uint32_t cur) {
+  Ring g;
+  g.prev = prev;
+  g.cur = cur;
+  g.rprev = lanes_rotate_up(op_lag_s(prev));  // lane 0 <- B(prev[63]) = B(x_{p-65})
+  return g;
+}
+
+// Computes the next 64 words x_p .. x_{p+63} (lane j: x_{p+j}) and advances g.
+__device__ __forceinline__ uint32_t ring_step(Ring &g, bool lane0) {
+  const uint32_t bc = op_lag_s(g.cur);
+  const uint32_t rc = lanes_rotate_up(bc);     // lane j >= 1: B(x_{p+j-65}); lane 0: B(x_{p-1})
+  const uint32_t bs = lane0 ? g.rprev : rc;    // B(x_{p+j-65}) on every lane
+  // A(prev) = prev (I + L^15)(I + R^14) = t xor (t >> 14), t = prev xor (prev << 15)
+  const uint32_t t = g.prev ^ (g.prev << 15);
+  const uint32_t x = xor3(t, t >> 14, bs);
+  g.prev = g.cur;
+  g.cur = x;
+  g.rprev = rc;                                // lane 0: B(x_{p-1}) = B(x_{p'-65}), p' = p + 64
+  return x;
+}
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Writes the 128-word window ending `rem` words into chunk `x` (rem in 1..63),
+// i.e. words [rem, rem + 128) of the concatenation prev | cur | x, as the new
+// linear ring; rem == 0 writes prev | cur.
+__device__ __forceinline__ void store_ring(uint32_t *st, uint32_t prev, uint32_t cur, uint32_t x,
+                                           uint32_t rem, uint32_t lane) {
+  uint32_t lo = prev, hi = cur;
+  if (rem) {
+    const int src = (int)((rem + lane) & 63u);
+    const uint32_t a = (uint32_t)__shfl((int)prev, src);
+    const uint32_t b = (uint32_t)__shfl((int)cur, src);
+    const uint32_t c = (uint32_t)__shfl((int)x, src);
+    const bool wrap = rem + lane >= 64u;
+    lo = wrap ? b : a;
+    hi = wrap ? c : b;
+  }
+  st[lane] = lo;
+  st[64 + lane] = hi;
+}
+
+__device__ __forceinline__ void store_weyl_pos(uint32_t *st, uint32_t weyl, uint64_t pos,
+                                               uint32_t lane) {
+  if (lane == 0) {
+    st[128] = weyl;
+    st[129] = 0u;
+    st[130] = (uint32_t)pos;
+    st[131] = (uint32_t)(pos >> 32);
+  }
+}
+
+__device__ __forceinline__ uint64_t load_pos(const uint32_t *st) {
+  return (uint64_t)st[130] | ((uint64_t)st[131] << 32);
+}
+
+template <uint32_t KIND>
+__device__ __forceinline__ void emit_word(uint32_t *p, uint32_t o) {
+  if constexpr (KIND == kU32) {
+    __builtin_nontemporal_store(o, p);
+  } else {
+    const float f = (float)(o >> 8) * 0x1p-24f;  // exact: a 24-bit integer times 2^-24
+    __builtin_nontemporal_store(f, reinterpret_cast<float *>(p));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// u32 / f32: n words of one stream, written contiguously at out[0 .. n).
+// ---------------------------------------------------------------------------
+template <uint32_t KIND, int UNROLL>
+__device__ __forceinline__ void serve_words(uint32_t *__restrict__ st, uint64_t n,
+                                            uint32_t *__restrict__ out) {
+  const uint32_t lane = lane_id();
+  const bool lane0 = lane == 0;
+  Ring g = ring_from(st[lane], st[64 + lane]);
+  const uint32_t w_start = st[128];
+  const uint64_t pos = load_pos(st);
+  uint32_t wbase = w_start;                     // W_{p-1}
+  const uint32_t wlane = (lane + 1u) * kOmega;  // W_{p+j} = W_{p-1} + (j + 1) omega
+  const uint64_t nfull = n >> 6;
+  const uint32_t rem = (uint32_t)(n & 63u);
+  uint32_t *o = out + lane;
+  const uint64_t nouter = nfull / UNROLL;
+  for (uint64_t it = 0; it != nouter; ++it) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint32_t x = ring_step(g, lane0);
+      const uint32_t w = wbase + wlane;
+      wbase += kChunkOmega;
+      emit_word<KIND>(o + u * 64, x + temper_weyl(w));
+    }
+    o += UNROLL * 64;
+  }
+  const uint32_t nleft = (uint32_t)(nfull % UNROLL);
+  for (uint32_t c = 0; c != nleft; ++c) {
+    const uint32_t x = ring_step(g, lane0);
+    const uint32_t w = wbase + wlane;
+    wbase += kChunkOmega;
+    emit_word<KIND>(o, x + temper_weyl(w));
+    o += 64;
+  }
+  uint32_t p0 = g.prev, c0 = g.cur, x = 0u;
+  if (rem) {
+    x = ring_step(g, lane0);
+    const uint32_t w = wbase + wlane;
+    if (lane < rem) emit_word<KIND>(o, x + temper_weyl(w));
+  }
+  store_ring(st, p0, c0, x, rem, lane);
+  store_weyl_pos(st, w_start + (uint32_t)n * kOmega, pos + n, lane);
+}
+
+// ---------------------------------------------------------------------------
+// normals: Box-Muller on consecutive output pairs of the call.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void box_muller(uint32_t e, uint32_t o, float &z0, float &z1) {
+  const float u1 = (float)((e >> 8) + 1u) * 0x1p-24f;  // (0, 1], exact
+  const float u2 = (float)(o >> 8) * 0x1p-24f;         // [0, 1), exact
+  const float rho = sqrtf(-2.0f * logf(u1));
+  float s, c;
+  sincospif(2.0f * u2, &s, &c);                        // angle 2 pi u2 reduced exactly
+  z0 = rho * c;
+  z1 = rho * s;
+}
+
+// Lane j gathers words 2j and 2j + 1 of the 128-word block lo | hi.
+__device__ __forceinline__ void gather_pair(uint32_t lo, uint32_t hi, uint32_t lane, uint32_t &e,
+                                            uint32_t &o) {
+  const int se = (int)((2u * lane) & 63u);
+  const int so = se + 1;
+  const uint32_t e_lo = (uint32_t)__shfl((int)lo, se), e_hi = (uint32_t)__shfl((int)hi, se);
+  const uint32_t o_lo = (uint32_t)__shfl((int)lo, so), o_hi = (uint32_t)__shfl((int)hi, so);
+  const bool upper = lane >= 32u;
+  e = upper ? e_hi : e_lo;
+  o = upper ? o_hi : o_lo;
+}
+
+struct Moments {
+  float s1, c1, s2, c2;  // compensated sums of z and z^2
+};
+
+__device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
+  const float y = v - c;
+  const float t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// Stores (or accumulates) normals idx and idx + 1 of the call.  `pair_aligned`
+// (wave-uniform) says out is 8-byte aligned, so a pair is one 8-byte store.
+template <bool MOMENTS>
+__device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t idx, uint64_t n,
+                                             float *__restrict__ out, bool pair_aligned,
+                                             Moments &m) {
+  float z0, z1;
+  box_muller(e, o, z0, z1);
+  if constexpr (MOMENTS) {
+    if (idx < n) {
+      kahan_add(m.s1, m.c1, z0);
+      kahan_add(m.s2, m.c2, z0 * z0);
+    }
+    if (idx + 1 < n) {
+      kahan_add(m.s1, m.c1, z1);
+      kahan_add(m.s2, m.c2, z1 * z1);
+    }
+  } else {
+    if (pair_aligned && idx + 1 < n) {
+      const f32x2 pair = {z0, z1};
+      __builtin_nontemporal_store(pair, reinterpret_cast<f32x2 *>(out + idx));
+    } else {
+      if (idx < n) __builtin_nontemporal_store(z0, out + idx);
+      if (idx + 1 < n) __builtin_nontemporal_store(z1, out + idx + 1);
+    }
+  }
+}
+
+// n normals of one stream; MOMENTS: reduce to (sum z, sum z^2) in sums[0..1]
+// instead of storing them.  Consumes 2 ceil(n / 2) words.
+template <bool MOMENTS, int UNROLL>
+__device__ __forceinline__ void serve_normals(uint32_t *__restrict__ st, uint64_t n,
+                                              float *__restrict__ out, float *__restrict__ sums) {
+  const uint32_t lane = lane_id();
+  const bool lane0 = lane == 0;
+  Ring g = ring_from(st[lane], st[64 + lane]);
+  const uint32_t w_start = st[128];
+  const uint64_t pos = load_pos(st);
+  uint32_t wbase = w_start;
+  const uint32_t wlane = (lane + 1u) * kOmega;
+  const uint64_t words = n + (n & 1u);
+  const uint64_t nblk = words >> 7;     // 128-word blocks: 64 pairs, one per lane
+  const uint32_t rw = (uint32_t)(words & 127u);
+  Moments m = {0.f, 0.f, 0.f, 0.f};
+  const bool pair_aligned = (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
+  const uint64_t nouter = nblk / UNROLL;
+  uint64_t b = 0;
+  for (uint64_t it = 0; it != nouter; ++it, b += UNROLL) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const uint32_t xa = ring_step(g, lane0);
+      const uint32_t oa = xa + temper_weyl(wbase + wlane);
+      wbase += kChunkOmega;
+      const uint32_t xb = ring_step(g, lane0);
+      const uint32_t ob = xb + temper_weyl(wbase + wlane);
+      wbase += kChunkOmega;
+      uint32_t e, o;
+      gather_pair(oa, ob, lane, e, o);
+      consume_pair<MOMENTS>(e, o, ((b + u) << 7) + 2u * lane, n, out, pair_aligned, m);
+    }
+  }
+  for (; b != nblk; ++b) {
+    const uint32_t xa = ring_step(g, lane0);
+    const uint32_t oa = xa + temper_weyl(wbase + wlane);
+    wbase += kChunkOmega;
+    const uint32_t xb = ring_step(g, lane0);
+    const uint32_t ob = xb + temper_weyl(wbase + wlane);
+    wbase += kChunkOmega;
+    uint32_t e, o;
+    gather_pair(oa, ob, lane, e, o);
+    consume_pair<MOMENTS>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
+  }
+  // Tail: rw (even, < 128) more words.
+  uint32_t p0 = g.prev, c0 = g.cur, xl = 0u, rem = 0u;
+  if (rw) {
+    uint32_t oa, ob = 0u;
+    if (rw <= 64u) {
+      p0 = g.prev;
+      c0 = g.cur;
+      xl = ring_step(g, lane0);
+      oa = xl + temper_weyl(wbase + wlane);
+      rem = rw & 63u;               // rw == 64 completes the chunk
+      if (!rem) { p0 = g.prev; c0 = g.cur; }
+    } else {
+      const uint32_t xa = ring_step(g, lane0);
+      oa = xa + temper_weyl(wbase + wlane);
+      wbase += kChunkOmega;
+      p0 = g.prev;
+      c0 = g.cur;
+      xl = ring_step(g, lane0);
+      ob = xl + temper_weyl(wbase + wlane);
+      rem = rw - 64u;
+    }
+    uint32_t e, o;
+    gather_pair(oa, ob, lane, e, o);
+    if (2u * lane < rw) consume_pair<MOMENTS>(e, o, (nblk << 7) + 2u * lane, n, out, pair_aligned, m);
+  }
+  store_ring(st, p0, c0, xl, rem, lane);
+  store_weyl_pos(st, w_start + (uint32_t)words * kOmega, pos + words, lane);
+  if constexpr (MOMENTS) {
+    float v1 = m.s1 - m.c1, v2 = m.s2 - m.c2;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      v1 += __shfl_xor(v1, off);
+      v2 += __shfl_xor(v2, off);
+    }
+    if (lane == 0) {
+      sums[0] = v1;
+      sums[1] = v2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t k) {
+  // k-th SplitMix64 output (k >= 1): the state after k increments is seed + k * gamma.
+  uint64_t z = seed + k * kGolden64;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Seeds one stream per wavefront: ring and Weyl start from SplitMix64(seed + i),
+// zero-ring guard, then 512 = 8 chunks of discarded steps.
+__global__ __launch_bounds__(256) void k_init(uint32_t *__restrict__ state, uint64_t num_streams,
+                                              uint64_t seed) {
+  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wid >= num_streams) return;
+  const uint32_t lane = lane_id();
+  const uint64_t s = seed + wid;
+  uint32_t lo = (uint32_t)(splitmix64_at(s, lane + 1u) >> 32);    // x_{-128+j}
+  uint32_t hi = (uint32_t)(splitmix64_at(s, lane + 65u) >> 32);   // x_{-64+j}
+  const uint32_t w0 = (uint32_t)(splitmix64_at(s, 129u) >> 32);   // W
+  const bool any = __any((lo | hi) != 0u);
+  if (!any && lane == 63u) hi = 1u;                                // x_{-1} = 1
+  Ring g = ring_from(lo, hi);
+  const bool lane0 = lane == 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) (void)ring_step(g, lane0);
+  uint32_t *st = state + wid * kStateWords;
+  store_ring(st, g.prev, g.cur, 0u, 0u, lane);
+  store_weyl_pos(st, w0 + 512u * kOmega, 0ull, lane);
+}
+
+template <uint32_t KIND, int UNROLL>
+__global__ __launch_bounds__(1024) void k_generate(uint32_t *__restrict__ state, uint64_t first,
+                                                   uint64_t count, uint64_t n, void *__restrict__ out) {
+  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wid >= count) return;
+  uint32_t *st = state + (first + wid) * kStateWords;
+  if constexpr (KIND == kU32 || KIND == kF32) {
+    serve_words<KIND, UNROLL>(st, n, reinterpret_cast<uint32_t *>(out) + wid * n);
+  } else if constexpr (KIND == kNormal) {
+    serve_normals<false, UNROLL>(st, n, reinterpret_cast<float *>(out) + wid * n, nullptr);
+  } else {
+    serve_normals<true, UNROLL>(st, n, nullptr, reinterpret_cast<float *>(out) + 2 * wid);
+  }
+}
+
+__global__ void k_clear_work(uint32_t *work) {
+  if (threadIdx.x < 64) work[threadIdx.x] = 0u;
+}
+
+// Persistent batched kernel: wavefronts take request groups from an atomic
+// queue (work[0]) until it is exhausted; every wavefront reaches the exit.
+template <int UNROLL>
+__global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, uint64_t num_streams,
+                                                const xg_request *__restrict__ reqs,
+                                                uint32_t num_reqs,
+                                                const uint32_t *__restrict__ groups,
+                                                uint32_t num_groups, uint32_t *__restrict__ out,
+                                                uint64_t out_elems, uint32_t *__restrict__ work) {
+  const uint32_t lane = lane_id();
+  for (;;) {
+    uint32_t g = 0;
+    if (lane == 0) g = atomicAdd(&work[0], 1u);
+    g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
+    if (g >= num_groups) break;
+    const uint32_t r0 = groups[g], r1 = groups[g + 1];
+    if (r0 > r1 || r1 > num_reqs) {
+      if (lane == 0) atomicOr(&work[1], 1u);
+      continue;
+    }
+    for (uint32_t r = r0; r < r1; ++r) {
+      const xg_request q = reqs[r];
+      const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u &&
+                      q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
+      if (!ok) {
+        if (lane == 0) atomicOr(&work[1], 1u);
+        continue;
+      }
+      uint32_t *st = state + q.stream * kStateWords;
+      uint32_t *o = out + q.out_offset;
+      if (q.dtype == XG_U32) {
+        serve_words<kU32, UNROLL>(st, q.n, o);
+      } else if (q.dtype == XG_F32) {
+        serve_words<kF32, UNROLL>(st, q.n, o);
+      } else {
+        serve_normals<false, UNROLL>(st, q.n, reinterpret_cast<float *>(o), nullptr);
+      }
+    }
+  }
+}
+
+template <uint32_t KIND>
+hipError_t launch_generate_k(int unroll, dim3 grid, dim3 block, uint32_t *state, uint64_t first,
+                             uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL((k_generate<KIND, 1>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 2: hipLaunchKernelGGL((k_generate<KIND, 2>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 4: hipLaunchKernelGGL((k_generate<KIND, 4>), grid, block, 0, stream, state, first, count, n, out); break;
+    default: hipLaunchKernelGGL((k_generate<KIND, 8>), grid, block, 0, stream, state, first, count, n, out); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+bool shape_valid(const Shape &s) {
+  const bool wpb = s.waves_per_block == 1 || s.waves_per_block == 2 || s.waves_per_block == 4 ||
+                   s.waves_per_block == 8 || s.waves_per_block == 16;
+  const bool un = s.unroll == 1 || s.unroll == 2 || s.unroll == 4 || s.unroll == 8;
+  return wpb && un && s.blocks_per_cu >= 1 && s.blocks_per_cu <= 32;
+}
+
+hipError_t launch_init(uint32_t *state, uint64_t num_streams, uint64_t seed, hipStream_t stream) {
+  const uint64_t blocks = (num_streams + 3) / 4;
+  hipLaunchKernelGGL(k_init, dim3((uint32_t)blocks), dim3(256), 0, stream, state, num_streams, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint64_t first,
+                           uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  const uint64_t wpb = shape.waves_per_block;
+  const dim3 grid((uint32_t)((count + wpb - 1) / wpb));
+  const dim3 block((uint32_t)(wpb * kWave));
+  switch (kind) {
+    case kU32: return launch_generate_k<kU32>(shape.unroll, grid, block, state, first, count, n, out, stream);
+    case kF32: return launch_generate_k<kF32>(shape.unroll, grid, block, state, first, count, n, out, stream);
+    case kNormal: return launch_generate_k<kNormal>(shape.unroll, grid, block, state, first, count, n, out, stream);
+    default: return launch_generate_k<kMoments>(shape.unroll, grid, block, state, first, count, n, out, stream);
+  }
+}
+
+hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
+                        const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,
+                        uint32_t num_groups, uint32_t *out, uint64_t out_elems, uint32_t *work,
+                        hipStream_t stream) {
+  hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(64), 0, stream, work);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint64_t want_waves = (uint64_t)num_groups;
+  uint64_t blocks = (uint64_t)num_cus * shape.blocks_per_cu;
+  const uint64_t need = (want_waves + shape.waves_per_block - 1) / shape.waves_per_block;
+  if (need < blocks) blocks = need ? need : 1;
+  const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  switch (shape.unroll) {
+    case 1: hipLaunchKernelGGL(k_batch<1>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 2: hipLaunchKernelGGL(k_batch<2>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 4: hipLaunchKernelGGL(k_batch<4>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    default: hipLaunchKernelGGL(k_batch<8>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace xg

@@ -1,0 +1,121 @@
+"""Device-resident xorgens streams: torch owns the memory, libxg does the work.
+
+PyTorch is used here only to allocate device buffers and to name the HIP
+stream; each method is one call through the C ABI (paper_1108_0486_amd.xg).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from . import xg
+
+
+def _stream_handle(stream: torch.cuda.Stream | None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class XorgensStreams:
+    """num_streams streams; stream i is seeded from seed + i."""
+
+    def __init__(self, num_streams: int, seed: int, device: str | torch.device = "cuda",
+                 stream: torch.cuda.Stream | None = None, state: torch.Tensor | None = None):
+        self.device = torch.device(device)
+        self.num_streams = int(num_streams)
+        nbytes = xg.xg_state_bytes(self.num_streams)
+        if state is None:
+            self.state = torch.empty(nbytes // 4, dtype=torch.int32, device=self.device)
+            with torch.cuda.device(self.device):
+                self.ctx = xg.xg_init_streams(self.state.data_ptr(), nbytes, self.num_streams, seed,
+                                              _stream_handle(stream))
+        else:
+            if state.numel() * state.element_size() < nbytes or not state.is_cuda:
+                raise ValueError("state buffer too small or not on a GPU")
+            self.state = state
+            with torch.cuda.device(self.device):
+                self.ctx = xg.xg_attach_streams(self.state.data_ptr(), nbytes, self.num_streams)
+
+    @classmethod
+    def attach(cls, state: torch.Tensor, num_streams: int) -> "XorgensStreams":
+        return cls(num_streams, 0, device=state.device, state=state)
+
+    def close(self) -> None:
+        if getattr(self, "ctx", None) is not None:
+            xg.xg_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- tuning -----------------------------------------------------------
+    def set_plain_tune(self, waves_per_block: int, unroll: int) -> None:
+        xg.xg_set_plain_tune(self.ctx, waves_per_block, unroll)
+
+    def plain_tune(self) -> tuple:
+        return xg.xg_get_plain_tune(self.ctx)
+
+    # ---- plain launches -------------------------------------------------------
+    def _range(self, first: int, count: int | None) -> tuple[int, int]:
+        return first, (self.num_streams - first if count is None else count)
+
+    def _out(self, out, shape, dtype):
+        if out is None:
+            return torch.empty(shape, dtype=dtype, device=self.device)
+        return out
+
+    def u32(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+            stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """[count, n] int32 tensor holding the uint32 outputs' bits."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count, n), torch.int32)
+        xg.xg_generate_u32(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def f32(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+            stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        first, count = self._range(first, count)
+        out = self._out(out, (count, n), torch.float32)
+        xg.xg_generate_f32(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def normal(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+               stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        first, count = self._range(first, count)
+        out = self._out(out, (count, n), torch.float32)
+        xg.xg_generate_normal(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def moments(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """[count, 2] float32: sum of z and sum of z^2 over n normals."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count, 2), torch.float32)
+        xg.xg_normal_moments(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    # ---- state --------------------------------------------------------------
+    def host_state(self, idx=None):
+        """(ring[k, 128] uint32, weyl[k] uint32, pos[k] uint64) of the selected streams."""
+        words = self.state.view(self.num_streams, xg.XG_STATE_WORDS)
+        if idx is not None:
+            words = words[torch.as_tensor(idx, device=self.device)]
+        a = words.cpu().numpy().view(np.uint32)
+        ring = a[:, :128].copy()
+        weyl = a[:, 128].copy()
+        pos = a[:, 130].astype(np.uint64) | (a[:, 131].astype(np.uint64) << np.uint64(32))
+        return ring, weyl, pos
+
+    def checkpoint(self) -> torch.Tensor:
+        return self.state.clone()
+
+    def restore(self, saved: torch.Tensor) -> None:
+        self.state.copy_(saved)
+
+
+def as_u32(t: torch.Tensor) -> np.ndarray:
+    """Host uint32 view of an int32 device tensor of generator outputs."""
+    return t.cpu().numpy().view(np.uint32)

@@ -1,0 +1,199 @@
+"""ctypes binding of libxg (include/xg.h), with the same function names.
+
+Argument marshalling only: every step of generation runs in the HIP kernels
+of libxg.so.  Pointers are passed as integers (device addresses from
+torch tensors' data_ptr()), HIP streams as integers (torch's cuda_stream).
+If libxg.so has not been built this module raises on first use; there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libxg.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "xg.h")
+
+XG_OK = 0
+XG_EINVAL = -1
+XG_ERANGE = -2
+XG_EALIGN = -3
+XG_EHIP = -4
+XG_ENOTSUP = -5
+XG_ENOMEM = -6
+XG_EBUSY = -7
+
+XG_STATE_WORDS = 132
+XG_U32, XG_F32, XG_NORMAL = 0, 1, 2
+
+
+class XgError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        super().__init__("%s: %s (%d)" % (where, strerror(status), status))
+
+
+class xg_request(ctypes.Structure):
+    _fields_ = [("stream", ctypes.c_uint64), ("n", ctypes.c_uint64), ("out_offset", ctypes.c_uint64),
+                ("dtype", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class xg_tune(ctypes.Structure):
+    _fields_ = [("waves_per_block", ctypes.c_uint32), ("unroll", ctypes.c_uint32),
+                ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+    def as_tuple(self):
+        return (self.waves_per_block, self.unroll, self.blocks_per_cu)
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Loads libxg.so (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libxg.so is not built (%s); run `python -m paper_1108_0486_amd.build`" % LIB_PATH)
+    L = ctypes.CDLL(LIB_PATH)
+    vp, u64, u32, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int
+    st = ctypes.c_int32
+    P = ctypes.POINTER
+    sig = {
+        "xg_state_bytes": (ctypes.c_size_t, [u64]),
+        "xg_init_streams": (st, [P(vp), vp, ctypes.c_size_t, u64, u64, vp]),
+        "xg_attach_streams": (st, [P(vp), vp, ctypes.c_size_t, u64]),
+        "xg_destroy": (None, [vp]),
+        "xg_num_streams": (u64, [vp]),
+        "xg_state_ptr": (vp, [vp]),
+        "xg_set_plain_tune": (st, [vp, P(xg_tune)]),
+        "xg_get_plain_tune": (st, [vp, P(xg_tune)]),
+        "xg_generate_u32": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_generate_f32": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_generate_normal": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_normal_moments": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
+        "xg_plan_batch": (st, [P(xg_request), u32, u64, u64, P(xg_request), P(u32), P(u32)]),
+        "xg_generate_batch": (st, [vp, vp, u32, vp, u32, vp, u64, P(xg_tune), vp, vp]),
+        "xg_autotune_batch": (st, [vp, vp, u32, vp, u32, vp, u64, vp, vp, i32, P(xg_tune),
+                                   P(ctypes.c_float), u32, P(u32), vp]),
+        "xg_strerror": (ctypes.c_char_p, [st]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/xg.h declares."""
+    text = open(HEADER_PATH).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xg_[a-z0-9_]+)\s*\(", text)))
+
+
+def strerror(status: int) -> str:
+    return lib().xg_strerror(status).decode()
+
+
+def _check(status: int, where: str) -> None:
+    if status != XG_OK:
+        raise XgError(status, where)
+
+
+# ---- thin wrappers with the C names ------------------------------------------
+
+def xg_state_bytes(num_streams: int) -> int:
+    return int(lib().xg_state_bytes(num_streams))
+
+
+def xg_init_streams(d_state: int, state_bytes: int, num_streams: int, seed: int, stream: int = 0):
+    ctx = ctypes.c_void_p()
+    _check(lib().xg_init_streams(ctypes.byref(ctx), d_state, state_bytes, num_streams,
+                                 seed & (2**64 - 1), stream), "xg_init_streams")
+    return ctx
+
+
+def xg_attach_streams(d_state: int, state_bytes: int, num_streams: int):
+    ctx = ctypes.c_void_p()
+    _check(lib().xg_attach_streams(ctypes.byref(ctx), d_state, state_bytes, num_streams),
+           "xg_attach_streams")
+    return ctx
+
+
+def xg_destroy(ctx) -> None:
+    lib().xg_destroy(ctx)
+
+
+def xg_set_plain_tune(ctx, waves_per_block: int, unroll: int) -> None:
+    t = xg_tune(waves_per_block, unroll, 1, 0)
+    _check(lib().xg_set_plain_tune(ctx, ctypes.byref(t)), "xg_set_plain_tune")
+
+
+def xg_get_plain_tune(ctx) -> tuple:
+    t = xg_tune()
+    _check(lib().xg_get_plain_tune(ctx, ctypes.byref(t)), "xg_get_plain_tune")
+    return t.as_tuple()[:2]
+
+
+def xg_generate_u32(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_generate_u32(ctx, first, count, n, d_out, stream), "xg_generate_u32")
+
+
+def xg_generate_f32(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_generate_f32(ctx, first, count, n, d_out, stream), "xg_generate_f32")
+
+
+def xg_generate_normal(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_generate_normal(ctx, first, count, n, d_out, stream), "xg_generate_normal")
+
+
+def xg_normal_moments(ctx, first: int, count: int, n: int, d_sums: int, stream: int = 0) -> None:
+    _check(lib().xg_normal_moments(ctx, first, count, n, d_sums, stream), "xg_normal_moments")
+
+
+def xg_batch_workspace_bytes() -> int:
+    return int(lib().xg_batch_workspace_bytes())
+
+
+def xg_plan_batch(requests, num_streams: int, out_elems: int):
+    """requests: sequence of (stream, n, out_offset, dtype).  Returns
+    (sorted ctypes array of xg_request, list of group offsets)."""
+    nr = len(requests)
+    arr = (xg_request * max(1, nr))()
+    for i, (s, n, off, dt) in enumerate(requests):
+        arr[i] = xg_request(s, n, off, dt, 0)
+    out = (xg_request * max(1, nr))()
+    groups = (ctypes.c_uint32 * (nr + 1))()
+    ng = ctypes.c_uint32()
+    _check(lib().xg_plan_batch(arr, nr, num_streams, out_elems, out, groups, ctypes.byref(ng)),
+           "xg_plan_batch")
+    return out, list(groups[: ng.value + 1])
+
+
+def xg_generate_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int, d_out: int,
+                      out_elems: int, tune: tuple | None, d_work: int, stream: int = 0) -> None:
+    t = None if tune is None else ctypes.byref(xg_tune(tune[0], tune[1], tune[2], 0))
+    _check(lib().xg_generate_batch(ctx, d_reqs, num_reqs, d_groups, num_groups, d_out, out_elems, t,
+                                   d_work, stream), "xg_generate_batch")
+
+
+def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int,
+                      d_scratch_out: int, out_elems: int, d_scratch_state: int, d_work: int,
+                      reps: int = 3, stream: int = 0):
+    """Returns (best shape tuple, [(wpb, unroll, bpc, ms), ...])."""
+    best = xg_tune()
+    maxt = 256
+    times = (ctypes.c_float * (5 * maxt))()
+    nt = ctypes.c_uint32()
+    _check(lib().xg_autotune_batch(ctx, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out, out_elems,
+                                   d_scratch_state, d_work, reps, ctypes.byref(best), times, maxt,
+                                   ctypes.byref(nt), stream), "xg_autotune_batch")
+    recs = [(int(times[5 * i]), int(times[5 * i + 1]), int(times[5 * i + 2]), float(times[5 * i + 3]))
+            for i in range(nt.value)]
+    return best.as_tuple(), recs

@@ -1,0 +1,27 @@
+"""Shared helpers of the GPU parity tests (comparison metrics only)."""
+import numpy as np
+import pytest
+
+try:
+    import torch
+    HAVE_GPU = torch.cuda.is_available()
+except Exception:  # pragma: no cover
+    torch = None
+    HAVE_GPU = False
+
+needs_gpu = pytest.mark.skipif(not HAVE_GPU, reason="no GPU visible")
+
+
+def ulp32_error(z32: np.ndarray, z64: np.ndarray) -> np.ndarray:
+    """|z32 - z64| in units of the FP32 ulp of z64: ulp32(v) = 2^(max(e, -126) - 23)
+    with e = floor(log2 |v|).  Where z64 == 0 exactly the error is 0 if z32 == 0
+    and infinite otherwise."""
+    z32 = np.asarray(z32, dtype=np.float32).astype(np.float64)
+    z64 = np.asarray(z64, dtype=np.float64)
+    a = np.abs(z64)
+    _, e2 = np.frexp(np.where(a > 0, a, 1.0))      # a = m 2^e2, m in [0.5, 1)
+    e = np.maximum(e2 - 1, -126)
+    err = np.abs(z32 - z64) / np.exp2(e - 23.0)
+    zero = a == 0
+    err[zero] = np.where(z32[zero] == 0, 0.0, np.inf)
+    return err
