@@ -3,9 +3,12 @@
 
 Workload (one step): 1024 independent streams (stream i seeded from 42 + i),
 2^20 outputs each as uint32, then 2^20 more each as FP32 uniforms in [0, 1)
-by the top-24-bit mapping; each written contiguously (stream-major) to HBM by
-one plain launch per type.  A step produces 2^31 random numbers.  The streams
-advance across steps, so every step generates new numbers.
+by the top-24-bit mapping; each type written contiguously to HBM by one plain
+launch in the bulk-fill layout (xg_fill_*: 64-word chunks of the streams
+interleaved, so the wavefronts write one dense region).  A step produces 2^31
+random numbers.  The streams advance across steps, so every step generates
+new numbers.  The stream-major layout (xg_generate_*) is timed beside it and
+reported under "stream_major".
 
 Prints one JSON line: RN/s of the whole job, the roofline of the uint32
 kernel (HBM write bound, per-launch duration from HIP events on the launch
@@ -80,6 +83,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--unroll", type=int, default=None)
+    ap.add_argument("--store-words", type=int, default=None)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -92,34 +96,46 @@ def main() -> int:
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     gs = XorgensStreams(STREAMS, seed=SEED, device=dev)
-    if args.waves_per_block or args.unroll:
-        wpb, un = gs.plain_tune()
-        gs.set_plain_tune(args.waves_per_block or wpb, args.unroll or un)
+    if args.waves_per_block or args.unroll or args.store_words:
+        wpb, un, sw = gs.plain_tune()
+        gs.set_plain_tune(args.waves_per_block or wpb, args.unroll or un, args.store_words or sw)
     out_u = torch.empty((STREAMS, N), dtype=torch.int32, device=dev)
     out_f = torch.empty((STREAMS, N), dtype=torch.float32, device=dev)
     stream = torch.cuda.current_stream()
 
+    def timed(launch_u, launch_f, steps):
+        """Per-launch event times (ms) of `steps` steps, and the wall time
+        between synchronisations."""
+        ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(steps)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(steps):
+            ev[k][0].record(stream)
+            launch_u()
+            ev[k][1].record(stream)
+            ev[k][2].record(stream)
+            launch_f()
+            ev[k][3].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return (sum(e[0].elapsed_time(e[1]) for e in ev) / steps,
+                sum(e[2].elapsed_time(e[3]) for e in ev) / steps, wall)
+
+    fill_u = lambda: gs.fill_u32(N, out=out_u.view(-1), stream=stream)       # noqa: E731
+    fill_f = lambda: gs.fill_f32(N, out=out_f.view(-1), stream=stream)       # noqa: E731
+    gen_u = lambda: gs.u32(N, out=out_u, stream=stream)                      # noqa: E731
+    gen_f = lambda: gs.f32(N, out=out_f, stream=stream)                      # noqa: E731
+
     for _ in range(args.warmup):
-        gs.u32(N, out=out_u, stream=stream)
-        gs.f32(N, out=out_f, stream=stream)
+        fill_u()
+        fill_f()
+        gen_u()
+        gen_f()
     torch.cuda.synchronize()
 
     K = args.steps
-    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(K)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(K):
-        ev[k][0].record(stream)
-        gs.u32(N, out=out_u, stream=stream)
-        ev[k][1].record(stream)
-        ev[k][2].record(stream)
-        gs.f32(N, out=out_f, stream=stream)
-        ev[k][3].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-
-    u32_ms = sum(e[0].elapsed_time(e[1]) for e in ev) / K
-    f32_ms = sum(e[2].elapsed_time(e[3]) for e in ev) / K
+    u32_ms, f32_ms, wall = timed(fill_u, fill_f, K)
+    sm_u32_ms, sm_f32_ms, _ = timed(gen_u, gen_f, max(5, K // 2))
     rn_per_step = 2 * STREAMS * N
     ms_per_step = wall * 1e3 / K
     bytes_per_launch = 4 * STREAMS * N
@@ -140,7 +156,7 @@ def main() -> int:
     threads = max(1, min(16, os.cpu_count() or 1))
     cpu = None if args.no_cpu_baseline else cpu_baseline(threads)
 
-    wpb, un = gs.plain_tune()
+    wpb, un, sw = gs.plain_tune()
     line = {
         "metric": "RN/s (32-bit) and % of HBM write BW",
         "value": rn_per_step / (ms_per_step * 1e-3),
@@ -156,12 +172,14 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": "bulk uniform generation: 1024 xorgens streams (seed 42 + i) x 2^20 outputs, "
-                        "uint32 then FP32 [0,1) (top-24-bit), one plain launch per type, stream-major in HBM",
+                        "uint32 then FP32 [0,1) (top-24-bit), one plain launch per type, written contiguously "
+                        "to HBM in the bulk-fill layout (64-word chunks of the streams interleaved)",
+            "layout": "bulk-fill (xg_fill_u32 / xg_fill_f32)",
             "streams": STREAMS,
             "outputs_per_stream_per_type": N,
             "rn_per_step": rn_per_step,
             "params": "(r,s,a,b,c,d)=(128,65,15,14,12,17), w=32, omega=0x9E3779B9, gamma=16",
-            "launch": {"waves_per_block": wpb, "unroll": un},
+            "launch": {"waves_per_block": wpb, "unroll": un, "store_words": sw},
         },
         "roofline": {
             "bound": "hbm",
@@ -170,12 +188,19 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_generate<u32> (xg_generate_u32)",
+            "kernel": "k_fill<u32> (xg_fill_u32)",
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": u32_ms,
         },
-        "kernels_ms": {"u32": u32_ms, "f32": f32_ms},
+        "kernels_ms": {"fill_u32": u32_ms, "fill_f32": f32_ms,
+                       "stream_major_u32": sm_u32_ms, "stream_major_f32": sm_f32_ms},
         "f32_GBs": bytes_per_launch / (f32_ms * 1e-3) / 1e9,
+        "stream_major": {
+            "layout": "stream-major (xg_generate_u32 / xg_generate_f32): out[i * 2^20 + t]",
+            "rn_per_s_kernels": rn_per_step / ((sm_u32_ms + sm_f32_ms) * 1e-3),
+            "u32_GBs": bytes_per_launch / (sm_u32_ms * 1e-3) / 1e9,
+            "u32_frac_of_peak": bytes_per_launch / (sm_u32_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        },
         "fill_ceiling_GBs": fill_gbs,
         "frac_of_fill_ceiling": achieved / fill_gbs,
         "cpu_baseline": cpu,

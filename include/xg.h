@@ -107,12 +107,17 @@ typedef struct {
     uint32_t waves_per_block;  /* streams served at once by one workgroup: 1, 2, 4, 8, 16 */
     uint32_t unroll;           /* 64-word chunks per thread per loop trip: 1, 2, 4, 8 */
     uint32_t blocks_per_cu;    /* persistent workgroups per compute unit: 1 .. 32 */
-    uint32_t reserved;         /* 0 */
+    uint32_t store_words;      /* words each lane writes per store instruction: 1, or 4
+                                  (groups of four chunks staged through a 1 KB LDS slot
+                                  per wavefront; needs unroll >= 4); 0 = library default */
 } xg_tune;
 
-/* Launch shape of the plain launches of this handle (waves_per_block and
- * unroll are used; blocks_per_cu is ignored).  The default is
- * {1, 4, 1, 0}.  Output bits do not depend on it.
+/* Launch shape of the plain and fill launches of this handle
+ * (waves_per_block, unroll and store_words are used; blocks_per_cu is
+ * ignored).  waves_per_block 0 chooses per launch: 4 when count >= 4 x the
+ * compute units, else 2 when count >= 2 x, else 1, so one stream's wavefront
+ * lands on each SIMD before any SIMD gets a second.  The default is
+ * {0, 8, 1, 4}.  Output bits do not depend on it.
  * Errors: XG_EINVAL (NULL pointer or a shape outside the ranges of xg_tune). */
 xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune);
 xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune);
@@ -130,6 +135,22 @@ xg_status xg_generate_u32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t 
                           uint32_t *d_out, void *stream);
 xg_status xg_generate_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                           float *d_out, void *stream);
+
+/* Bulk fill: the same values as xg_generate_u32 / xg_generate_f32 (same
+ * streams, same positions, same state advance), placed for HBM write
+ * bandwidth rather than per stream.  With k = i - first, full = n / 64 and
+ * rem = n mod 64, value t of stream i is at
+ *     d_out[(t / 64) * 64 * count + k * 64 + t mod 64]        for t < 64 * full,
+ *     d_out[64 * full * count + k * rem + (t - 64 * full)]      otherwise,
+ * so the count * n outputs fill d_out contiguously with no gaps, and the
+ * wavefronts of a launch advance together through one dense region of HBM
+ * (stream-major placement keeps count write fronts n words apart).  A chunk
+ * of 64 words of one stream stays contiguous.  Same arguments and errors as
+ * xg_generate_u32; waves_per_block and unroll of the plain tune apply. */
+xg_status xg_fill_u32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                      uint32_t *d_out, void *stream);
+xg_status xg_fill_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                      float *d_out, void *stream);
 
 /* Standard normals by the Box-Muller transform on consecutive pairs of
  * outputs (o_{2m}, o_{2m+1}) of the call: u1 = ((o_{2m} >> 8) + 1) 2^-24 in
@@ -212,7 +233,7 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
  * so the streams of ctx do not advance.  Synchronises `stream`.
  * times_ms, if non-NULL, receives up to max_times (shape, time) records as
  * consecutive groups of 5 floats: waves_per_block, unroll, blocks_per_cu, ms,
- * 0.  *num_times receives their count.
+ * store_words.  *num_times receives their count.
  * Errors: those of xg_generate_batch, XG_EHIP. */
 xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
                             const uint32_t *d_groups, uint32_t num_groups,

@@ -188,8 +188,9 @@ class OracleStreams:
         return out
 
     def moments(self, n: int, threads: int | None = None) -> np.ndarray:
-        """[count, 2] FP64 sums of z and z^2 over n normals."""
-        out = np.empty((self.count, 2), dtype=np.float64)
+        """[count, 3] FP64 sums of z, z^2 and |z| over n normals (the last one
+        scales the error bound of an FP32 sum of z)."""
+        out = np.empty((self.count, 3), dtype=np.float64)
         self._run(MOMENTS, n, out, threads)
         return out
 

@@ -195,8 +195,9 @@ void xgo_box_muller(uint32_t o_even, uint32_t o_odd, double *z0, double *z1)
 enum { XGO_U32 = 0, XGO_F32 = 1, XGO_NORMAL = 2, XGO_MOMENTS = 3, XGO_SKIP = 4 };
 
 /* Runs one request of kind `kind` on one stream.  `out` is uint32_t* (U32),
-   float* (F32), double* (NORMAL: n values; MOMENTS: 2 values).  A normal or
-   moments request of n variates consumes 2 * ceil(n / 2) words. */
+   float* (F32), double* (NORMAL: n values; MOMENTS: 3 values, the sums of z,
+   z^2 and |z|).  A normal or moments request of n variates consumes
+   2 * ceil(n / 2) words. */
 static void run_one(const xgo_params *p, xgo_state *st, int kind, uint64_t n, void *out)
 {
     uint64_t t;
@@ -207,7 +208,7 @@ static void run_one(const xgo_params *p, xgo_state *st, int kind, uint64_t n, vo
         float *o = (float *)out;
         for (t = 0; t < n; t++) o[t] = map_f32(step_out(p, st));
     } else if (kind == XGO_NORMAL || kind == XGO_MOMENTS) {
-        double *o = (double *)out, s1 = 0.0, s2 = 0.0;
+        double *o = (double *)out, s1 = 0.0, s2 = 0.0, sa = 0.0;
         for (t = 0; t < n; t += 2) {
             uint32_t e = step_out(p, st);
             uint32_t d = step_out(p, st);
@@ -217,11 +218,11 @@ static void run_one(const xgo_params *p, xgo_state *st, int kind, uint64_t n, vo
                 o[t] = z0;
                 if (t + 1 < n) o[t + 1] = z1;
             } else {
-                s1 += z0; s2 += z0 * z0;
-                if (t + 1 < n) { s1 += z1; s2 += z1 * z1; }
+                s1 += z0; s2 += z0 * z0; sa += fabs(z0);
+                if (t + 1 < n) { s1 += z1; s2 += z1 * z1; sa += fabs(z1); }
             }
         }
-        if (kind == XGO_MOMENTS) { o[0] = s1; o[1] = s2; }
+        if (kind == XGO_MOMENTS) { o[0] = s1; o[1] = s2; o[2] = sa; }
     } else { /* XGO_SKIP */
         for (t = 0; t < n; t++) (void)step_out(p, st);
     }

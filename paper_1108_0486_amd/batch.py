@@ -55,7 +55,8 @@ class Batch:
 
     def autotune(self, reps: int = 3, stream: torch.cuda.Stream | None = None):
         """Times every launch shape on a scratch copy of the state; returns
-        (best (waves_per_block, unroll, blocks_per_cu), [(wpb, unroll, bpc, ms)])."""
+        (best (waves_per_block, unroll, blocks_per_cu, store_words),
+         [(wpb, unroll, bpc, store_words, ms)])."""
         scratch_state = torch.empty_like(self.streams.state)
         scratch_out = torch.empty_like(self.out)
         return xg.xg_autotune_batch(self.streams.ctx, self.d_reqs.data_ptr(), self.num_reqs,

@@ -51,7 +51,7 @@ xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num
   c->num_streams = num_streams;
   c->device = dev;
   c->num_cus = cus;
-  c->plain = xg::Shape{1, 4, 1};
+  c->plain = xg::kDefaultPlain;
   *out = c;
   return XG_OK;
 }
@@ -75,20 +75,37 @@ xg_status check_range(const xg_ctx *ctx, uint64_t first, uint64_t count, uint64_
   return check_ctx_device(ctx);
 }
 
+// The plain shape with an automatic waves_per_block resolved for this launch.
+xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count) {
+  xg::Shape s = ctx->plain;
+  if (s.waves_per_block == 0) s.waves_per_block = xg::auto_waves_per_block(count, ctx->num_cus);
+  return s;
+}
+
 xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, void *out,
                 void *stream) {
   const uint64_t per_stream = kind == xg::kMoments ? 2 : n;
   xg_status st = check_range(ctx, first, count, n, out, per_stream);
   if (st != XG_OK || n == 0) return st;
-  const hipError_t e = xg::launch_generate(kind, ctx->plain, ctx->d_state, first, count, n, out,
-                                           static_cast<hipStream_t>(stream));
+  const hipError_t e = xg::launch_generate(kind, plain_shape(ctx, count), ctx->d_state, first, count,
+                                           n, out, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
-bool tune_to_shape(const xg_tune *t, xg::Shape *s) {
+xg_status fill(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, void *out,
+               void *stream) {
+  xg_status st = check_range(ctx, first, count, n, out, n);
+  if (st != XG_OK || n == 0) return st;
+  const hipError_t e = xg::launch_fill(kind, plain_shape(ctx, count), ctx->d_state, first, count, n,
+                                       static_cast<uint32_t *>(out), static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
+bool tune_to_shape(const xg_tune *t, uint32_t blocks_per_cu, xg::Shape *s) {
   if (!t) return false;
-  *s = xg::Shape{t->waves_per_block, t->unroll, t->blocks_per_cu};
-  return t->reserved == 0 && xg::shape_valid(*s);
+  const uint32_t sw = t->store_words ? t->store_words : (t->unroll >= 4 ? 4u : 1u);
+  *s = xg::Shape{t->waves_per_block, t->unroll, blocks_per_cu, sw};
+  return xg::shape_valid(*s);
 }
 
 // Relative cost of a request in the planner's balance: words consumed, with
@@ -132,8 +149,12 @@ void *xg_state_ptr(const xg_ctx *ctx) { return ctx ? ctx->d_state : nullptr; }
 
 xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune) {
   if (!ctx || !tune) return XG_EINVAL;
-  xg::Shape s{tune->waves_per_block, tune->unroll, 1};
-  if (!xg::shape_valid(s)) return XG_EINVAL;
+  xg_tune t = *tune;
+  const bool automatic = t.waves_per_block == 0;
+  if (automatic) t.waves_per_block = 1;  // validate the other fields
+  xg::Shape s;
+  if (!tune_to_shape(&t, 1, &s)) return XG_EINVAL;
+  if (automatic) s.waves_per_block = 0;
   ctx->plain = s;
   return XG_OK;
 }
@@ -143,7 +164,7 @@ xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune) {
   tune->waves_per_block = ctx->plain.waves_per_block;
   tune->unroll = ctx->plain.unroll;
   tune->blocks_per_cu = 1;
-  tune->reserved = 0;
+  tune->store_words = ctx->plain.store_words;
   return XG_OK;
 }
 
@@ -165,6 +186,16 @@ xg_status xg_generate_normal(xg_ctx *ctx, uint64_t first, uint64_t count, uint64
 xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, float *d_sums,
                             void *stream) {
   return plain(ctx, xg::kMoments, first, count, n, d_sums, stream);
+}
+
+xg_status xg_fill_u32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, uint32_t *d_out,
+                      void *stream) {
+  return fill(ctx, xg::kU32, first, count, n, d_out, stream);
+}
+
+xg_status xg_fill_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, float *d_out,
+                      void *stream) {
+  return fill(ctx, xg::kF32, first, count, n, d_out, stream);
 }
 
 size_t xg_batch_workspace_bytes(void) { return 256; }
@@ -226,8 +257,8 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_groups) % 4 ||
       reinterpret_cast<uintptr_t>(d_out) % 4 || reinterpret_cast<uintptr_t>(d_work) % 4)
     return XG_EALIGN;
-  xg::Shape shape{4, 4, 8};
-  if (tune && !tune_to_shape(tune, &shape)) return XG_EINVAL;
+  xg::Shape shape = xg::kDefaultBatch;
+  if (tune && !tune_to_shape(tune, tune->blocks_per_cu, &shape)) return XG_EINVAL;
   xg_status st = check_ctx_device(ctx);
   if (st != XG_OK) return st;
   if (num_groups == 0) return XG_OK;
@@ -255,6 +286,7 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   static const uint32_t kWpb[] = {1, 2, 4, 8, 16};
   static const uint32_t kUnroll[] = {1, 2, 4, 8};
   static const uint32_t kBpc[] = {1, 2, 4, 8, 16, 32};
+  static const uint32_t kStoreWords[] = {1, 4};
   hipEvent_t t0 = nullptr, t1 = nullptr;
   if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
     if (t0) (void)hipEventDestroy(t0);
@@ -266,38 +298,43 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   for (uint32_t wpb : kWpb) {
     for (uint32_t un : kUnroll) {
       for (uint32_t bpc : kBpc) {
-        if (wpb * bpc > 32) continue;  // more waves than a compute unit holds
-        const xg_tune cand{wpb, un, bpc, 0};
-        std::vector<float> ms;
-        for (int rep = 0; rep <= reps && result == XG_OK; ++rep) {
-          if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) != hipSuccess) {
-            result = XG_EHIP;
-            break;
+        for (uint32_t sw : kStoreWords) {
+          if (wpb * bpc > 32) continue;  // more waves than a compute unit holds
+          if (sw == 4 && un < 4) continue;
+          const xg_tune cand{wpb, un, bpc, sw};
+          std::vector<float> ms;
+          for (int rep = 0; rep <= reps && result == XG_OK; ++rep) {
+            if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) !=
+                hipSuccess) {
+              result = XG_EHIP;
+              break;
+            }
+            if (hipEventRecord(t0, s) != hipSuccess) { result = XG_EHIP; break; }
+            result = xg_generate_batch(&scratch, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out,
+                                       out_elems, &cand, d_work, stream);
+            if (result != XG_OK) break;
+            if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
+              result = XG_EHIP;
+              break;
+            }
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, t0, t1) != hipSuccess) { result = XG_EHIP; break; }
+            if (rep > 0) ms.push_back(t);  // rep 0 is the warm-up
           }
-          if (hipEventRecord(t0, s) != hipSuccess) { result = XG_EHIP; break; }
-          result = xg_generate_batch(&scratch, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out,
-                                     out_elems, &cand, d_work, stream);
           if (result != XG_OK) break;
-          if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
-            result = XG_EHIP;
-            break;
+          std::sort(ms.begin(), ms.end());
+          const float med = ms[ms.size() / 2];
+          if (times_ms && recorded < max_times) {
+            float *rec = times_ms + 5 * recorded;
+            rec[0] = (float)wpb; rec[1] = (float)un; rec[2] = (float)bpc; rec[3] = med; rec[4] = (float)sw;
+            ++recorded;
           }
-          float t = 0.f;
-          if (hipEventElapsedTime(&t, t0, t1) != hipSuccess) { result = XG_EHIP; break; }
-          if (rep > 0) ms.push_back(t);  // rep 0 is the warm-up
+          if (best_ms < 0.f || med < best_ms) {
+            best_ms = med;
+            *best = cand;
+          }
         }
         if (result != XG_OK) break;
-        std::sort(ms.begin(), ms.end());
-        const float med = ms[ms.size() / 2];
-        if (times_ms && recorded < max_times) {
-          float *rec = times_ms + 5 * recorded;
-          rec[0] = (float)wpb; rec[1] = (float)un; rec[2] = (float)bpc; rec[3] = med; rec[4] = 0.f;
-          ++recorded;
-        }
-        if (best_ms < 0.f || med < best_ms) {
-          best_ms = med;
-          *best = cand;
-        }
       }
       if (result != XG_OK) break;
     }

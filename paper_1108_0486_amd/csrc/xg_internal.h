@@ -17,10 +17,19 @@ constexpr uint32_t kWave = 64;
 enum Kind : uint32_t { kU32 = XG_U32, kF32 = XG_F32, kNormal = XG_NORMAL, kMoments = 3 };
 
 struct Shape {
-  uint32_t waves_per_block;  // 1, 2, 4, 8, 16
+  uint32_t waves_per_block;  // 1, 2, 4, 8, 16; 0 (plain launches only): chosen per launch
   uint32_t unroll;           // 1, 2, 4, 8
   uint32_t blocks_per_cu;    // persistent batch only
+  uint32_t store_words;      // 1 or 4 (4 needs unroll >= 4)
 };
+
+constexpr Shape kDefaultPlain{0, 8, 1, 4};
+
+// Waves per block for a plain launch of `count` streams on `num_cus` compute
+// units: one stream per wavefront, and at least as many blocks as compute
+// units, so that the wavefronts spread one per SIMD before any SIMD gets two.
+uint32_t auto_waves_per_block(uint64_t count, int num_cus);
+constexpr Shape kDefaultBatch{4, 8, 8, 4};
 
 bool shape_valid(const Shape &s);
 
@@ -28,6 +37,10 @@ hipError_t launch_init(uint32_t *state, uint64_t num_streams, uint64_t seed, hip
 
 hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint64_t first,
                            uint64_t count, uint64_t n, void *out, hipStream_t stream);
+
+// Bulk-fill layout of xg_fill_u32 / xg_fill_f32 (kind kU32 or kF32).
+hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t first, uint64_t count,
+                       uint64_t n, uint32_t *out, hipStream_t stream);
 
 hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
                         const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,

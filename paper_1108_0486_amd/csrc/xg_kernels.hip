@@ -31,6 +31,7 @@ constexpr uint32_t kChunkOmega = 64u * kOmega;  // Weyl advance per chunk (mod 2
 constexpr uint64_t kGolden64 = 0x9E3779B97F4A7C15ull;
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 // x (I + L^12)(I + R^17): the operator applied to x_{i-s}.
 __device__ __forceinline__ uint32_t op_lag_s(uint32_t v) {
@@ -114,59 +115,156 @@ __device__ __forceinline__ uint64_t load_pos(const uint32_t *st) {
   return (uint64_t)st[130] | ((uint64_t)st[131] << 32);
 }
 
+// Output word of type KIND for generator output o (FP32 as its bit pattern):
+// u32 as is; f32 (o >> 8) * 2^-24, exact (a 24-bit integer times a power of two).
 template <uint32_t KIND>
-__device__ __forceinline__ void emit_word(uint32_t *p, uint32_t o) {
+__device__ __forceinline__ uint32_t map_word(uint32_t o) {
   if constexpr (KIND == kU32) {
-    __builtin_nontemporal_store(o, p);
+    return o;
   } else {
-    const float f = (float)(o >> 8) * 0x1p-24f;  // exact: a 24-bit integer times 2^-24
-    __builtin_nontemporal_store(f, reinterpret_cast<float *>(p));
+    return __float_as_uint((float)(o >> 8) * 0x1p-24f);
   }
 }
 
+template <uint32_t KIND>
+__device__ __forceinline__ void emit_word(uint32_t *p, uint32_t o) {
+  __builtin_nontemporal_store(map_word<KIND>(o), p);
+}
+
+// Dynamic LDS: one 256-word staging slot per wavefront of the block (wide stores).
+extern __shared__ __align__(16) uint32_t xg_lds[];
+
+__device__ __forceinline__ uint32_t *wave_stage() { return xg_lds + (threadIdx.x >> 6) * 256u; }
+
 // ---------------------------------------------------------------------------
-// u32 / f32: n words of one stream, written contiguously at out[0 .. n).
+// One stream's word sequence inside a wavefront: open (load the state), next
+// (one 64-word chunk of outputs, lane j holding word j), close (the ragged last
+// chunk, then the state write-back).
 // ---------------------------------------------------------------------------
-template <uint32_t KIND, int UNROLL>
+struct WordStream {
+  Ring g;
+  uint32_t w_start;  // W_{pos-1} at open
+  uint32_t wbase;    // W_{p-1} for the next chunk at p
+  uint32_t wlane;    // (j + 1) omega: W_{p+j} = W_{p-1} + (j + 1) omega
+  uint64_t pos;
+  uint32_t lane;
+  bool lane0;
+};
+
+__device__ __forceinline__ WordStream open_stream(const uint32_t *st) {
+  WordStream s;
+  s.lane = lane_id();
+  s.lane0 = s.lane == 0;
+  s.g = ring_from(st[s.lane], st[64 + s.lane]);
+  s.w_start = st[128];
+  s.wbase = s.w_start;
+  s.wlane = (s.lane + 1u) * kOmega;
+  s.pos = load_pos(st);
+  return s;
+}
+
+__device__ __forceinline__ uint32_t next_chunk(WordStream &s) {
+  const uint32_t x = ring_step(s.g, s.lane0);
+  const uint32_t w = s.wbase + s.wlane;
+  s.wbase += kChunkOmega;
+  return x + temper_weyl(w);
+}
+
+// Emits the last rem (< 64) words of an n-word request through `tail`
+// (lane-indexed: lane j writes tail[j], j < rem) and writes the state back.
+template <uint32_t KIND>
+__device__ __forceinline__ void close_stream(uint32_t *st, WordStream &s, uint64_t n, uint32_t rem,
+                                             uint32_t *tail) {
+  const uint32_t p0 = s.g.prev, c0 = s.g.cur;
+  uint32_t x = 0u;
+  if (rem) {
+    x = ring_step(s.g, s.lane0);
+    const uint32_t w = s.wbase + s.wlane;
+    if (s.lane < rem) emit_word<KIND>(tail, x + temper_weyl(w));
+  }
+  store_ring(st, p0, c0, x, rem, s.lane);
+  store_weyl_pos(st, s.w_start + (uint32_t)n * kOmega, s.pos + n, s.lane);
+}
+
+// ---------------------------------------------------------------------------
+// u32 / f32, stream-major: n words of one stream written at out[0 .. n).
+// WIDE: while out is 16-byte aligned, four chunks (256 words) are staged in
+// the wavefront's LDS slot and leave as one 16-byte store per lane (1 KB per
+// store instruction instead of 256 B); the rest uses one 4-byte store per lane.
+// ---------------------------------------------------------------------------
+template <uint32_t KIND, int UNROLL, bool WIDE>
 __device__ __forceinline__ void serve_words(uint32_t *__restrict__ st, uint64_t n,
                                             uint32_t *__restrict__ out) {
-  const uint32_t lane = lane_id();
-  const bool lane0 = lane == 0;
-  Ring g = ring_from(st[lane], st[64 + lane]);
-  const uint32_t w_start = st[128];
-  const uint64_t pos = load_pos(st);
-  uint32_t wbase = w_start;                     // W_{p-1}
-  const uint32_t wlane = (lane + 1u) * kOmega;  // W_{p+j} = W_{p-1} + (j + 1) omega
+  WordStream s = open_stream(st);
+  const uint32_t lane = s.lane;
   const uint64_t nfull = n >> 6;
   const uint32_t rem = (uint32_t)(n & 63u);
-  uint32_t *o = out + lane;
+  uint64_t done = 0;  // chunks written by the wide loop
+  if constexpr (WIDE) {
+    static_assert(UNROLL % 4 == 0, "wide stores take groups of four chunks");
+    if ((reinterpret_cast<uintptr_t>(out) & 15u) == 0) {
+      uint32_t *stage = wave_stage();
+      u32x4 *o4 = reinterpret_cast<u32x4 *>(out) + lane;
+      const uint64_t nouter = nfull / UNROLL;
+      for (uint64_t it = 0; it != nouter; ++it) {
+#pragma unroll
+        for (int q = 0; q < UNROLL / 4; ++q) {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) stage[64 * u + lane] = map_word<KIND>(next_chunk(s));
+          // In-order LDS: this read sees the four writes above, and the next
+          // group's writes land after it.
+          const u32x4 v = *reinterpret_cast<const u32x4 *>(stage + 4 * lane);
+          __builtin_nontemporal_store(v, o4 + q * 64);
+        }
+        o4 += (UNROLL / 4) * 64;
+      }
+      done = nouter * UNROLL;
+    }
+  }
+  uint32_t *o = out + done * 64 + lane;
+  const uint64_t nrest = nfull - done;
+  const uint64_t nouter = nrest / UNROLL;
+  for (uint64_t it = 0; it != nouter; ++it) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) emit_word<KIND>(o + u * 64, next_chunk(s));
+    o += UNROLL * 64;
+  }
+  const uint32_t nleft = (uint32_t)(nrest % UNROLL);
+  for (uint32_t c = 0; c != nleft; ++c) {
+    emit_word<KIND>(o, next_chunk(s));
+    o += 64;
+  }
+  close_stream<KIND>(st, s, n, rem, o);
+}
+
+// ---------------------------------------------------------------------------
+// u32 / f32, bulk-fill layout: chunk c (words 64c .. 64c + 63) of the k-th of
+// `count` streams goes to out[(c count + k) 64 ..], so the wavefronts of a
+// launch write one dense, advancing region of HBM instead of `count` fronts
+// n words apart; the ragged last chunks (rem = n mod 64 words each) follow,
+// packed, at out[64 (n / 64) count + k rem ..].  The values are those of the
+// stream-major layout; only their places differ.
+// ---------------------------------------------------------------------------
+template <uint32_t KIND, int UNROLL>
+__device__ __forceinline__ void serve_words_fill(uint32_t *__restrict__ st, uint64_t n, uint64_t k,
+                                                 uint64_t count, uint32_t *__restrict__ out) {
+  WordStream s = open_stream(st);
+  const uint64_t nfull = n >> 6;
+  const uint32_t rem = (uint32_t)(n & 63u);
+  const uint64_t stride = count * 64;
+  uint32_t *o = out + k * 64 + s.lane;
   const uint64_t nouter = nfull / UNROLL;
   for (uint64_t it = 0; it != nouter; ++it) {
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) {
-      const uint32_t x = ring_step(g, lane0);
-      const uint32_t w = wbase + wlane;
-      wbase += kChunkOmega;
-      emit_word<KIND>(o + u * 64, x + temper_weyl(w));
-    }
-    o += UNROLL * 64;
+    for (int u = 0; u < UNROLL; ++u) emit_word<KIND>(o + u * stride, next_chunk(s));
+    o += UNROLL * stride;
   }
   const uint32_t nleft = (uint32_t)(nfull % UNROLL);
   for (uint32_t c = 0; c != nleft; ++c) {
-    const uint32_t x = ring_step(g, lane0);
-    const uint32_t w = wbase + wlane;
-    wbase += kChunkOmega;
-    emit_word<KIND>(o, x + temper_weyl(w));
-    o += 64;
+    emit_word<KIND>(o, next_chunk(s));
+    o += stride;
   }
-  uint32_t p0 = g.prev, c0 = g.cur, x = 0u;
-  if (rem) {
-    x = ring_step(g, lane0);
-    const uint32_t w = wbase + wlane;
-    if (lane < rem) emit_word<KIND>(o, x + temper_weyl(w));
-  }
-  store_ring(st, p0, c0, x, rem, lane);
-  store_weyl_pos(st, w_start + (uint32_t)n * kOmega, pos + n, lane);
+  close_stream<KIND>(st, s, n, rem, out + nfull * stride + k * rem + s.lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -352,19 +450,28 @@ __global__ __launch_bounds__(256) void k_init(uint32_t *__restrict__ state, uint
   store_weyl_pos(st, w0 + 512u * kOmega, 0ull, lane);
 }
 
-template <uint32_t KIND, int UNROLL>
+template <uint32_t KIND, int UNROLL, bool WIDE>
 __global__ __launch_bounds__(1024) void k_generate(uint32_t *__restrict__ state, uint64_t first,
                                                    uint64_t count, uint64_t n, void *__restrict__ out) {
   const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   if (wid >= count) return;
   uint32_t *st = state + (first + wid) * kStateWords;
   if constexpr (KIND == kU32 || KIND == kF32) {
-    serve_words<KIND, UNROLL>(st, n, reinterpret_cast<uint32_t *>(out) + wid * n);
+    serve_words<KIND, UNROLL, WIDE>(st, n, reinterpret_cast<uint32_t *>(out) + wid * n);
   } else if constexpr (KIND == kNormal) {
     serve_normals<false, UNROLL>(st, n, reinterpret_cast<float *>(out) + wid * n, nullptr);
   } else {
     serve_normals<true, UNROLL>(st, n, nullptr, reinterpret_cast<float *>(out) + 2 * wid);
   }
+}
+
+// Bulk-fill layout (see serve_words_fill): uint32 / FP32 only.
+template <uint32_t KIND, int UNROLL>
+__global__ __launch_bounds__(1024) void k_fill(uint32_t *__restrict__ state, uint64_t first,
+                                               uint64_t count, uint64_t n, uint32_t *__restrict__ out) {
+  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wid >= count) return;
+  serve_words_fill<KIND, UNROLL>(state + (first + wid) * kStateWords, n, wid, count, out);
 }
 
 __global__ void k_clear_work(uint32_t *work) {
@@ -373,7 +480,7 @@ __global__ void k_clear_work(uint32_t *work) {
 
 // Persistent batched kernel: wavefronts take request groups from an atomic
 // queue (work[0]) until it is exhausted; every wavefront reaches the exit.
-template <int UNROLL>
+template <int UNROLL, bool WIDE>
 __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, uint64_t num_streams,
                                                 const xg_request *__restrict__ reqs,
                                                 uint32_t num_reqs,
@@ -402,9 +509,9 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
       uint32_t *st = state + q.stream * kStateWords;
       uint32_t *o = out + q.out_offset;
       if (q.dtype == XG_U32) {
-        serve_words<kU32, UNROLL>(st, q.n, o);
+        serve_words<kU32, UNROLL, WIDE>(st, q.n, o);
       } else if (q.dtype == XG_F32) {
-        serve_words<kF32, UNROLL>(st, q.n, o);
+        serve_words<kF32, UNROLL, WIDE>(st, q.n, o);
       } else {
         serve_normals<false, UNROLL>(st, q.n, reinterpret_cast<float *>(o), nullptr);
       }
@@ -413,29 +520,71 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
 }
 
 template <uint32_t KIND>
-hipError_t launch_generate_k(int unroll, dim3 grid, dim3 block, uint32_t *state, uint64_t first,
+hipError_t launch_generate_k(const Shape &sh, dim3 grid, dim3 block, uint32_t *state, uint64_t first,
                              uint64_t count, uint64_t n, void *out, hipStream_t stream) {
-  switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_generate<KIND, 1>), grid, block, 0, stream, state, first, count, n, out); break;
-    case 2: hipLaunchKernelGGL((k_generate<KIND, 2>), grid, block, 0, stream, state, first, count, n, out); break;
-    case 4: hipLaunchKernelGGL((k_generate<KIND, 4>), grid, block, 0, stream, state, first, count, n, out); break;
-    default: hipLaunchKernelGGL((k_generate<KIND, 8>), grid, block, 0, stream, state, first, count, n, out); break;
+  constexpr bool kWords = KIND == kU32 || KIND == kF32;
+  const bool wide = kWords && sh.store_words == 4;
+  const size_t lds = wide ? (size_t)sh.waves_per_block * 1024u : 0u;
+  if (wide) {
+    if (sh.unroll == 4) {
+      hipLaunchKernelGGL((k_generate<KIND, 4, kWords>), grid, block, lds, stream, state, first, count, n, out);
+    } else {
+      hipLaunchKernelGGL((k_generate<KIND, 8, kWords>), grid, block, lds, stream, state, first, count, n, out);
+    }
+    return hipGetLastError();
+  }
+  switch (sh.unroll) {
+    case 1: hipLaunchKernelGGL((k_generate<KIND, 1, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 2: hipLaunchKernelGGL((k_generate<KIND, 2, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 4: hipLaunchKernelGGL((k_generate<KIND, 4, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    default: hipLaunchKernelGGL((k_generate<KIND, 8, false>), grid, block, 0, stream, state, first, count, n, out); break;
   }
   return hipGetLastError();
 }
 
 }  // namespace
 
+uint32_t auto_waves_per_block(uint64_t count, int num_cus) {
+  const uint64_t cus = num_cus > 0 ? (uint64_t)num_cus : 1;
+  if (count >= 4 * cus) return 4;
+  if (count >= 2 * cus) return 2;
+  return 1;
+}
+
 bool shape_valid(const Shape &s) {
   const bool wpb = s.waves_per_block == 1 || s.waves_per_block == 2 || s.waves_per_block == 4 ||
                    s.waves_per_block == 8 || s.waves_per_block == 16;
   const bool un = s.unroll == 1 || s.unroll == 2 || s.unroll == 4 || s.unroll == 8;
-  return wpb && un && s.blocks_per_cu >= 1 && s.blocks_per_cu <= 32;
+  const bool sw = s.store_words == 1 || (s.store_words == 4 && s.unroll >= 4);
+  return wpb && un && sw && s.blocks_per_cu >= 1 && s.blocks_per_cu <= 32;
 }
 
 hipError_t launch_init(uint32_t *state, uint64_t num_streams, uint64_t seed, hipStream_t stream) {
   const uint64_t blocks = (num_streams + 3) / 4;
   hipLaunchKernelGGL(k_init, dim3((uint32_t)blocks), dim3(256), 0, stream, state, num_streams, seed);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t first, uint64_t count,
+                       uint64_t n, uint32_t *out, hipStream_t stream) {
+  const uint64_t wpb = shape.waves_per_block;
+  const dim3 grid((uint32_t)((count + wpb - 1) / wpb));
+  const dim3 block((uint32_t)(wpb * kWave));
+  const bool f = kind == kF32;
+  switch (shape.unroll) {
+    case 1: if (f) hipLaunchKernelGGL((k_fill<kF32, 1>), grid, block, 0, stream, state, first, count, n, out);
+            else hipLaunchKernelGGL((k_fill<kU32, 1>), grid, block, 0, stream, state, first, count, n, out);
+            break;
+    case 2: if (f) hipLaunchKernelGGL((k_fill<kF32, 2>), grid, block, 0, stream, state, first, count, n, out);
+            else hipLaunchKernelGGL((k_fill<kU32, 2>), grid, block, 0, stream, state, first, count, n, out);
+            break;
+    case 4: if (f) hipLaunchKernelGGL((k_fill<kF32, 4>), grid, block, 0, stream, state, first, count, n, out);
+            else hipLaunchKernelGGL((k_fill<kU32, 4>), grid, block, 0, stream, state, first, count, n, out);
+            break;
+    default: if (f) hipLaunchKernelGGL((k_fill<kF32, 8>), grid, block, 0, stream, state, first, count, n, out);
+             else hipLaunchKernelGGL((k_fill<kU32, 8>), grid, block, 0, stream, state, first, count, n, out);
+             break;
+  }
   return hipGetLastError();
 }
 
@@ -445,10 +594,10 @@ hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint6
   const dim3 grid((uint32_t)((count + wpb - 1) / wpb));
   const dim3 block((uint32_t)(wpb * kWave));
   switch (kind) {
-    case kU32: return launch_generate_k<kU32>(shape.unroll, grid, block, state, first, count, n, out, stream);
-    case kF32: return launch_generate_k<kF32>(shape.unroll, grid, block, state, first, count, n, out, stream);
-    case kNormal: return launch_generate_k<kNormal>(shape.unroll, grid, block, state, first, count, n, out, stream);
-    default: return launch_generate_k<kMoments>(shape.unroll, grid, block, state, first, count, n, out, stream);
+    case kU32: return launch_generate_k<kU32>(shape, grid, block, state, first, count, n, out, stream);
+    case kF32: return launch_generate_k<kF32>(shape, grid, block, state, first, count, n, out, stream);
+    case kNormal: return launch_generate_k<kNormal>(shape, grid, block, state, first, count, n, out, stream);
+    default: return launch_generate_k<kMoments>(shape, grid, block, state, first, count, n, out, stream);
   }
 }
 
@@ -464,11 +613,20 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
   const uint64_t need = (want_waves + shape.waves_per_block - 1) / shape.waves_per_block;
   if (need < blocks) blocks = need ? need : 1;
   const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  if (shape.store_words == 4) {
+    const size_t lds = (size_t)shape.waves_per_block * 1024u;
+    if (shape.unroll == 4) {
+      hipLaunchKernelGGL((k_batch<4, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work);
+    } else {
+      hipLaunchKernelGGL((k_batch<8, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work);
+    }
+    return hipGetLastError();
+  }
   switch (shape.unroll) {
-    case 1: hipLaunchKernelGGL(k_batch<1>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    case 2: hipLaunchKernelGGL(k_batch<2>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    case 4: hipLaunchKernelGGL(k_batch<4>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    default: hipLaunchKernelGGL(k_batch<8>, grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 1: hipLaunchKernelGGL((k_batch<1, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 2: hipLaunchKernelGGL((k_batch<2, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 4: hipLaunchKernelGGL((k_batch<4, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    default: hipLaunchKernelGGL((k_batch<8, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
   }
   return hipGetLastError();
 }

@@ -52,8 +52,8 @@ class XorgensStreams:
             pass
 
     # ---- tuning -----------------------------------------------------------
-    def set_plain_tune(self, waves_per_block: int, unroll: int) -> None:
-        xg.xg_set_plain_tune(self.ctx, waves_per_block, unroll)
+    def set_plain_tune(self, waves_per_block: int, unroll: int, store_words: int = 0) -> None:
+        xg.xg_set_plain_tune(self.ctx, waves_per_block, unroll, store_words)
 
     def plain_tune(self) -> tuple:
         return xg.xg_get_plain_tune(self.ctx)
@@ -80,6 +80,21 @@ class XorgensStreams:
         first, count = self._range(first, count)
         out = self._out(out, (count, n), torch.float32)
         xg.xg_generate_f32(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def fill_u32(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """count * n int32 (uint32 bits) in the bulk-fill layout (xg.fill_index)."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count * n,), torch.int32)
+        xg.xg_fill_u32(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def fill_f32(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        first, count = self._range(first, count)
+        out = self._out(out, (count * n,), torch.float32)
+        xg.xg_fill_f32(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
         return out
 
     def normal(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,

@@ -42,10 +42,16 @@ class xg_request(ctypes.Structure):
 
 class xg_tune(ctypes.Structure):
     _fields_ = [("waves_per_block", ctypes.c_uint32), ("unroll", ctypes.c_uint32),
-                ("blocks_per_cu", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("blocks_per_cu", ctypes.c_uint32), ("store_words", ctypes.c_uint32)]
+
+    @classmethod
+    def of(cls, shape) -> "xg_tune":
+        """(waves_per_block, unroll, blocks_per_cu[, store_words]); store_words 0 = default."""
+        shape = tuple(shape) + (0,) * (4 - len(shape))
+        return cls(*shape)
 
     def as_tuple(self):
-        return (self.waves_per_block, self.unroll, self.blocks_per_cu)
+        return (self.waves_per_block, self.unroll, self.blocks_per_cu, self.store_words)
 
 
 _lib = None
@@ -75,6 +81,8 @@ def lib() -> ctypes.CDLL:
         "xg_generate_f32": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_generate_normal": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_normal_moments": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_fill_u32": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_fill_f32": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
         "xg_plan_batch": (st, [P(xg_request), u32, u64, u64, P(xg_request), P(u32), P(u32)]),
         "xg_generate_batch": (st, [vp, vp, u32, vp, u32, vp, u64, P(xg_tune), vp, vp]),
@@ -130,15 +138,16 @@ def xg_destroy(ctx) -> None:
     lib().xg_destroy(ctx)
 
 
-def xg_set_plain_tune(ctx, waves_per_block: int, unroll: int) -> None:
-    t = xg_tune(waves_per_block, unroll, 1, 0)
+def xg_set_plain_tune(ctx, waves_per_block: int, unroll: int, store_words: int = 0) -> None:
+    t = xg_tune(waves_per_block, unroll, 1, store_words)
     _check(lib().xg_set_plain_tune(ctx, ctypes.byref(t)), "xg_set_plain_tune")
 
 
 def xg_get_plain_tune(ctx) -> tuple:
+    """(waves_per_block, unroll, store_words) of the plain launches."""
     t = xg_tune()
     _check(lib().xg_get_plain_tune(ctx, ctypes.byref(t)), "xg_get_plain_tune")
-    return t.as_tuple()[:2]
+    return (t.waves_per_block, t.unroll, t.store_words)
 
 
 def xg_generate_u32(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
@@ -155,6 +164,25 @@ def xg_generate_normal(ctx, first: int, count: int, n: int, d_out: int, stream: 
 
 def xg_normal_moments(ctx, first: int, count: int, n: int, d_sums: int, stream: int = 0) -> None:
     _check(lib().xg_normal_moments(ctx, first, count, n, d_sums, stream), "xg_normal_moments")
+
+
+def xg_fill_u32(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_fill_u32(ctx, first, count, n, d_out, stream), "xg_fill_u32")
+
+
+def xg_fill_f32(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_fill_f32(ctx, first, count, n, d_out, stream), "xg_fill_f32")
+
+
+def fill_index(count: int, n: int):
+    """numpy index array idx[k, t]: where xg_fill_* put value t of the k-th stream."""
+    import numpy as np
+    full, rem = n // 64, n % 64
+    t = np.arange(n, dtype=np.int64)
+    k = np.arange(count, dtype=np.int64)[:, None]
+    head = (t // 64) * 64 * count + k * 64 + t % 64
+    tail = 64 * full * count + k * rem + (t - 64 * full)
+    return np.where(t < 64 * full, head, tail)
 
 
 def xg_batch_workspace_bytes() -> int:
@@ -178,7 +206,7 @@ def xg_plan_batch(requests, num_streams: int, out_elems: int):
 
 def xg_generate_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int, d_out: int,
                       out_elems: int, tune: tuple | None, d_work: int, stream: int = 0) -> None:
-    t = None if tune is None else ctypes.byref(xg_tune(tune[0], tune[1], tune[2], 0))
+    t = None if tune is None else ctypes.byref(xg_tune.of(tune))
     _check(lib().xg_generate_batch(ctx, d_reqs, num_reqs, d_groups, num_groups, d_out, out_elems, t,
                                    d_work, stream), "xg_generate_batch")
 
@@ -186,7 +214,7 @@ def xg_generate_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups
 def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int,
                       d_scratch_out: int, out_elems: int, d_scratch_state: int, d_work: int,
                       reps: int = 3, stream: int = 0):
-    """Returns (best shape tuple, [(wpb, unroll, bpc, ms), ...])."""
+    """Returns (best (wpb, unroll, bpc, store_words), [(wpb, unroll, bpc, store_words, ms), ...])."""
     best = xg_tune()
     maxt = 256
     times = (ctypes.c_float * (5 * maxt))()
@@ -194,6 +222,6 @@ def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups
     _check(lib().xg_autotune_batch(ctx, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out, out_elems,
                                    d_scratch_state, d_work, reps, ctypes.byref(best), times, maxt,
                                    ctypes.byref(nt), stream), "xg_autotune_batch")
-    recs = [(int(times[5 * i]), int(times[5 * i + 1]), int(times[5 * i + 2]), float(times[5 * i + 3]))
-            for i in range(nt.value)]
+    recs = [(int(times[5 * i]), int(times[5 * i + 1]), int(times[5 * i + 2]), int(times[5 * i + 4]),
+             float(times[5 * i + 3])) for i in range(nt.value)]
     return best.as_tuple(), recs

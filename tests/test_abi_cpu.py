@@ -89,3 +89,16 @@ def test_plan_batch_large_is_balanced_order():
     assert sorted((out[i].stream for i in range(len(reqs)))) == list(range(4096))
     assert len(groups) == 4097
     del np
+
+
+@pytest.mark.parametrize("count,n", [(1, 1), (3, 64), (5, 65), (7, 1000), (64, 4096 + 13), (2, 0)])
+def test_fill_index_is_a_permutation(count, n):
+    import numpy as np
+    idx = xg.fill_index(count, n)
+    assert idx.shape == (count, n)
+    assert np.array_equal(np.sort(idx.ravel()), np.arange(count * n))
+    # a 64-word chunk of one stream stays contiguous; chunk c of stream k at (c count + k) 64
+    for k in range(count):
+        for c in range(n // 64):
+            assert idx[k, 64 * c] == (c * count + k) * 64
+            assert (np.diff(idx[k, 64 * c:64 * c + 64]) == 1).all()

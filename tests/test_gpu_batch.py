@@ -55,7 +55,8 @@ def _check_outputs(out_i32: np.ndarray, reqs, want):
             assert ulp32_error(got.view(np.float32), w).max() <= 4.0, (s, n, dt)
 
 
-@pytest.mark.parametrize("tune", [None, (1, 1, 1), (4, 4, 8), (16, 8, 2), (2, 2, 32)])
+@pytest.mark.parametrize("tune", [None, (1, 1, 1), (4, 4, 8), (16, 8, 2), (2, 2, 32), (4, 8, 4, 4),
+                                  (1, 4, 8, 4), (8, 8, 4, 1)])
 def test_batch_matches_oracle(tune):
     rng = np.random.default_rng(17)
     reqs, total = _requests(rng, 300, 700)
@@ -119,8 +120,9 @@ def test_autotune_keeps_state_and_bits():
     best, recs = b.autotune(reps=1)
     torch.cuda.synchronize()
     assert torch.equal(before, gs.state)
-    assert len(recs) > 10 and all(r[3] > 0 for r in recs)
-    assert best in [r[:3] for r in recs]
+    assert len(recs) > 10 and all(r[4] > 0 for r in recs)
+    assert best in [r[:4] for r in recs]
+    assert {r[3] for r in recs} == {1, 4}
     b.run(tune=best)
     out_best = b.out.clone()
     gs.restore(before)

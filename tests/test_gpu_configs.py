@@ -1,0 +1,133 @@
+"""The workloads at their full sizes, in the launch configurations bench.py
+and the batched path use, against the CPU oracle.
+
+- one stream, seed 42, 2^20 uint32: every word, and the stored digest;
+- 1024 streams (seed 42 + i) x 2^20, uint32 then FP32, bulk-fill layout (the
+  benchmark's launches) and stream-major layout: every word of every stream;
+- 65536 streams with log-uniform lengths in [2^10, 2^20] (seed 7), one
+  persistent launch captured in a HIP graph with the autotuner's shape:
+  sampled streams word by word, every stream's final position;
+- 4096 streams x 2^18 normals reduced in-kernel to sums of z and z^2: every
+  stream within the stated bound, and the variates of sampled streams within
+  4 ulp through the unfused path.
+"""
+import hashlib
+import os
+
+import numpy as np
+import pytest
+
+from gpu_helpers import needs_gpu, ulp32_error
+from oracle import oracle as O
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+torch = pytest.importorskip("torch")
+
+from paper_1108_0486_amd import workloads as W  # noqa: E402
+from paper_1108_0486_amd.batch import Batch  # noqa: E402
+from paper_1108_0486_amd.streams import XorgensStreams, as_u32  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _fill_view(flat: np.ndarray, count: int, n: int, k0: int, k1: int) -> np.ndarray:
+    """[k1 - k0, n] per-stream view of a bulk-fill output (n a multiple of 64)."""
+    assert n % 64 == 0
+    return flat.reshape(n // 64, count, 64)[:, k0:k1, :].transpose(1, 0, 2).reshape(k1 - k0, n)
+
+
+def test_single_stream_seed42():
+    gs = XorgensStreams(1, seed=W.SEED)
+    out = as_u32(gs.u32(W.SINGLE_N))[0]
+    ref = O.OracleStreams(W.SEED, 1)
+    assert (out == ref.u32(W.SINGLE_N)[0]).all()
+    lines = dict(l.split(" ", 1) for l in open(os.path.join(GOLDEN, "single_stream_seed42_2p20.txt"))
+                 if not l.startswith("#"))
+    assert hashlib.sha256(out.tobytes()).hexdigest() == lines["sha256_le_u32"].strip()
+    ring, weyl, pos = gs.host_state()
+    assert int(weyl[0]) == int(lines["final_weyl"], 16) and int(pos[0]) == W.SINGLE_N
+
+
+def test_bulk_fill_layout_every_stream():
+    """The benchmark's two launches (xg_fill_u32, then xg_fill_f32, default
+    launch shape) against the oracle, every word."""
+    S, N = W.BULK_STREAMS, W.BULK_N
+    gs = XorgensStreams(S, seed=W.SEED)
+    u = as_u32(gs.fill_u32(N))
+    f = gs.fill_f32(N).cpu().numpy()
+    torch.cuda.synchronize()
+    step = 128
+    for k0 in range(0, S, step):
+        ref = O.OracleStreams(W.SEED, step, first=k0)
+        assert (_fill_view(u, S, N, k0, k0 + step) == ref.u32(N)).all(), k0
+        assert (_fill_view(f, S, N, k0, k0 + step) == ref.f32(N)).all(), k0
+        ring, weyl, pos = gs.host_state(list(range(k0, k0 + step)))
+        assert (ring == ref.ring).all() and (weyl == ref.weyl).all() and (pos == ref.pos).all()
+
+
+def test_bulk_stream_major_every_stream():
+    S, N = W.BULK_STREAMS, W.BULK_N
+    gs = XorgensStreams(S, seed=W.SEED)
+    u = as_u32(gs.u32(N))
+    digests = dict(l.split()[1:] for l in open(os.path.join(GOLDEN, "bulk_1024x2p20_samples.txt"))
+                   if l.startswith("stream"))
+    for i, d in digests.items():
+        assert hashlib.sha256(u[int(i)].tobytes()).hexdigest() == d, i
+    f = gs.f32(N).cpu().numpy()
+    step = 128
+    for k0 in range(0, S, step):
+        ref = O.OracleStreams(W.SEED, step, first=k0)
+        assert (u[k0:k0 + step] == ref.u32(N)).all(), k0
+        assert (f[k0:k0 + step] == ref.f32(N)).all(), k0
+
+
+def test_ragged_batch_full_size_graph():
+    lengths = W.ragged_lengths()
+    off = W.csr_offsets(lengths)
+    total = int(off[-1])
+    S = len(lengths)
+    reqs = [(i, int(lengths[i]), int(off[i]), 0) for i in range(S)]
+    gs = XorgensStreams(S, seed=W.SEED)
+    b = Batch(gs, reqs, total)
+    best, recs = b.autotune(reps=1)
+    g = b.capture_graph(tune=best)
+    g.replay()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    _, _, pos = gs.host_state()
+    assert (pos == lengths).all()
+    rng = np.random.default_rng(0)
+    sample = sorted(set(rng.choice(S, size=192, replace=False).tolist()
+                        + [int(np.argmax(lengths)), int(np.argmin(lengths)), 0, S - 1]))
+    ref = O.OracleStreams.from_state(*[np.stack(a) for a in zip(*[
+        (r.ring[0], r.weyl[0], r.pos[0]) for r in (O.OracleStreams(W.SEED + i, 1) for i in sample)])])
+    for j, i in enumerate(sample):
+        n = int(lengths[i])
+        got = as_u32(b.out[int(off[i]):int(off[i]) + n])
+        one = ref.subset([j])
+        assert (got == one.u32(n)[0]).all(), i
+    del recs
+
+
+def test_fused_moments_full_size():
+    S, N = W.FUSED_STREAMS, W.FUSED_N
+    gs = XorgensStreams(S, seed=W.SEED)
+    saved = gs.checkpoint()
+    m = gs.moments(N).cpu().numpy().astype(np.float64)
+    ref = O.OracleStreams(W.SEED, S)
+    mref = ref.moments(N)
+    tau = 27 * 2.0**-24
+    err1 = np.abs(m[:, 0] - mref[:, 0]) / mref[:, 2]
+    err2 = np.abs(m[:, 1] - mref[:, 1]) / mref[:, 1]
+    assert err1.max() <= tau, err1.max()
+    assert err2.max() <= tau, err2.max()
+    ring, weyl, pos = gs.host_state()
+    assert (pos == ref.pos).all() and (ring == ref.ring).all()
+    # the same variates through the unfused path, for a sample of streams
+    gs.restore(saved)
+    first, count = 1000, 64
+    z = gs.normal(N, first=first, count=count).cpu().numpy()
+    zr = O.OracleStreams(W.SEED, count, first=first).normal(N)
+    assert ulp32_error(z, zr).max() <= 4.0
+    print("moments: max rel err sum z %.3g, sum z^2 %.3g (bound %.3g)" % (err1.max(), err2.max(), tau))

@@ -88,18 +88,58 @@ def test_sequential_calls_mixed_types():
         _assert_state(gs, ref)
 
 
-@pytest.mark.parametrize("wpb", [1, 2, 4, 8, 16])
-@pytest.mark.parametrize("unroll", [1, 2, 4, 8])
-def test_plain_shapes_identical(wpb, unroll):
-    n = 64 * 19 + 37
+PLAIN_SHAPES = [(w, u, 1) for w in (1, 2, 4, 8, 16) for u in (1, 2, 4, 8)] + \
+               [(w, u, 4) for w in (1, 2, 4, 8, 16) for u in (4, 8)]
+
+
+@pytest.mark.parametrize("wpb,unroll,store_words", PLAIN_SHAPES)
+def test_plain_shapes_identical(wpb, unroll, store_words):
+    n = 64 * 37 + 37
     gs = XorgensStreams(37, seed=3)
-    gs.set_plain_tune(wpb, unroll)
-    assert gs.plain_tune() == (wpb, unroll)
+    gs.set_plain_tune(wpb, unroll, store_words)
+    assert gs.plain_tune() == (wpb, unroll, store_words)
     ref = O.OracleStreams(3, 37)
     assert (as_u32(gs.u32(n)) == ref.u32(n)).all()
+    assert (gs.f32(n).cpu().numpy() == ref.f32(n)).all()
     z = gs.normal(2 * 64 * 9 + 77).cpu().numpy()
     assert ulp32_error(z, ref.normal(2 * 64 * 9 + 77)).max() <= 4.0
     _assert_state(gs, ref)
+
+
+@pytest.mark.parametrize("n", [256 * 5, 256 * 5 + 64, 256 * 9 + 3])
+def test_wide_stores_with_unaligned_output(n):
+    """16-byte stores are used only while the output is 16-byte aligned; a
+    4-byte-aligned output takes the 4-byte path with the same bits."""
+    gs = XorgensStreams(6, seed=21)
+    gs.set_plain_tune(1, 8, 4)
+    ref = O.OracleStreams(21, 6)
+    buf = torch.zeros(6 * n + 1, dtype=torch.int32, device="cuda")
+    out = buf[1:].view(6, n)
+    gs.u32(n, out=out)
+    assert (as_u32(out) == ref.u32(n)).all() and buf[0].item() == 0
+    _assert_state(gs, ref)
+
+
+def test_default_plain_shape():
+    gs = XorgensStreams(2, seed=1)
+    assert gs.plain_tune() == (0, 8, 4)
+    gs.set_plain_tune(0, 4, 1)
+    assert gs.plain_tune() == (0, 4, 1)
+
+
+@pytest.mark.parametrize("count", [1, 255, 256, 511, 512, 1023, 1024, 1025, 2049])
+def test_auto_shape_counts(count):
+    """The automatic waves-per-block choice around the compute-unit multiples
+    gives the same bits (and touches only the selected streams)."""
+    gs = XorgensStreams(count + 2, seed=13)
+    ref = O.OracleStreams(13, count + 2)
+    sub = ref.subset(range(1, 1 + count))
+    n = 130
+    assert (as_u32(gs.u32(n, first=1, count=count)) == sub.u32(n)).all()
+    flat = as_u32(gs.fill_u32(n, first=1, count=count))
+    assert (flat[xg.fill_index(count, n)] == sub.u32(n)).all()
+    _, _, pos = gs.host_state()
+    assert pos[0] == 0 and pos[-1] == 0 and (pos[1:-1] == 2 * n).all()
 
 
 def test_split_calls_equal_one_call():
@@ -200,3 +240,38 @@ def test_streams_are_independent_of_neighbours():
     a = XorgensStreams(100, seed=500)
     b = XorgensStreams(1, seed=537)
     assert (as_u32(a.u32(3000, first=37, count=1)) == as_u32(b.u32(3000))).all()
+
+
+@pytest.mark.parametrize("count,n", [(1, 1), (5, 64), (7, 65), (33, 1000), (67, 64 * 19 + 37), (3, 8 * 64)])
+def test_fill_layout_matches_oracle(count, n):
+    gs = XorgensStreams(70, seed=55)
+    ref = O.OracleStreams(55, 70)
+    sub = ref.subset(range(2, 2 + count))
+    flat = as_u32(gs.fill_u32(n, first=2, count=count))
+    assert flat.shape == (count * n,)
+    want = sub.u32(n)
+    assert (flat[xg.fill_index(count, n)] == want).all()
+    f = gs.fill_f32(n, first=2, count=count).cpu().numpy()
+    assert (f[xg.fill_index(count, n)] == sub.f32(n)).all()
+    ring, weyl, pos = gs.host_state(list(range(2, 2 + count)))
+    assert (ring == sub.ring).all() and (weyl == sub.weyl).all() and (pos == sub.pos).all()
+
+
+@pytest.mark.parametrize("wpb,unroll", [(1, 1), (2, 2), (4, 4), (16, 8), (1, 8)])
+def test_fill_shapes_identical(wpb, unroll):
+    gs = XorgensStreams(40, seed=8)
+    gs.set_plain_tune(wpb, unroll, 1)
+    ref = O.OracleStreams(8, 40)
+    n = 64 * 21 + 5
+    flat = as_u32(gs.fill_u32(n))
+    assert (flat[xg.fill_index(40, n)] == ref.u32(n)).all()
+
+
+def test_fill_unaligned_buffer():
+    gs = XorgensStreams(9, seed=2)
+    ref = O.OracleStreams(2, 9)
+    n = 300
+    buf = torch.zeros(9 * n + 1, dtype=torch.int32, device="cuda")
+    gs.fill_u32(n, out=buf[1:])
+    flat = as_u32(buf)[1:]
+    assert (flat[xg.fill_index(9, n)] == ref.u32(n)).all() and buf[0].item() == 0

@@ -465,6 +465,7 @@ def test_normals_pairing_and_moments():
     mom = st.copy().moments(1001)
     assert np.allclose(mom[:, 0], z.sum(axis=1), rtol=0, atol=1e-9)
     assert np.allclose(mom[:, 1], (z * z).sum(axis=1), rtol=1e-14)
+    assert np.allclose(mom[:, 2], np.abs(z).sum(axis=1), rtol=1e-14)
 
 
 def test_normals_are_standard():
