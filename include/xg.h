@@ -242,6 +242,84 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
                             float *times_ms, uint32_t max_times, uint32_t *num_times,
                             void *stream);
 
+/* ---- serving: continuous batching over device-resident streams ------------- */
+
+/* A request server over the streams of one handle.  Requests (stream, n,
+ * dtype) are submitted from the host; xg_server_poll reaps finished batches,
+ * admits pending requests in arrival order as output memory and streams free
+ * up, and launches each admitted set as one persistent batched launch
+ * (xg_generate_batch's kernel) on one of num_lanes HIP streams, so batches that
+ * arrive while others run overlap on the device.  A request reads its stream
+ * from the position the stream has when it is admitted; requests on one stream
+ * are served in submission order and never run in two batches at once, so a
+ * request's values equal those of the same request run alone from that
+ * position.  Outputs live in a caller-provided device pool until released.
+ * Not thread-safe: one host thread drives a server. */
+typedef struct xg_server xg_server;
+
+typedef struct {
+    uint32_t num_lanes;   /* HIP streams, each with at most one batch in flight: 1 .. 8 */
+    uint32_t max_batch;   /* requests per batch: 1 .. 65536 */
+    xg_tune tune;         /* batch launch shape; all zero selects the default */
+} xg_server_config;
+
+typedef struct {
+    uint64_t id;          /* the caller's request id */
+    uint64_t stream;
+    uint64_t n;
+    uint64_t out_offset;  /* element offset of the output in the pool */
+    uint64_t start_pos;   /* stream position the request read from */
+    uint64_t t_submit_ns; /* host steady-clock times (ns) of submission, launch and */
+    uint64_t t_launch_ns; /* of the poll that saw the batch finish */
+    uint64_t t_done_ns;
+    uint32_t dtype;
+    uint32_t lane;
+} xg_completion;
+
+typedef struct {
+    uint64_t submitted, completed, batches, admitted;
+    uint64_t max_lanes_busy;     /* most batches observed in flight at once */
+    uint64_t max_batch_seen;     /* most requests in one batch */
+    uint64_t pool_high_water;    /* most pool elements in use at once */
+    uint64_t admission_waits;    /* polls where the oldest request waited for pool memory */
+} xg_server_stats;
+
+/* Device bytes of request tables and workspaces a server needs. */
+size_t xg_server_device_bytes(const xg_server_config *cfg);
+
+/* Creates a server.  d_pool (pool_elems 4-byte elements, 256-byte aligned)
+ * holds request outputs; d_tables (xg_server_device_bytes(cfg) bytes,
+ * 256-byte aligned) holds request tables.  Both stay owned by the caller.
+ * Creates num_lanes HIP streams (default priority) and pinned host staging;
+ * synchronises the device once and reads the streams' positions.
+ * Errors: XG_EINVAL, XG_ERANGE (a buffer too small), XG_EALIGN, XG_ENOMEM,
+ * XG_EHIP. */
+xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config *cfg,
+                           void *d_pool, uint64_t pool_elems, void *d_tables, size_t tables_bytes);
+
+/* Queues a request of n >= 1 values.  Errors: XG_EINVAL (NULL server, n == 0,
+ * bad dtype), XG_ERANGE (stream out of range, or n larger than the whole
+ * pool: such a request could never be admitted). */
+xg_status xg_server_submit(xg_server *srv, uint64_t id, uint64_t stream, uint64_t n, uint32_t dtype);
+
+/* Makes progress without blocking: reaps finished batches, admits and
+ * launches, and returns up to max_out completions (more wait for the next
+ * poll).  Errors: XG_EINVAL, XG_EHIP. */
+xg_status xg_server_poll(xg_server *srv, xg_completion *out, uint32_t max_out, uint32_t *num_out);
+
+/* Returns a completed request's output to the pool.  Errors: XG_EINVAL
+ * (unknown or unfinished id). */
+xg_status xg_server_release(xg_server *srv, uint64_t id);
+
+/* Requests submitted but not yet completed. */
+uint64_t xg_server_outstanding(const xg_server *srv);
+
+xg_status xg_server_get_stats(const xg_server *srv, xg_server_stats *out);
+
+/* Waits for in-flight batches, then frees the server's host resources and
+ * streams (never the caller's buffers).  NULL is accepted. */
+void xg_server_destroy(xg_server *srv);
+
 /* Human-readable name of a status. */
 const char *xg_strerror(xg_status status);
 

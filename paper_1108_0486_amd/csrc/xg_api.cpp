@@ -13,14 +13,6 @@
 #include "xg.h"
 #include "xg_internal.h"
 
-struct xg_ctx {
-  uint32_t *d_state;
-  uint64_t num_streams;
-  int device;
-  int num_cus;
-  xg::Shape plain;
-};
-
 namespace {
 
 constexpr uint64_t kMaxStreams = 0xFFFFFFFFull;

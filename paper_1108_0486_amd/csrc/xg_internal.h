@@ -48,3 +48,12 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
                         uint32_t *out, uint64_t out_elems, uint32_t *work, hipStream_t stream);
 
 }  // namespace xg
+
+// The handle behind xg_ctx (include/xg.h).
+struct xg_ctx {
+  uint32_t *d_state;
+  uint64_t num_streams;
+  int device;
+  int num_cus;
+  xg::Shape plain;
+};

@@ -1,0 +1,401 @@
+// Request server of libxg (include/xg.h, "serving"): continuous batching of
+// (stream, n, dtype) requests over device-resident streams.
+//
+// One host thread drives it through xg_server_poll:
+//   reap    - a lane whose event has fired has finished its batch: its
+//             requests complete and their streams become free;
+//   admit   - pending requests are taken in submission order; a request waits
+//             while its stream is inside a batch still in flight, and admission
+//             stops at the first request whose output does not fit in the pool
+//             (memory admission, no overtaking);
+//   launch  - the admitted set is planned (same-stream requests grouped in
+//             order, largest groups first), copied to the lane's device table and
+//             served by one persistent batched launch on the lane's HIP stream.
+// Lanes are independent HIP streams, so a batch admitted while others run
+// overlaps with them on the device.  A stream is never in two in-flight
+// batches, so every request reads the exact positions it would read alone.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdint>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <new>
+#include <unordered_map>
+#include <vector>
+
+#include "xg.h"
+#include "xg_internal.h"
+
+namespace {
+
+constexpr uint64_t kAlignElems = 64;  // pool allocations in 256-byte units
+constexpr size_t kAlignBytes = 256;
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+uint64_t words_consumed(uint64_t n, uint32_t dtype) { return dtype == XG_NORMAL ? n + (n & 1) : n; }
+
+// First-fit allocator over [0, capacity) elements with coalescing frees.
+class Pool {
+ public:
+  explicit Pool(uint64_t capacity) : capacity_(capacity) {
+    if (capacity_) free_[0] = capacity_;
+  }
+  // Returns the offset, or UINT64_MAX if no free range fits.
+  uint64_t alloc(uint64_t n) {
+    const uint64_t need = (n + kAlignElems - 1) / kAlignElems * kAlignElems;
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= need) {
+        const uint64_t off = it->first, len = it->second;
+        free_.erase(it);
+        if (len > need) free_[off + need] = len - need;
+        used_ += need;
+        return off;
+      }
+    }
+    return UINT64_MAX;
+  }
+  void release(uint64_t off, uint64_t n) {
+    const uint64_t len = (n + kAlignElems - 1) / kAlignElems * kAlignElems;
+    used_ -= len;
+    auto next = free_.lower_bound(off);
+    uint64_t start = off, size = len;
+    if (next != free_.begin()) {
+      auto prev = std::prev(next);
+      if (prev->first + prev->second == start) {
+        start = prev->first;
+        size += prev->second;
+        free_.erase(prev);
+      }
+    }
+    if (next != free_.end() && start + size == next->first) {
+      size += next->second;
+      free_.erase(next);
+    }
+    free_[start] = size;
+  }
+  uint64_t used() const { return used_; }
+
+ private:
+  uint64_t capacity_;
+  uint64_t used_ = 0;
+  std::map<uint64_t, uint64_t> free_;  // offset -> length
+};
+
+struct Pending {
+  uint64_t id, stream, n;
+  uint32_t dtype;
+  uint64_t t_submit;
+};
+
+struct Lane {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  xg_request *h_reqs = nullptr;  // pinned staging
+  uint32_t *h_groups = nullptr;
+  xg_request *h_scratch = nullptr;
+  xg_request *d_reqs = nullptr;  // in the caller's table buffer
+  uint32_t *d_groups = nullptr;
+  uint32_t *d_work = nullptr;
+  std::vector<xg_completion> reqs;
+  uint64_t t_launch = 0;
+};
+
+struct TableLayout {
+  size_t reqs, groups, work, per_lane;
+};
+
+TableLayout table_layout(uint32_t max_batch) {
+  TableLayout t;
+  t.reqs = round_up((size_t)max_batch * sizeof(xg_request), kAlignBytes);
+  t.groups = round_up(((size_t)max_batch + 1) * sizeof(uint32_t), kAlignBytes);
+  t.work = round_up(xg_batch_workspace_bytes(), kAlignBytes);
+  t.per_lane = t.reqs + t.groups + t.work;
+  return t;
+}
+
+bool config_valid(const xg_server_config *c) {
+  return c && c->num_lanes >= 1 && c->num_lanes <= 8 && c->max_batch >= 1 && c->max_batch <= 65536;
+}
+
+}  // namespace
+
+struct xg_server {
+  xg_ctx *ctx = nullptr;
+  uint32_t *d_pool = nullptr;
+  uint64_t pool_elems = 0;
+  uint32_t max_batch = 0;
+  xg_tune tune{};
+  bool default_tune = true;
+  Pool pool{0};
+  std::vector<Lane> lanes;
+  std::deque<Pending> pending;
+  std::vector<uint8_t> busy_stream;   // stream is inside an in-flight batch
+  std::vector<uint64_t> pos;          // each stream's position after all admitted work
+  std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> finished;  // id -> (offset, n)
+  std::deque<xg_completion> ready;    // completions not yet handed out
+  xg_server_stats stats{};
+  uint64_t outstanding = 0;
+};
+
+namespace {
+
+void destroy_lanes(xg_server *s) {
+  for (Lane &l : s->lanes) {
+    if (l.stream) (void)hipStreamSynchronize(l.stream);
+    if (l.done) (void)hipEventDestroy(l.done);
+    if (l.stream) (void)hipStreamDestroy(l.stream);
+    if (l.h_reqs) (void)hipHostFree(l.h_reqs);
+    if (l.h_groups) (void)hipHostFree(l.h_groups);
+    delete[] l.h_scratch;
+  }
+  s->lanes.clear();
+}
+
+// Reaps lanes whose batch has finished.
+xg_status reap(xg_server *s) {
+  for (uint32_t li = 0; li < s->lanes.size(); ++li) {
+    Lane &l = s->lanes[li];
+    if (!l.busy) continue;
+    const hipError_t q = hipEventQuery(l.done);
+    if (q == hipErrorNotReady) continue;
+    if (q != hipSuccess) return XG_EHIP;
+    const uint64_t t = now_ns();
+    for (xg_completion &c : l.reqs) {
+      c.t_done_ns = t;
+      s->busy_stream[c.stream] = 0;
+      s->finished[c.id] = {c.out_offset, c.n};
+      s->ready.push_back(c);
+      ++s->stats.completed;
+      --s->outstanding;
+    }
+    l.reqs.clear();
+    l.busy = false;
+  }
+  return XG_OK;
+}
+
+// Admits pending requests into lane l and launches them; returns the number
+// admitted (0: nothing to do).
+xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
+  Lane &l = s->lanes[li];
+  *admitted = 0;
+  std::vector<uint64_t> in_this_batch;
+  uint32_t k = 0;
+  bool waited = false;
+  for (auto it = s->pending.begin(); it != s->pending.end() && k < s->max_batch;) {
+    const Pending &p = *it;
+    if (s->busy_stream[p.stream] == 1) {  // in flight in another lane: keep order, wait
+      ++it;
+      continue;
+    }
+    const uint64_t off = s->pool.alloc(p.n);
+    if (off == UINT64_MAX) {
+      waited = true;
+      break;
+    }
+    if (s->busy_stream[p.stream] == 0) {
+      s->busy_stream[p.stream] = 2;  // joins this batch
+      in_this_batch.push_back(p.stream);
+    }
+    xg_completion c{};
+    c.id = p.id;
+    c.stream = p.stream;
+    c.n = p.n;
+    c.dtype = p.dtype;
+    c.out_offset = off;
+    c.start_pos = s->pos[p.stream];
+    c.t_submit_ns = p.t_submit;
+    c.lane = li;
+    s->pos[p.stream] += words_consumed(p.n, p.dtype);
+    l.h_scratch[k] = xg_request{p.stream, p.n, off, p.dtype, 0};
+    l.reqs.push_back(c);
+    ++k;
+    it = s->pending.erase(it);
+  }
+  if (waited) ++s->stats.admission_waits;
+  for (uint64_t st : in_this_batch) s->busy_stream[st] = 1;
+  if (k == 0) return XG_OK;
+  uint32_t num_groups = 0;
+  xg_status st = xg_plan_batch(l.h_scratch, k, s->ctx->num_streams, s->pool_elems, l.h_reqs, l.h_groups,
+                               &num_groups);
+  if (st != XG_OK) return st;
+  if (hipMemcpyAsync(l.d_reqs, l.h_reqs, (size_t)k * sizeof(xg_request), hipMemcpyHostToDevice, l.stream) !=
+          hipSuccess ||
+      hipMemcpyAsync(l.d_groups, l.h_groups, ((size_t)num_groups + 1) * sizeof(uint32_t),
+                     hipMemcpyHostToDevice, l.stream) != hipSuccess)
+    return XG_EHIP;
+  st = xg_generate_batch(s->ctx, l.d_reqs, k, l.d_groups, num_groups, s->d_pool, s->pool_elems,
+                         s->default_tune ? nullptr : &s->tune, l.d_work, l.stream);
+  if (st != XG_OK) return st;
+  if (hipEventRecord(l.done, l.stream) != hipSuccess) return XG_EHIP;
+  l.t_launch = now_ns();
+  for (xg_completion &c : l.reqs) c.t_launch_ns = l.t_launch;
+  l.busy = true;
+  *admitted = k;
+  ++s->stats.batches;
+  s->stats.admitted += k;
+  s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, k);
+  s->stats.pool_high_water = std::max<uint64_t>(s->stats.pool_high_water, s->pool.used());
+  uint64_t busy = 0;
+  for (const Lane &x : s->lanes) busy += x.busy;
+  s->stats.max_lanes_busy = std::max<uint64_t>(s->stats.max_lanes_busy, busy);
+  return XG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t xg_server_device_bytes(const xg_server_config *cfg) {
+  if (!config_valid(cfg)) return 0;
+  return table_layout(cfg->max_batch).per_lane * cfg->num_lanes;
+}
+
+xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config *cfg, void *d_pool,
+                           uint64_t pool_elems, void *d_tables, size_t tables_bytes) {
+  if (!out) return XG_EINVAL;
+  *out = nullptr;
+  if (!ctx || !config_valid(cfg) || !d_pool || !d_tables || pool_elems == 0) return XG_EINVAL;
+  if (tables_bytes < xg_server_device_bytes(cfg)) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(d_pool) % kAlignBytes || reinterpret_cast<uintptr_t>(d_tables) % kAlignBytes)
+    return XG_EALIGN;
+  const bool default_tune = cfg->tune.waves_per_block == 0 && cfg->tune.unroll == 0 &&
+                            cfg->tune.blocks_per_cu == 0 && cfg->tune.store_words == 0;
+  if (!default_tune) {
+    xg::Shape sh{cfg->tune.waves_per_block, cfg->tune.unroll, cfg->tune.blocks_per_cu,
+                 cfg->tune.store_words ? cfg->tune.store_words : (cfg->tune.unroll >= 4 ? 4u : 1u)};
+    if (!xg::shape_valid(sh)) return XG_EINVAL;
+  }
+  xg_server *s = new (std::nothrow) xg_server;
+  if (!s) return XG_ENOMEM;
+  try {
+    s->ctx = ctx;
+    s->d_pool = static_cast<uint32_t *>(d_pool);
+    s->pool_elems = pool_elems;
+    s->max_batch = cfg->max_batch;
+    s->tune = cfg->tune;
+    s->default_tune = default_tune;
+    s->pool = Pool(pool_elems);
+    s->busy_stream.assign(ctx->num_streams, 0);
+    s->pos.assign(ctx->num_streams, 0);
+  } catch (const std::bad_alloc &) {
+    delete s;
+    return XG_ENOMEM;
+  }
+  // Positions of every stream (and completion of any prior work on the state).
+  if (hipDeviceSynchronize() != hipSuccess) {
+    delete s;
+    return XG_EHIP;
+  }
+  {
+    std::vector<uint32_t> state;
+    try {
+      state.resize((size_t)ctx->num_streams * XG_STATE_WORDS);
+    } catch (const std::bad_alloc &) {
+      delete s;
+      return XG_ENOMEM;
+    }
+    if (hipMemcpy(state.data(), ctx->d_state, state.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+      delete s;
+      return XG_EHIP;
+    }
+    for (uint64_t i = 0; i < ctx->num_streams; ++i) {
+      const uint32_t *w = state.data() + i * XG_STATE_WORDS;
+      s->pos[i] = (uint64_t)w[130] | ((uint64_t)w[131] << 32);
+    }
+  }
+  const TableLayout tl = table_layout(cfg->max_batch);
+  s->lanes.resize(cfg->num_lanes);
+  char *base = static_cast<char *>(d_tables);
+  for (uint32_t li = 0; li < cfg->num_lanes; ++li) {
+    Lane &l = s->lanes[li];
+    char *lb = base + li * tl.per_lane;
+    l.d_reqs = reinterpret_cast<xg_request *>(lb);
+    l.d_groups = reinterpret_cast<uint32_t *>(lb + tl.reqs);
+    l.d_work = reinterpret_cast<uint32_t *>(lb + tl.reqs + tl.groups);
+    l.h_scratch = new (std::nothrow) xg_request[cfg->max_batch];
+    if (!l.h_scratch || hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&l.h_reqs), (size_t)cfg->max_batch * sizeof(xg_request),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void **>(&l.h_groups), ((size_t)cfg->max_batch + 1) * sizeof(uint32_t),
+                      hipHostMallocDefault) != hipSuccess) {
+      destroy_lanes(s);
+      delete s;
+      return XG_EHIP;
+    }
+    l.reqs.reserve(cfg->max_batch);
+  }
+  *out = s;
+  return XG_OK;
+}
+
+xg_status xg_server_submit(xg_server *s, uint64_t id, uint64_t stream, uint64_t n, uint32_t dtype) {
+  if (!s || n == 0 || dtype > XG_NORMAL) return XG_EINVAL;
+  if (stream >= s->ctx->num_streams || n > s->pool_elems) return XG_ERANGE;
+  try {
+    s->pending.push_back(Pending{id, stream, n, dtype, now_ns()});
+  } catch (const std::bad_alloc &) {
+    return XG_ENOMEM;
+  }
+  ++s->stats.submitted;
+  ++s->outstanding;
+  return XG_OK;
+}
+
+xg_status xg_server_poll(xg_server *s, xg_completion *out, uint32_t max_out, uint32_t *num_out) {
+  if (!s || !num_out || (max_out && !out)) return XG_EINVAL;
+  *num_out = 0;
+  xg_status st = reap(s);
+  if (st != XG_OK) return st;
+  for (uint32_t li = 0; li < s->lanes.size() && !s->pending.empty(); ++li) {
+    if (s->lanes[li].busy) continue;
+    uint32_t admitted = 0;
+    st = admit_and_launch(s, li, &admitted);
+    if (st != XG_OK) return st;
+    if (admitted == 0) break;  // the oldest request waits for memory or its stream
+  }
+  uint32_t k = 0;
+  while (k < max_out && !s->ready.empty()) {
+    out[k++] = s->ready.front();
+    s->ready.pop_front();
+  }
+  *num_out = k;
+  return XG_OK;
+}
+
+xg_status xg_server_release(xg_server *s, uint64_t id) {
+  if (!s) return XG_EINVAL;
+  auto it = s->finished.find(id);
+  if (it == s->finished.end()) return XG_EINVAL;
+  s->pool.release(it->second.first, it->second.second);
+  s->finished.erase(it);
+  return XG_OK;
+}
+
+uint64_t xg_server_outstanding(const xg_server *s) { return s ? s->outstanding : 0; }
+
+xg_status xg_server_get_stats(const xg_server *s, xg_server_stats *out) {
+  if (!s || !out) return XG_EINVAL;
+  *out = s->stats;
+  return XG_OK;
+}
+
+void xg_server_destroy(xg_server *s) {
+  if (!s) return;
+  destroy_lanes(s);
+  delete s;
+}
+
+}  // extern "C"

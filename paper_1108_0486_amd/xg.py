@@ -54,6 +54,25 @@ class xg_tune(ctypes.Structure):
         return (self.waves_per_block, self.unroll, self.blocks_per_cu, self.store_words)
 
 
+class xg_server_config(ctypes.Structure):
+    _fields_ = [("num_lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("tune", xg_tune)]
+
+
+class xg_completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("stream", ctypes.c_uint64), ("n", ctypes.c_uint64),
+                ("out_offset", ctypes.c_uint64), ("start_pos", ctypes.c_uint64),
+                ("t_submit_ns", ctypes.c_uint64), ("t_launch_ns", ctypes.c_uint64),
+                ("t_done_ns", ctypes.c_uint64), ("dtype", ctypes.c_uint32), ("lane", ctypes.c_uint32)]
+
+
+class xg_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "batches", "admitted", "max_lanes_busy",
+                                              "max_batch_seen", "pool_high_water", "admission_waits")]
+
+    def as_dict(self):
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -89,6 +108,14 @@ def lib() -> ctypes.CDLL:
         "xg_autotune_batch": (st, [vp, vp, u32, vp, u32, vp, u64, vp, vp, i32, P(xg_tune),
                                    P(ctypes.c_float), u32, P(u32), vp]),
         "xg_strerror": (ctypes.c_char_p, [st]),
+        "xg_server_device_bytes": (ctypes.c_size_t, [P(xg_server_config)]),
+        "xg_server_create": (st, [P(vp), vp, P(xg_server_config), vp, u64, vp, ctypes.c_size_t]),
+        "xg_server_submit": (st, [vp, u64, u64, u64, u32]),
+        "xg_server_poll": (st, [vp, P(xg_completion), u32, P(u32)]),
+        "xg_server_release": (st, [vp, u64]),
+        "xg_server_outstanding": (u64, [vp]),
+        "xg_server_get_stats": (st, [vp, P(xg_server_stats)]),
+        "xg_server_destroy": (None, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -225,3 +252,48 @@ def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups
     recs = [(int(times[5 * i]), int(times[5 * i + 1]), int(times[5 * i + 2]), int(times[5 * i + 4]),
              float(times[5 * i + 3])) for i in range(nt.value)]
     return best.as_tuple(), recs
+
+
+# ---- serving -----------------------------------------------------------------
+
+def xg_server_device_bytes(num_lanes: int, max_batch: int) -> int:
+    cfg = xg_server_config(num_lanes, max_batch, xg_tune())
+    return int(lib().xg_server_device_bytes(ctypes.byref(cfg)))
+
+
+def xg_server_create(ctx, num_lanes: int, max_batch: int, tune, d_pool: int, pool_elems: int,
+                     d_tables: int, tables_bytes: int):
+    cfg = xg_server_config(num_lanes, max_batch, xg_tune() if tune is None else xg_tune.of(tune))
+    srv = ctypes.c_void_p()
+    _check(lib().xg_server_create(ctypes.byref(srv), ctx, ctypes.byref(cfg), d_pool, pool_elems, d_tables,
+                                  tables_bytes), "xg_server_create")
+    return srv
+
+
+def xg_server_submit(srv, rid: int, stream: int, n: int, dtype: int) -> None:
+    _check(lib().xg_server_submit(srv, rid, stream, n, dtype), "xg_server_submit")
+
+
+def xg_server_poll(srv, buf, max_out: int) -> int:
+    """Fills the ctypes array `buf` (xg_completion * max_out); returns the count."""
+    k = ctypes.c_uint32()
+    _check(lib().xg_server_poll(srv, buf, max_out, ctypes.byref(k)), "xg_server_poll")
+    return k.value
+
+
+def xg_server_release(srv, rid: int) -> None:
+    _check(lib().xg_server_release(srv, rid), "xg_server_release")
+
+
+def xg_server_outstanding(srv) -> int:
+    return int(lib().xg_server_outstanding(srv))
+
+
+def xg_server_get_stats(srv) -> dict:
+    st = xg_server_stats()
+    _check(lib().xg_server_get_stats(srv, ctypes.byref(st)), "xg_server_get_stats")
+    return st.as_dict()
+
+
+def xg_server_destroy(srv) -> None:
+    lib().xg_server_destroy(srv)

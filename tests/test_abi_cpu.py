@@ -102,3 +102,18 @@ def test_fill_index_is_a_permutation(count, n):
         for c in range(n // 64):
             assert idx[k, 64 * c] == (c * count + k) * 64
             assert (np.diff(idx[k, 64 * c:64 * c + 64]) == 1).all()
+
+
+def test_server_abi_without_gpu():
+    L = xg.lib()
+    assert xg.xg_server_device_bytes(4, 1024) > 4 * 1024 * 32
+    assert xg.xg_server_device_bytes(0, 1024) == 0
+    assert xg.xg_server_device_bytes(9, 1024) == 0
+    assert L.xg_server_submit(None, 0, 0, 1, 0) == xg.XG_EINVAL
+    k = ctypes.c_uint32()
+    assert L.xg_server_poll(None, None, 0, ctypes.byref(k)) == xg.XG_EINVAL
+    assert L.xg_server_release(None, 0) == xg.XG_EINVAL
+    assert L.xg_server_outstanding(None) == 0
+    srv = ctypes.c_void_p()
+    assert L.xg_server_create(ctypes.byref(srv), None, None, None, 0, None, 0) == xg.XG_EINVAL
+    L.xg_server_destroy(None)

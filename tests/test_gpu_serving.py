@@ -1,0 +1,131 @@
+"""The request server: continuous batching with memory admission and
+per-stream order.  Every request's values equal the oracle's from the
+position it was admitted at, and equal the same request run alone."""
+import numpy as np
+import pytest
+
+from gpu_helpers import needs_gpu, ulp32_error
+from oracle import oracle as O
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+torch = pytest.importorskip("torch")
+
+from paper_1108_0486_amd import xg  # noqa: E402
+from paper_1108_0486_amd import workloads as W  # noqa: E402
+from paper_1108_0486_amd.serve import Server, run_trace, run_trace_plain_fifo  # noqa: E402
+from paper_1108_0486_amd.streams import XorgensStreams, as_u32  # noqa: E402
+
+SEED = 42
+
+
+def _check_against_oracle(done, outputs, num_streams):
+    by_stream = {}
+    for c in done:
+        by_stream.setdefault(c.stream, []).append(c)
+    for s, cs in by_stream.items():
+        cs.sort(key=lambda c: c.start_pos)
+        ref = O.OracleStreams(SEED + s, 1)
+        pos = 0
+        for c in cs:
+            assert c.start_pos == pos, (s, c.id, c.start_pos, pos)   # requests chain on their stream
+            got = outputs[c.id].cpu().numpy()
+            if c.dtype == xg.XG_U32:
+                assert (got.view(np.uint32) == ref.u32(c.n)[0]).all(), c
+            elif c.dtype == xg.XG_F32:
+                assert (got == ref.f32(c.n)[0]).all(), c
+            else:
+                assert ulp32_error(got, ref.normal(c.n)[0]).max() <= 4.0, c
+            pos += c.n + (c.n & 1 if c.dtype == xg.XG_NORMAL else 0)
+
+
+def _dense_trace(num_reqs, num_streams, seed, lo=4, hi=14, rate=50_000.0):
+    trace = W.serving_trace(num_reqs, num_streams=num_streams, rate=rate, seed=seed, lo_exp=lo, hi_exp=hi)
+    # a long request first, so that later arrivals are admitted while it runs
+    trace[0].n = 1 << 20
+    trace[0].dtype = 0
+    return trace
+
+
+def test_serving_matches_oracle_and_overlaps():
+    S = 40                                   # few streams: many same-stream requests
+    gs = XorgensStreams(S, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 22, num_lanes=4, max_batch=32)
+    trace = _dense_trace(300, S, seed=3)
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True)
+    st = summary["server"]
+    assert st["completed"] == 300 and st["submitted"] == 300
+    assert st["max_lanes_busy"] >= 2          # batches overlapped on the device
+    assert st["batches"] > 1 and st["max_batch_seen"] > 1
+    _check_against_oracle(done, outputs, S)
+    # final device positions agree with the host's bookkeeping
+    _, _, pos = gs.host_state()
+    want = np.zeros(S, dtype=np.uint64)
+    for c in done:
+        want[c.stream] = max(want[c.stream], c.start_pos + c.n + (c.n & 1 if c.dtype == 2 else 0))
+    assert (pos == want).all()
+    srv.close()
+
+
+def test_alone_equals_in_the_mix():
+    S = 64
+    gs = XorgensStreams(S, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 22, num_lanes=3, max_batch=16)
+    summary, done, outputs = run_trace(srv, _dense_trace(200, S, seed=9), keep_outputs=True)
+    srv.close()
+    rng = np.random.default_rng(1)
+    for c in [done[i] for i in rng.choice(len(done), size=24, replace=False)]:
+        alone = XorgensStreams(1, seed=SEED + c.stream)
+        if c.start_pos:
+            alone.u32(c.start_pos)           # advance to the admitted position
+        if c.dtype == xg.XG_U32:
+            ref = alone.u32(c.n)[0]
+        elif c.dtype == xg.XG_F32:
+            ref = alone.f32(c.n)[0]
+        else:
+            ref = alone.normal(c.n)[0]
+        assert torch.equal(ref.view(torch.int32), outputs[c.id].view(torch.int32)), c
+
+
+def test_memory_admission_queues_instead_of_failing():
+    S = 30
+    gs = XorgensStreams(S, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 15, num_lanes=2, max_batch=8)   # far less than the trace needs
+    trace = W.serving_trace(120, num_streams=S, rate=1e6, seed=5, lo_exp=10, hi_exp=15)
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True)
+    st = summary["server"]
+    assert st["completed"] == 120
+    assert st["admission_waits"] > 0
+    assert st["pool_high_water"] <= 1 << 15
+    _check_against_oracle(done, outputs, S)
+    srv.close()
+
+
+def test_oversize_and_bad_requests_rejected():
+    gs = XorgensStreams(4, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4)
+    with pytest.raises(xg.XgError) as e:
+        srv.submit(1, 0, (1 << 12) + 1, 0)
+    assert e.value.status == xg.XG_ERANGE
+    with pytest.raises(xg.XgError) as e:
+        srv.submit(2, 4, 10, 0)
+    assert e.value.status == xg.XG_ERANGE
+    with pytest.raises(xg.XgError) as e:
+        srv.submit(3, 0, 0, 0)
+    assert e.value.status == xg.XG_EINVAL
+    with pytest.raises(xg.XgError) as e:
+        srv.submit(4, 0, 10, 3)
+    assert e.value.status == xg.XG_EINVAL
+    with pytest.raises(xg.XgError) as e:
+        srv.release(12345)
+    assert e.value.status == xg.XG_EINVAL
+    assert srv.outstanding == 0
+    srv.close()
+
+
+def test_plain_fifo_baseline_runs():
+    S = 16
+    gs = XorgensStreams(S, seed=SEED)
+    trace = W.serving_trace(50, num_streams=S, rate=20_000.0, seed=2, lo_exp=8, hi_exp=14)
+    summary = run_trace_plain_fifo(gs, trace, max_n=1 << 14)
+    assert summary["requests"] == 50 and summary["p99_ms"] > 0
