@@ -75,6 +75,130 @@ def cpu_baseline(threads: int):
                       "one POSIX thread per share of streams (includes per-slice seeding, %.1f s)" % dt}
 
 
+def extra_ragged_batch(torch, dev):
+    """65536 streams, lengths log-uniform in [2^10, 2^20] (seed 7), uint32, one
+    persistent launch in a HIP graph with the autotuner's shape, against one
+    plain launch per stream on the same GPU."""
+    from paper_1108_0486_amd import workloads as W
+    from paper_1108_0486_amd.batch import Batch
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    lengths = W.ragged_lengths()
+    off = W.csr_offsets(lengths)
+    total = int(off[-1])
+    S = len(lengths)
+    gs = XorgensStreams(S, seed=SEED, device=dev)
+    b = Batch(gs, [(i, int(lengths[i]), int(off[i]), 0) for i in range(S)], total)
+    t0 = time.perf_counter()
+    best, recs = b.autotune(reps=1)
+    tune_s = time.perf_counter() - t0
+    default_ms = [r[4] for r in recs if r[:4] == (4, 8, 8, 4)]
+    g = b.capture_graph(tune=best)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 5
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    e.record()
+    torch.cuda.synchronize()
+    batch_ms = a.elapsed_time(e) / reps
+    # baseline: one plain launch per stream (one wavefront each), in order on one stream
+    out = b.out
+    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    a.record()
+    t0 = time.perf_counter()
+    for i in range(S):
+        gs.u32(int(lengths[i]), first=i, count=1, out=out[int(off[i]):int(off[i + 1])], stream=stream)
+    e.record()
+    torch.cuda.synchronize()
+    plain_wall = time.perf_counter() - t0
+    plain_ms = a.elapsed_time(e)
+    res = {
+        "workload": "65536 streams, n_i = floor(2^(10 + 10 U_i)) (U from seed 7), uint32, CSR offsets",
+        "total_rn": total,
+        "batched_graph_ms": batch_ms,
+        "batched_rn_per_s": total / (batch_ms * 1e-3),
+        "batched_frac_of_hbm_peak": 4 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "autotuned_shape": {"waves_per_block": best[0], "unroll": best[1], "blocks_per_cu": best[2],
+                            "store_words": best[3]},
+        "default_shape_ms": default_ms[0] if default_ms else None,
+        "autotune_s": tune_s,
+        "autotune_candidates": len(recs),
+        "per_stream_plain_launches_ms": plain_ms,
+        "per_stream_plain_wall_s": plain_wall,
+        "speedup_batched_vs_per_stream": plain_ms / batch_ms,
+    }
+    del b, g, gs, out
+    torch.cuda.empty_cache()
+    return res
+
+
+def extra_fused_moments(torch, dev):
+    """4096 streams x 2^18 normals reduced in-kernel to sums of z and z^2."""
+    from paper_1108_0486_amd import workloads as W
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    S, N = W.FUSED_STREAMS, W.FUSED_N
+    gs = XorgensStreams(S, seed=SEED, device=dev)
+    sums = torch.empty((S, 2), dtype=torch.float32, device=dev)
+    for _ in range(3):
+        gs.moments(N, out=sums)
+    reps = 20
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        gs.moments(N, out=sums)
+    e.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    zs = torch.empty((S, N), dtype=torch.float32, device=dev)
+    gs.normal(N, out=zs)
+    a.record()
+    for _ in range(5):
+        gs.normal(N, out=zs)
+    e.record()
+    torch.cuda.synchronize()
+    unfused_ms = a.elapsed_time(e) / 5
+    del zs, gs
+    torch.cuda.empty_cache()
+    return {"workload": "4096 streams x 2^18 FP32 normals (Box-Muller), sums of z and z^2 in-kernel",
+            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3),
+            "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3)}
+
+
+def extra_serving(torch, dev, num_requests: int):
+    """10^5 device-resident streams; Poisson arrivals at 20k req/s (seed 11);
+    N log-uniform in [2^8, 2^24]; dtype uniform over {u32, f32, normal};
+    8 GiB output pool; against one plain launch per request (FIFO) on a
+    prefix of the same trace."""
+    from paper_1108_0486_amd import workloads as W
+    from paper_1108_0486_amd.serve import Server, run_trace, run_trace_plain_fifo
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    trace = W.serving_trace(num_requests)
+    gs = XorgensStreams(W.SERVE_STREAMS, seed=SEED, device=dev)
+    srv = Server(gs, pool_elems=1 << 31, num_lanes=4, max_batch=4096)
+    full, _, _ = run_trace(srv, trace, timeout_s=600)
+    srv.close()
+    prefix = trace[:2000]
+    gs2 = XorgensStreams(W.SERVE_STREAMS, seed=SEED, device=dev)
+    srv2 = Server(gs2, pool_elems=1 << 31, num_lanes=4, max_batch=4096)
+    served_prefix, _, _ = run_trace(srv2, prefix, timeout_s=300)
+    srv2.close()
+    gs3 = XorgensStreams(W.SERVE_STREAMS, seed=SEED, device=dev)
+    plain_prefix = run_trace_plain_fifo(gs3, prefix, max_n=1 << 24, timeout_s=300)
+    del srv, srv2, gs, gs2, gs3
+    torch.cuda.empty_cache()
+    return {"workload": "10^5 streams, %d requests, Poisson 20k req/s (seed 11), N = floor(2^(8 + 16 U)), "
+                        "dtype in {u32, f32, normal}, 8 GiB pool, 4 lanes" % num_requests,
+            "served": full,
+            "prefix_2000": {"served": served_prefix, "plain_fifo": plain_prefix}}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +208,9 @@ def main() -> int:
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--unroll", type=int, default=None)
     ap.add_argument("--store-words", type=int, default=None)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the ragged-batch, fused-moments and serving measurements")
+    ap.add_argument("--serve-requests", type=int, default=200_000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -155,6 +282,13 @@ def main() -> int:
     traffic = measured_traffic()
     threads = max(1, min(16, os.cpu_count() or 1))
     cpu = None if args.no_cpu_baseline else cpu_baseline(threads)
+    del out_u, out_f
+    torch.cuda.empty_cache()
+    extras = None
+    if not args.no_extras:
+        extras = {"ragged_batch": extra_ragged_batch(torch, dev),
+                  "fused_moments": extra_fused_moments(torch, dev),
+                  "serving": extra_serving(torch, dev, args.serve_requests)}
 
     wpb, un, sw = gs.plain_tune()
     line = {
@@ -204,6 +338,7 @@ def main() -> int:
         "fill_ceiling_GBs": fill_gbs,
         "frac_of_fill_ceiling": achieved / fill_gbs,
         "cpu_baseline": cpu,
+        "extras": extras,
     }
     print(json.dumps(line), flush=True)
     return 0
