@@ -173,6 +173,23 @@ xg_status xg_generate_normal(xg_ctx *ctx, uint64_t first, uint64_t count, uint64
 xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                             float *d_sums, void *stream);
 
+/* Advances streams first .. first + count - 1 by J words each, producing
+ * nothing: afterwards they are where J generated words would have left them
+ * (positions, rings and Weyl values).  Short skips (J < 2^15) step through the
+ * words; longer ones jump: the x-part is GF(2)-linear (Section 1.5), its
+ * 4096-bit state moves by a matrix T, and T^J = g(T) with g = z^J mod P, P
+ * the characteristic polynomial of T (degree 4096, primitive); the host
+ * computes g and each wavefront evaluates g(T) on its stream's state by
+ * Horner's rule in steps of 64 words.  The Weyl value advances by J omega.
+ * Errors: XG_EINVAL, XG_ERANGE, XG_ENOTSUP (P unavailable), XG_EHIP.  J == 0
+ * enqueues nothing. */
+xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream);
+
+/* The jump polynomial z^J mod P itself: 4096 coefficients as 64 little-endian
+ * 64-bit words in h_g (host memory; bit i of word k is the coefficient of
+ * z^(64 k + i)).  Errors: XG_EINVAL (NULL h_g), XG_ENOTSUP. */
+xg_status xg_jump_polynomial(uint64_t J, uint64_t *h_g);
+
 /* ---- batched requests ------------------------------------------------------ */
 
 /* One request: n values of type dtype from stream `stream`'s current

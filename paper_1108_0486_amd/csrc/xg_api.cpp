@@ -190,6 +190,27 @@ xg_status xg_fill_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, f
   return fill(ctx, xg::kF32, first, count, n, d_out, stream);
 }
 
+xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream) {
+  if (!ctx || count == 0) return XG_EINVAL;
+  if (first > ctx->num_streams || count > ctx->num_streams - first) return XG_ERANGE;
+  xg_status st = check_ctx_device(ctx);
+  if (st != XG_OK || J == 0) return st;
+  hipError_t e;
+  if (J < xg::kJumpThreshold) {
+    e = xg::launch_skip(ctx->d_state, first, count, J, nullptr, static_cast<hipStream_t>(stream));
+  } else {
+    xg::JumpPoly g;
+    if (!xg::jump_polynomial(J, g.w)) return XG_ENOTSUP;
+    e = xg::launch_skip(ctx->d_state, first, count, J, &g, static_cast<hipStream_t>(stream));
+  }
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
+xg_status xg_jump_polynomial(uint64_t J, uint64_t *h_g) {
+  if (!h_g) return XG_EINVAL;
+  return xg::jump_polynomial(J, h_g) ? XG_OK : XG_ENOTSUP;
+}
+
 size_t xg_batch_workspace_bytes(void) { return 256; }
 
 xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_streams,

@@ -42,6 +42,22 @@ hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint6
 hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t first, uint64_t count,
                        uint64_t n, uint32_t *out, hipStream_t stream);
 
+// Jump polynomial z^J mod P of the x-part's characteristic polynomial
+// (4096 bits, little-endian words).  False if P could not be derived.
+bool jump_polynomial(uint64_t J, uint64_t g[64]);
+
+// Skips below this many words step through them; longer skips jump.
+constexpr uint64_t kJumpThreshold = 1ull << 15;
+
+struct JumpPoly {
+  uint64_t w[64];
+};
+
+// Advances streams [first, first + count) by J words: by stepping when
+// g == nullptr, else by evaluating g(T) on each state (g = z^J mod P).
+hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
+                       hipStream_t stream);
+
 hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
                         const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,
                         uint32_t num_groups,

@@ -45,9 +45,15 @@ __device__ __forceinline__ uint32_t lanes_rotate_up(uint32_t v) {
   return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
 }
 
-// a xor b xor c in one gfx950 v_bitop3_b32 (truth table 0x96).
+// a xor b xor c in one gfx950 v_bitop3_b32.  A truth table is the function's
+// value on the operand patterns a = 0xF0, b = 0xCC, c = 0xAA: here 0x96.
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
   return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+// a xor (b and m) in one v_bitop3_b32 (truth table 0xF0 ^ (0xCC & 0xAA) = 0x78).
+__device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t m) {
+  return __builtin_amdgcn_bitop3_b32(a, b, m, 0x78);
 }
 
 __device__ __forceinline__ uint32_t temper_weyl(uint32_t w) { return w ^ (w >> 16); }
@@ -136,6 +142,17 @@ extern __shared__ __align__(16) uint32_t xg_lds[];
 
 __device__ __forceinline__ uint32_t *wave_stage() { return xg_lds + (threadIdx.x >> 6) * 256u; }
 
+// Orders the LDS accesses of a wavefront's lanes before it against those after
+// it.  Lanes read words other lanes wrote; without a fence the compiler may
+// move (or drop) such accesses as if each lane only ever read its own writes.
+// The fences cover LDS only, so outstanding global stores are not waited for;
+// the wavefront's LDS instructions execute in order.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // ---------------------------------------------------------------------------
 // One stream's word sequence inside a wavefront: open (load the state), next
 // (one 64-word chunk of outputs, lane j holding word j), close (the ragged last
@@ -211,9 +228,9 @@ __device__ __forceinline__ void serve_words(uint32_t *__restrict__ st, uint64_t 
         for (int q = 0; q < UNROLL / 4; ++q) {
 #pragma unroll
           for (int u = 0; u < 4; ++u) stage[64 * u + lane] = map_word<KIND>(next_chunk(s));
-          // In-order LDS: this read sees the four writes above, and the next
-          // group's writes land after it.
+          wave_lds_sync();  // the read below takes words other lanes wrote
           const u32x4 v = *reinterpret_cast<const u32x4 *>(stage + 4 * lane);
+          wave_lds_sync();  // the next group's writes come after this read
           __builtin_nontemporal_store(v, o4 + q * 64);
         }
         o4 += (UNROLL / 4) * 64;
@@ -474,6 +491,84 @@ __global__ __launch_bounds__(1024) void k_fill(uint32_t *__restrict__ state, uin
   serve_words_fill<KIND, UNROLL>(state + (first + wid) * kStateWords, n, wid, count, out);
 }
 
+// ---------------------------------------------------------------------------
+// skip: advance a stream by J words without producing them.
+// ---------------------------------------------------------------------------
+
+// By stepping: the recurrence runs J words and only the state is kept.
+__device__ __forceinline__ void skip_by_stepping(uint32_t *st, uint64_t J) {
+  WordStream s = open_stream(st);
+  const uint64_t nfull = J >> 6;
+  const uint32_t rem = (uint32_t)(J & 63u);
+  for (uint64_t c = 0; c != nfull; ++c) (void)ring_step(s.g, s.lane0);
+  const uint32_t p0 = s.g.prev, c0 = s.g.cur;
+  uint32_t x = 0u;
+  if (rem) x = ring_step(s.g, s.lane0);
+  store_ring(st, p0, c0, x, rem, s.lane);
+  store_weyl_pos(st, s.w_start + (uint32_t)J * kOmega, s.pos + J, s.lane);
+}
+
+// By jumping: with g = z^J mod P = sum_c z^(64 c) h_c(z) (h_c of degree < 64),
+// T^J S0 = g(T) S0 is evaluated by Horner's rule in steps of 64 words,
+//     S <- T^64 S  xor  h_c(T) S0,      c = 63 .. 0,
+// where T^64 S is one wavefront chunk step on the state S, and
+// h_c(T) S0 = xor of the windows T^i S0 (i < 64, bit i of h_c set); window i
+// holds words x_{i-128} .. x_{i-1} of S0's continuation, so lane j's two words
+// of it are x_{i-128+j} and x_{i-64+j}, staged once from LDS into registers.
+__device__ __forceinline__ void skip_by_jump(uint32_t *st, const JumpPoly &g, uint64_t J) {
+  const uint32_t lane = lane_id();
+  const bool lane0 = lane == 0;
+  const uint32_t prev0 = st[lane], cur0 = st[64 + lane];
+  const uint32_t w0 = st[128];
+  const uint64_t pos = load_pos(st);
+  Ring r = ring_from(prev0, cur0);
+  const uint32_t x0 = ring_step(r, lane0);             // x_0 .. x_63
+  uint32_t *buf = wave_stage();                          // x_{-128} .. x_{63}
+  buf[lane] = prev0;
+  buf[64 + lane] = cur0;
+  buf[128 + lane] = x0;
+  wave_lds_sync();
+  uint32_t xw[128];                                      // xw[k] = x_{k-128+j}
+#pragma unroll
+  for (int k = 0; k < 128; ++k) xw[k] = buf[lane + k];
+  uint32_t slo = 0u, shi = 0u;
+#pragma unroll 1
+  for (int c = 63; c >= 0; --c) {
+    if (c != 63) {
+      Ring q = ring_from(slo, shi);
+      const uint32_t nx = ring_step(q, lane0);
+      slo = shi;
+      shi = nx;
+    }
+    const uint32_t hlo = (uint32_t)g.w[c], hhi = (uint32_t)(g.w[c] >> 32);
+    uint32_t alo = 0u, ahi = 0u;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const uint32_t word = i < 32 ? hlo : hhi;
+      const uint32_t m = (uint32_t)((int32_t)(word << (31 - (i & 31))) >> 31);  // bit i of h_c, all ones or zero
+      alo = xor_and(alo, xw[i], m);
+      ahi = xor_and(ahi, xw[64 + i], m);
+    }
+    slo ^= alo;
+    shi ^= ahi;
+  }
+  store_ring(st, slo, shi, 0u, 0u, lane);
+  store_weyl_pos(st, w0 + (uint32_t)J * kOmega, pos + J, lane);
+}
+
+template <bool JUMP>
+__global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ state, uint64_t first, uint64_t count,
+                                              uint64_t J, JumpPoly g) {
+  const uint64_t wid = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (wid >= count) return;
+  uint32_t *st = state + (first + wid) * kStateWords;
+  if constexpr (JUMP) {
+    skip_by_jump(st, g, J);
+  } else {
+    skip_by_stepping(st, J);
+  }
+}
+
 __global__ void k_clear_work(uint32_t *work) {
   if (threadIdx.x < 64) work[threadIdx.x] = 0u;
 }
@@ -584,6 +679,19 @@ hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t 
     default: if (f) hipLaunchKernelGGL((k_fill<kF32, 8>), grid, block, 0, stream, state, first, count, n, out);
              else hipLaunchKernelGGL((k_fill<kU32, 8>), grid, block, 0, stream, state, first, count, n, out);
              break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
+                       hipStream_t stream) {
+  const dim3 grid((uint32_t)((count + 3) / 4)), block(256);
+  if (g) {
+    hipLaunchKernelGGL((k_skip<true>), grid, block, 4 * 1024, stream, state, first, count, J, *g);
+  } else {
+    JumpPoly none;
+    for (int i = 0; i < 64; ++i) none.w[i] = 0;
+    hipLaunchKernelGGL((k_skip<false>), grid, block, 0, stream, state, first, count, J, none);
   }
   return hipGetLastError();
 }

@@ -112,6 +112,12 @@ class XorgensStreams:
         xg.xg_normal_moments(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
         return out
 
+    def skip(self, J: int, first: int = 0, count: int | None = None,
+             stream: torch.cuda.Stream | None = None) -> None:
+        """Advances the selected streams by J words without producing them."""
+        first, count = self._range(first, count)
+        xg.xg_skip(self.ctx, first, count, J, _stream_handle(stream))
+
     # ---- state --------------------------------------------------------------
     def host_state(self, idx=None):
         """(ring[k, 128] uint32, weyl[k] uint32, pos[k] uint64) of the selected streams."""

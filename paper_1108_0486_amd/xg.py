@@ -101,6 +101,8 @@ def lib() -> ctypes.CDLL:
         "xg_generate_normal": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_normal_moments": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_fill_u32": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_skip": (st, [vp, u64, u64, u64, vp]),
+        "xg_jump_polynomial": (st, [u64, P(u64)]),
         "xg_fill_f32": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
         "xg_plan_batch": (st, [P(xg_request), u32, u64, u64, P(xg_request), P(u32), P(u32)]),
@@ -210,6 +212,17 @@ def fill_index(count: int, n: int):
     head = (t // 64) * 64 * count + k * 64 + t % 64
     tail = 64 * full * count + k * rem + (t - 64 * full)
     return np.where(t < 64 * full, head, tail)
+
+
+def xg_skip(ctx, first: int, count: int, J: int, stream: int = 0) -> None:
+    _check(lib().xg_skip(ctx, first, count, J, stream), "xg_skip")
+
+
+def xg_jump_polynomial(J: int) -> int:
+    """z^J mod P as a Python int (bit i = coefficient of z^i)."""
+    g = (ctypes.c_uint64 * 64)()
+    _check(lib().xg_jump_polynomial(J, g), "xg_jump_polynomial")
+    return sum(int(g[k]) << (64 * k) for k in range(64))
 
 
 def xg_batch_workspace_bytes() -> int:

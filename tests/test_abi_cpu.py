@@ -117,3 +117,11 @@ def test_server_abi_without_gpu():
     srv = ctypes.c_void_p()
     assert L.xg_server_create(ctypes.byref(srv), None, None, None, 0, None, 0) == xg.XG_EINVAL
     L.xg_server_destroy(None)
+
+
+@pytest.mark.parametrize("J", [0, 1, 64, 4095, 4096, 10**5, 2**32 + 5, 2**63 + 12345, 2**64 - 1])
+def test_jump_polynomial_matches_oracle(J):
+    """The library's own z^J mod P (host, no GPU) equals the oracle's."""
+    from oracle import oracle as O
+    P = O.charpoly(O.PAPER)
+    assert xg.xg_jump_polynomial(J) == O.z_pow_mod(J, P)
