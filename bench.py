@@ -173,20 +173,22 @@ def extra_fused_moments(torch, dev):
 def extra_serving(torch, dev, num_requests: int):
     """10^5 device-resident streams; Poisson arrivals at 20k req/s (seed 11);
     N log-uniform in [2^8, 2^24]; dtype uniform over {u32, f32, normal};
-    8 GiB output pool; against one plain launch per request (FIFO) on a
-    prefix of the same trace."""
+    8 GiB output pool, 4 lanes, requests longer than 2^16 words served as
+    jumped segments; against one plain launch per request (FIFO) on a prefix
+    of the same trace."""
     from paper_1108_0486_amd import workloads as W
     from paper_1108_0486_amd.serve import Server, run_trace, run_trace_plain_fifo
     from paper_1108_0486_amd.streams import XorgensStreams
 
     trace = W.serving_trace(num_requests)
     gs = XorgensStreams(W.SERVE_STREAMS, seed=SEED, device=dev)
-    srv = Server(gs, pool_elems=1 << 31, num_lanes=4, max_batch=4096)
+    seg = 1 << 16
+    srv = Server(gs, pool_elems=1 << 31, num_lanes=4, max_batch=8192, segment_words=seg)
     full, _, _ = run_trace(srv, trace, timeout_s=600)
     srv.close()
     prefix = trace[:2000]
     gs2 = XorgensStreams(W.SERVE_STREAMS, seed=SEED, device=dev)
-    srv2 = Server(gs2, pool_elems=1 << 31, num_lanes=4, max_batch=4096)
+    srv2 = Server(gs2, pool_elems=1 << 31, num_lanes=4, max_batch=8192, segment_words=seg)
     served_prefix, _, _ = run_trace(srv2, prefix, timeout_s=300)
     srv2.close()
     gs3 = XorgensStreams(W.SERVE_STREAMS, seed=SEED, device=dev)
@@ -194,7 +196,7 @@ def extra_serving(torch, dev, num_requests: int):
     del srv, srv2, gs, gs2, gs3
     torch.cuda.empty_cache()
     return {"workload": "10^5 streams, %d requests, Poisson 20k req/s (seed 11), N = floor(2^(8 + 16 U)), "
-                        "dtype in {u32, f32, normal}, 8 GiB pool, 4 lanes" % num_requests,
+                        "dtype in {u32, f32, normal}, 8 GiB pool, 4 lanes, 2^16-word segments" % num_requests,
             "served": full,
             "prefix_2000": {"served": served_prefix, "plain_fifo": plain_prefix}}
 

@@ -276,8 +276,13 @@ typedef struct xg_server xg_server;
 
 typedef struct {
     uint32_t num_lanes;   /* HIP streams, each with at most one batch in flight: 1 .. 8 */
-    uint32_t max_batch;   /* requests per batch: 1 .. 65536 */
+    uint32_t max_batch;   /* table entries per batch (requests and segments): 1 .. 65536 */
     xg_tune tune;         /* batch launch shape; all zero selects the default */
+    uint64_t segment_words; /* 0, or L (a multiple of 64, 2^12 .. 2^30): a request of more
+                               than L words is served as up to 256 segments of L words run
+                               by separate wavefronts, segment k starting from the request's
+                               start state jumped by k L words (xg_skip's jump); the values
+                               are those of the unsplit request */
 } xg_server_config;
 
 typedef struct {

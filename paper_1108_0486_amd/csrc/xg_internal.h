@@ -58,10 +58,39 @@ struct JumpPoly {
 hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
                        hipStream_t stream);
 
+// Request flags of server-built tables (the public batch call takes flags 0).
+// A segment covers words [k L, k L + n') of a longer request on its stream: it
+// reads the stream's state, jumps by k L (jump_table entry k - 1 holds
+// z^(k L) mod P) and generates its n values; it never writes the stream's
+// state.  The last segment writes the end state to staging slot (flags >> 16),
+// which k_commit copies into the stream's state after the batch.
+constexpr uint32_t kReqSegment = 1u;
+constexpr uint32_t kReqLast = 2u;
+constexpr uint32_t kReqUndefinedBits = 0x000000FCu;
+constexpr uint32_t kMaxSegments = 256;  // k in 0 .. 255
+
+struct SegmentArgs {
+  const uint64_t *jump_table;  // (max_k) x 64 words
+  uint64_t seg_words;          // L
+  uint32_t max_k;              // entries in jump_table
+  uint32_t *stage;             // max_slots x kStateWords words
+  uint32_t max_slots;
+};
+
 hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
                         const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,
                         uint32_t num_groups,
-                        uint32_t *out, uint64_t out_elems, uint32_t *work, hipStream_t stream);
+                        uint32_t *out, uint64_t out_elems, uint32_t *work, hipStream_t stream,
+                        const SegmentArgs *seg = nullptr);
+
+// Copies the staged end states of a batch's last segments into their streams.
+hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
+                         const SegmentArgs &seg, hipStream_t stream);
+
+// xg_plan_batch, with segment requests (kReqSegment) allowed: each forms its
+// own group.
+xg_status plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_streams, uint64_t out_elems,
+                     xg_request *h_sorted, uint32_t *h_groups, uint32_t *num_groups, bool allow_segments);
 
 }  // namespace xg
 

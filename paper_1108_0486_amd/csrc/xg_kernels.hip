@@ -154,7 +154,37 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // ---------------------------------------------------------------------------
-// One stream's word sequence inside a wavefront: open (load the state), next
+// A stream's state held by a wavefront: lane j has ring words j and 64 + j;
+// the Weyl value W_{pos-1} and the position are wave-uniform.
+// ---------------------------------------------------------------------------
+struct StreamState {
+  uint32_t prev;  // x_{pos-128+j}
+  uint32_t cur;   // x_{pos-64+j}
+  uint32_t weyl;  // W_{pos-1}
+  uint64_t pos;
+};
+
+__device__ __forceinline__ StreamState load_state(const uint32_t *st) {
+  const uint32_t lane = lane_id();
+  StreamState s;
+  s.prev = st[lane];
+  s.cur = st[64 + lane];
+  s.weyl = st[128];
+  s.pos = load_pos(st);
+  return s;
+}
+
+// Writes the state whose ring is the 128-word window ending `rem` words into
+// chunk x (see store_ring); dst == nullptr (wave-uniform) writes nothing.
+__device__ __forceinline__ void write_state(uint32_t *dst, uint32_t prev, uint32_t cur, uint32_t x,
+                                            uint32_t rem, uint32_t weyl, uint64_t pos, uint32_t lane) {
+  if (!dst) return;
+  store_ring(dst, prev, cur, x, rem, lane);
+  store_weyl_pos(dst, weyl, pos, lane);
+}
+
+// ---------------------------------------------------------------------------
+// One stream's word sequence inside a wavefront: open (from a state), next
 // (one 64-word chunk of outputs, lane j holding word j), close (the ragged last
 // chunk, then the state write-back).
 // ---------------------------------------------------------------------------
@@ -168,17 +198,19 @@ struct WordStream {
   bool lane0;
 };
 
-__device__ __forceinline__ WordStream open_stream(const uint32_t *st) {
+__device__ __forceinline__ WordStream open_from(const StreamState &st) {
   WordStream s;
   s.lane = lane_id();
   s.lane0 = s.lane == 0;
-  s.g = ring_from(st[s.lane], st[64 + s.lane]);
-  s.w_start = st[128];
+  s.g = ring_from(st.prev, st.cur);
+  s.w_start = st.weyl;
   s.wbase = s.w_start;
   s.wlane = (s.lane + 1u) * kOmega;
-  s.pos = load_pos(st);
+  s.pos = st.pos;
   return s;
 }
+
+__device__ __forceinline__ WordStream open_stream(const uint32_t *st) { return open_from(load_state(st)); }
 
 __device__ __forceinline__ uint32_t next_chunk(WordStream &s) {
   const uint32_t x = ring_step(s.g, s.lane0);
@@ -188,9 +220,10 @@ __device__ __forceinline__ uint32_t next_chunk(WordStream &s) {
 }
 
 // Emits the last rem (< 64) words of an n-word request through `tail`
-// (lane-indexed: lane j writes tail[j], j < rem) and writes the state back.
+// (lane-indexed: lane j writes tail[j], j < rem) and writes the end state to
+// dst (nullptr: nowhere).
 template <uint32_t KIND>
-__device__ __forceinline__ void close_stream(uint32_t *st, WordStream &s, uint64_t n, uint32_t rem,
+__device__ __forceinline__ void close_stream(uint32_t *dst, WordStream &s, uint64_t n, uint32_t rem,
                                              uint32_t *tail) {
   const uint32_t p0 = s.g.prev, c0 = s.g.cur;
   uint32_t x = 0u;
@@ -199,8 +232,7 @@ __device__ __forceinline__ void close_stream(uint32_t *st, WordStream &s, uint64
     const uint32_t w = s.wbase + s.wlane;
     if (s.lane < rem) emit_word<KIND>(tail, x + temper_weyl(w));
   }
-  store_ring(st, p0, c0, x, rem, s.lane);
-  store_weyl_pos(st, s.w_start + (uint32_t)n * kOmega, s.pos + n, s.lane);
+  write_state(dst, p0, c0, x, rem, s.w_start + (uint32_t)n * kOmega, s.pos + n, s.lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,9 +242,9 @@ __device__ __forceinline__ void close_stream(uint32_t *st, WordStream &s, uint64
 // store instruction instead of 256 B); the rest uses one 4-byte store per lane.
 // ---------------------------------------------------------------------------
 template <uint32_t KIND, int UNROLL, bool WIDE>
-__device__ __forceinline__ void serve_words(uint32_t *__restrict__ st, uint64_t n,
-                                            uint32_t *__restrict__ out) {
-  WordStream s = open_stream(st);
+__device__ __forceinline__ void serve_words_from(const StreamState &s0, uint64_t n, uint32_t *__restrict__ out,
+                                                 uint32_t *dst) {
+  WordStream s = open_from(s0);
   const uint32_t lane = s.lane;
   const uint64_t nfull = n >> 6;
   const uint32_t rem = (uint32_t)(n & 63u);
@@ -251,7 +283,12 @@ __device__ __forceinline__ void serve_words(uint32_t *__restrict__ st, uint64_t 
     emit_word<KIND>(o, next_chunk(s));
     o += 64;
   }
-  close_stream<KIND>(st, s, n, rem, o);
+  close_stream<KIND>(dst, s, n, rem, o);
+}
+
+template <uint32_t KIND, int UNROLL, bool WIDE>
+__device__ __forceinline__ void serve_words(uint32_t *st, uint64_t n, uint32_t *__restrict__ out) {
+  serve_words_from<KIND, UNROLL, WIDE>(load_state(st), n, out, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -351,13 +388,13 @@ __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t id
 // n normals of one stream; MOMENTS: reduce to (sum z, sum z^2) in sums[0..1]
 // instead of storing them.  Consumes 2 ceil(n / 2) words.
 template <bool MOMENTS, int UNROLL>
-__device__ __forceinline__ void serve_normals(uint32_t *__restrict__ st, uint64_t n,
-                                              float *__restrict__ out, float *__restrict__ sums) {
+__device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64_t n, float *__restrict__ out,
+                                                   float *__restrict__ sums, uint32_t *dst) {
   const uint32_t lane = lane_id();
   const bool lane0 = lane == 0;
-  Ring g = ring_from(st[lane], st[64 + lane]);
-  const uint32_t w_start = st[128];
-  const uint64_t pos = load_pos(st);
+  Ring g = ring_from(s0.prev, s0.cur);
+  const uint32_t w_start = s0.weyl;
+  const uint64_t pos = s0.pos;
   uint32_t wbase = w_start;
   const uint32_t wlane = (lane + 1u) * kOmega;
   const uint64_t words = n + (n & 1u);
@@ -417,8 +454,7 @@ __device__ __forceinline__ void serve_normals(uint32_t *__restrict__ st, uint64_
     gather_pair(oa, ob, lane, e, o);
     if (2u * lane < rw) consume_pair<MOMENTS>(e, o, (nblk << 7) + 2u * lane, n, out, pair_aligned, m);
   }
-  store_ring(st, p0, c0, xl, rem, lane);
-  store_weyl_pos(st, w_start + (uint32_t)words * kOmega, pos + words, lane);
+  write_state(dst, p0, c0, xl, rem, w_start + (uint32_t)words * kOmega, pos + words, lane);
   if constexpr (MOMENTS) {
     float v1 = m.s1 - m.c1, v2 = m.s2 - m.c2;
 #pragma unroll
@@ -431,6 +467,12 @@ __device__ __forceinline__ void serve_normals(uint32_t *__restrict__ st, uint64_
       sums[1] = v2;
     }
   }
+}
+
+template <bool MOMENTS, int UNROLL>
+__device__ __forceinline__ void serve_normals(uint32_t *st, uint64_t n, float *__restrict__ out,
+                                              float *__restrict__ sums) {
+  serve_normals_from<MOMENTS, UNROLL>(load_state(st), n, out, sums, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -514,23 +556,23 @@ __device__ __forceinline__ void skip_by_stepping(uint32_t *st, uint64_t J) {
 // where T^64 S is one wavefront chunk step on the state S, and
 // h_c(T) S0 = xor of the windows T^i S0 (i < 64, bit i of h_c set); window i
 // holds words x_{i-128} .. x_{i-1} of S0's continuation, so lane j's two words
-// of it are x_{i-128+j} and x_{i-64+j}, staged once from LDS into registers.
-__device__ __forceinline__ void skip_by_jump(uint32_t *st, const JumpPoly &g, uint64_t J) {
+// of it are x_{i-128+j} and x_{i-64+j}, staged once through LDS into
+// registers.  word(c) returns h_c as 64 bits.  Needs the wavefront's LDS slot.
+template <typename WordOf>
+__device__ __forceinline__ void jump_state(StreamState &s, WordOf word, uint64_t J) {
   const uint32_t lane = lane_id();
   const bool lane0 = lane == 0;
-  const uint32_t prev0 = st[lane], cur0 = st[64 + lane];
-  const uint32_t w0 = st[128];
-  const uint64_t pos = load_pos(st);
-  Ring r = ring_from(prev0, cur0);
+  Ring r = ring_from(s.prev, s.cur);
   const uint32_t x0 = ring_step(r, lane0);             // x_0 .. x_63
   uint32_t *buf = wave_stage();                          // x_{-128} .. x_{63}
-  buf[lane] = prev0;
-  buf[64 + lane] = cur0;
+  buf[lane] = s.prev;
+  buf[64 + lane] = s.cur;
   buf[128 + lane] = x0;
   wave_lds_sync();
   uint32_t xw[128];                                      // xw[k] = x_{k-128+j}
 #pragma unroll
   for (int k = 0; k < 128; ++k) xw[k] = buf[lane + k];
+  wave_lds_sync();                                       // the slot may be reused after this
   uint32_t slo = 0u, shi = 0u;
 #pragma unroll 1
   for (int c = 63; c >= 0; --c) {
@@ -540,20 +582,23 @@ __device__ __forceinline__ void skip_by_jump(uint32_t *st, const JumpPoly &g, ui
       slo = shi;
       shi = nx;
     }
-    const uint32_t hlo = (uint32_t)g.w[c], hhi = (uint32_t)(g.w[c] >> 32);
+    const uint64_t h = word(c);
+    const uint32_t hlo = (uint32_t)h, hhi = (uint32_t)(h >> 32);
     uint32_t alo = 0u, ahi = 0u;
 #pragma unroll
     for (int i = 0; i < 64; ++i) {
-      const uint32_t word = i < 32 ? hlo : hhi;
-      const uint32_t m = (uint32_t)((int32_t)(word << (31 - (i & 31))) >> 31);  // bit i of h_c, all ones or zero
+      const uint32_t bits = i < 32 ? hlo : hhi;
+      const uint32_t m = (uint32_t)((int32_t)(bits << (31 - (i & 31))) >> 31);  // bit i of h_c, all ones or zero
       alo = xor_and(alo, xw[i], m);
       ahi = xor_and(ahi, xw[64 + i], m);
     }
     slo ^= alo;
     shi ^= ahi;
   }
-  store_ring(st, slo, shi, 0u, 0u, lane);
-  store_weyl_pos(st, w0 + (uint32_t)J * kOmega, pos + J, lane);
+  s.prev = slo;
+  s.cur = shi;
+  s.weyl += (uint32_t)J * kOmega;
+  s.pos += J;
 }
 
 template <bool JUMP>
@@ -563,7 +608,9 @@ __global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ state, uint
   if (wid >= count) return;
   uint32_t *st = state + (first + wid) * kStateWords;
   if constexpr (JUMP) {
-    skip_by_jump(st, g, J);
+    StreamState s = load_state(st);
+    jump_state(s, [&](int c) { return g.w[c]; }, J);
+    write_state(st, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane_id());
   } else {
     skip_by_stepping(st, J);
   }
@@ -581,7 +628,8 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
                                                 uint32_t num_reqs,
                                                 const uint32_t *__restrict__ groups,
                                                 uint32_t num_groups, uint32_t *__restrict__ out,
-                                                uint64_t out_elems, uint32_t *__restrict__ work) {
+                                                uint64_t out_elems, uint32_t *__restrict__ work,
+                                                SegmentArgs seg) {
   const uint32_t lane = lane_id();
   for (;;) {
     uint32_t g = 0;
@@ -595,7 +643,11 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
     }
     for (uint32_t r = r0; r < r1; ++r) {
       const xg_request q = reqs[r];
-      const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u &&
+      const bool is_seg = (q.flags & kReqSegment) != 0;
+      const uint32_t k = (q.flags >> 8) & 0xFFu, slot = q.flags >> 16;
+      const bool seg_ok = !is_seg || (seg.jump_table && (q.flags & kReqUndefinedBits) == 0 &&
+                                      k <= seg.max_k && (!(q.flags & kReqLast) || slot < seg.max_slots));
+      const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && (is_seg ? seg_ok : q.flags == 0u) &&
                       q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
       if (!ok) {
         if (lane == 0) atomicOr(&work[1], 1u);
@@ -603,15 +655,49 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
       }
       uint32_t *st = state + q.stream * kStateWords;
       uint32_t *o = out + q.out_offset;
+      if (!is_seg) {
+        if (q.dtype == XG_U32) {
+          serve_words<kU32, UNROLL, WIDE>(st, q.n, o);
+        } else if (q.dtype == XG_F32) {
+          serve_words<kF32, UNROLL, WIDE>(st, q.n, o);
+        } else {
+          serve_normals<false, UNROLL>(st, q.n, reinterpret_cast<float *>(o), nullptr);
+        }
+        continue;
+      }
+      StreamState s0 = load_state(st);
+      if (k) {
+        const uint64_t *gk = seg.jump_table + (uint64_t)(k - 1) * 64;
+        jump_state(s0, [&](int c) { return gk[c]; }, (uint64_t)k * seg.seg_words);
+      }
+      uint32_t *dst = (q.flags & kReqLast) ? seg.stage + (uint64_t)slot * kStateWords : nullptr;
       if (q.dtype == XG_U32) {
-        serve_words<kU32, UNROLL, WIDE>(st, q.n, o);
+        serve_words_from<kU32, UNROLL, WIDE>(s0, q.n, o, dst);
       } else if (q.dtype == XG_F32) {
-        serve_words<kF32, UNROLL, WIDE>(st, q.n, o);
+        serve_words_from<kF32, UNROLL, WIDE>(s0, q.n, o, dst);
       } else {
-        serve_normals<false, UNROLL>(st, q.n, reinterpret_cast<float *>(o), nullptr);
+        serve_normals_from<false, UNROLL>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
       }
     }
   }
+}
+
+// One wavefront per request: a last segment's staged end state becomes its
+// stream's state.
+__global__ __launch_bounds__(256) void k_commit(uint32_t *__restrict__ state, uint64_t num_streams,
+                                                const xg_request *__restrict__ reqs, uint32_t num_reqs,
+                                                const uint32_t *__restrict__ stage, uint32_t max_slots) {
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (r >= num_reqs) return;
+  const xg_request q = reqs[r];
+  const uint32_t slot = q.flags >> 16;
+  if (!(q.flags & kReqSegment) || !(q.flags & kReqLast) || slot >= max_slots || q.stream >= num_streams) return;
+  const uint32_t lane = lane_id();
+  const uint32_t *src = stage + (uint64_t)slot * kStateWords;
+  uint32_t *dst = state + q.stream * kStateWords;
+  dst[lane] = src[lane];
+  dst[64 + lane] = src[64 + lane];
+  if (lane < kStateWords - 128) dst[128 + lane] = src[128 + lane];
 }
 
 template <uint32_t KIND>
@@ -712,7 +798,7 @@ hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint6
 hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
                         const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,
                         uint32_t num_groups, uint32_t *out, uint64_t out_elems, uint32_t *work,
-                        hipStream_t stream) {
+                        hipStream_t stream, const SegmentArgs *seg) {
   hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(64), 0, stream, work);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -721,21 +807,31 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
   const uint64_t need = (want_waves + shape.waves_per_block - 1) / shape.waves_per_block;
   if (need < blocks) blocks = need ? need : 1;
   const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  const size_t lds = (size_t)shape.waves_per_block * 1024u;  // staging slots (wide stores, jumps)
+  SegmentArgs sa{};
+  if (seg) sa = *seg;
   if (shape.store_words == 4) {
-    const size_t lds = (size_t)shape.waves_per_block * 1024u;
     if (shape.unroll == 4) {
-      hipLaunchKernelGGL((k_batch<4, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work);
+      hipLaunchKernelGGL((k_batch<4, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa);
     } else {
-      hipLaunchKernelGGL((k_batch<8, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work);
+      hipLaunchKernelGGL((k_batch<8, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa);
     }
     return hipGetLastError();
   }
   switch (shape.unroll) {
-    case 1: hipLaunchKernelGGL((k_batch<1, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    case 2: hipLaunchKernelGGL((k_batch<2, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    case 4: hipLaunchKernelGGL((k_batch<4, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    default: hipLaunchKernelGGL((k_batch<8, false>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 1: hipLaunchKernelGGL((k_batch<1, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
+    case 2: hipLaunchKernelGGL((k_batch<2, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
+    case 4: hipLaunchKernelGGL((k_batch<4, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
+    default: hipLaunchKernelGGL((k_batch<8, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
+                         const SegmentArgs &seg, hipStream_t stream) {
+  if (num_reqs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_commit, dim3((num_reqs + 3) / 4), dim3(256), 0, stream, state, num_streams, reqs, num_reqs,
+                     seg.stage, seg.max_slots);
   return hipGetLastError();
 }
 

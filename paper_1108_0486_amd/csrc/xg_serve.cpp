@@ -14,6 +14,11 @@
 // Lanes are independent HIP streams, so a batch admitted while others run
 // overlaps with them on the device.  A stream is never in two in-flight
 // batches, so every request reads the exact positions it would read alone.
+// With segment_words = L, a request of more than L words becomes segments of
+// L words, each its own group (so separate wavefronts run them at once):
+// segment k jumps from the request's start state by k L words; only the last
+// one produces the end state, staged and committed after the batch.  A split
+// request is alone on its stream within its batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -98,6 +103,7 @@ struct Pending {
 };
 
 struct Lane {
+  uint32_t *d_stage = nullptr;   // max_batch staging states (split requests)
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
@@ -112,26 +118,36 @@ struct Lane {
 };
 
 struct TableLayout {
-  size_t reqs, groups, work, per_lane;
+  size_t reqs, groups, work, stage, per_lane, jump;
 };
 
-TableLayout table_layout(uint32_t max_batch) {
+// Jump table entries: z^(k L) mod P for k = 1 .. kMaxSegments - 1.
+constexpr uint32_t kJumpEntries = xg::kMaxSegments - 1;
+
+TableLayout table_layout(const xg_server_config *c) {
   TableLayout t;
-  t.reqs = round_up((size_t)max_batch * sizeof(xg_request), kAlignBytes);
-  t.groups = round_up(((size_t)max_batch + 1) * sizeof(uint32_t), kAlignBytes);
+  t.reqs = round_up((size_t)c->max_batch * sizeof(xg_request), kAlignBytes);
+  t.groups = round_up(((size_t)c->max_batch + 1) * sizeof(uint32_t), kAlignBytes);
   t.work = round_up(xg_batch_workspace_bytes(), kAlignBytes);
-  t.per_lane = t.reqs + t.groups + t.work;
+  t.stage = c->segment_words ? round_up((size_t)c->max_batch * XG_STATE_WORDS * 4, kAlignBytes) : 0;
+  t.per_lane = t.reqs + t.groups + t.work + t.stage;
+  t.jump = c->segment_words ? (size_t)kJumpEntries * 64 * sizeof(uint64_t) : 0;
   return t;
 }
 
 bool config_valid(const xg_server_config *c) {
-  return c && c->num_lanes >= 1 && c->num_lanes <= 8 && c->max_batch >= 1 && c->max_batch <= 65536;
+  const bool seg_ok = c && (c->segment_words == 0 ||
+                            (c->segment_words % 64 == 0 && c->segment_words >= (1ull << 12) &&
+                             c->segment_words <= (1ull << 30)));
+  return c && seg_ok && c->num_lanes >= 1 && c->num_lanes <= 8 && c->max_batch >= 1 && c->max_batch <= 65536;
 }
 
 }  // namespace
 
 struct xg_server {
   xg_ctx *ctx = nullptr;
+  uint64_t seg_words = 0;            // 0: no splitting
+  uint64_t *d_jump = nullptr;        // kJumpEntries x 64 words
   uint32_t *d_pool = nullptr;
   uint64_t pool_elems = 0;
   uint32_t max_batch = 0;
@@ -140,7 +156,9 @@ struct xg_server {
   Pool pool{0};
   std::vector<Lane> lanes;
   std::deque<Pending> pending;
-  std::vector<uint8_t> busy_stream;   // stream is inside an in-flight batch
+  // 0 free; 1 inside an in-flight batch; 2 in the batch being built;
+  // 3 in the batch being built as a split request (closed to further requests)
+  std::vector<uint8_t> busy_stream;
   std::vector<uint64_t> pos;          // each stream's position after all admitted work
   std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> finished;  // id -> (offset, n)
   std::deque<xg_completion> ready;    // completions not yet handed out
@@ -191,23 +209,30 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
   Lane &l = s->lanes[li];
   *admitted = 0;
   std::vector<uint64_t> in_this_batch;
-  uint32_t k = 0;
+  uint32_t k = 0, slots = 0, nreq = 0;
   bool waited = false;
   for (auto it = s->pending.begin(); it != s->pending.end() && k < s->max_batch;) {
     const Pending &p = *it;
-    if (s->busy_stream[p.stream] == 1) {  // in flight in another lane: keep order, wait
+    const uint8_t bs = s->busy_stream[p.stream];
+    const uint64_t words = words_consumed(p.n, p.dtype);
+    const uint64_t parts = s->seg_words ? (words + s->seg_words - 1) / s->seg_words : 1;
+    const bool split = parts > 1 && parts <= xg::kMaxSegments;  // longer ones run unsplit
+    const uint64_t nseg = split ? parts : 1;
+    // Wait (keeping this stream's order) when the stream is busy elsewhere,
+    // closed by a split request in this batch, or would mix a split request
+    // with others in this batch.
+    if (bs == 1 || bs == 3 || (split && bs == 2)) {
       ++it;
       continue;
     }
+    if (k + nseg > s->max_batch) break;
     const uint64_t off = s->pool.alloc(p.n);
     if (off == UINT64_MAX) {
       waited = true;
       break;
     }
-    if (s->busy_stream[p.stream] == 0) {
-      s->busy_stream[p.stream] = 2;  // joins this batch
-      in_this_batch.push_back(p.stream);
-    }
+    if (bs == 0) in_this_batch.push_back(p.stream);
+    s->busy_stream[p.stream] = split ? 3 : 2;
     xg_completion c{};
     c.id = p.id;
     c.stream = p.stream;
@@ -217,35 +242,54 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
     c.start_pos = s->pos[p.stream];
     c.t_submit_ns = p.t_submit;
     c.lane = li;
-    s->pos[p.stream] += words_consumed(p.n, p.dtype);
-    l.h_scratch[k] = xg_request{p.stream, p.n, off, p.dtype, 0};
+    s->pos[p.stream] += words;
+    if (!split) {
+      l.h_scratch[k++] = xg_request{p.stream, p.n, off, p.dtype, 0};
+    } else {
+      const uint32_t slot = slots++;
+      for (uint64_t j = 0; j < nseg; ++j) {
+        const uint64_t first = j * s->seg_words;
+        const uint64_t n_j = std::min<uint64_t>(s->seg_words, p.n - first);
+        uint32_t flags = xg::kReqSegment | ((uint32_t)j << 8);
+        if (j + 1 == nseg) flags |= xg::kReqLast | (slot << 16);
+        l.h_scratch[k++] = xg_request{p.stream, n_j, off + first, p.dtype, flags};
+      }
+    }
     l.reqs.push_back(c);
-    ++k;
+    ++nreq;
     it = s->pending.erase(it);
   }
   if (waited) ++s->stats.admission_waits;
   for (uint64_t st : in_this_batch) s->busy_stream[st] = 1;
   if (k == 0) return XG_OK;
   uint32_t num_groups = 0;
-  xg_status st = xg_plan_batch(l.h_scratch, k, s->ctx->num_streams, s->pool_elems, l.h_reqs, l.h_groups,
-                               &num_groups);
+  xg_status st = xg::plan_batch(l.h_scratch, k, s->ctx->num_streams, s->pool_elems, l.h_reqs, l.h_groups,
+                                &num_groups, true);
   if (st != XG_OK) return st;
   if (hipMemcpyAsync(l.d_reqs, l.h_reqs, (size_t)k * sizeof(xg_request), hipMemcpyHostToDevice, l.stream) !=
           hipSuccess ||
       hipMemcpyAsync(l.d_groups, l.h_groups, ((size_t)num_groups + 1) * sizeof(uint32_t),
                      hipMemcpyHostToDevice, l.stream) != hipSuccess)
     return XG_EHIP;
-  st = xg_generate_batch(s->ctx, l.d_reqs, k, l.d_groups, num_groups, s->d_pool, s->pool_elems,
-                         s->default_tune ? nullptr : &s->tune, l.d_work, l.stream);
-  if (st != XG_OK) return st;
+  xg::Shape shape = xg::kDefaultBatch;
+  if (!s->default_tune)
+    shape = xg::Shape{s->tune.waves_per_block, s->tune.unroll, s->tune.blocks_per_cu,
+                      s->tune.store_words ? s->tune.store_words : (s->tune.unroll >= 4 ? 4u : 1u)};
+  xg::SegmentArgs seg{s->d_jump, s->seg_words, s->d_jump ? kJumpEntries : 0u, l.d_stage, s->max_batch};
+  if (xg::launch_batch(shape, s->ctx->num_cus, s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_groups,
+                       num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream,
+                       s->seg_words ? &seg : nullptr) != hipSuccess)
+    return XG_EHIP;
+  if (slots && xg::launch_commit(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, seg, l.stream) != hipSuccess)
+    return XG_EHIP;
   if (hipEventRecord(l.done, l.stream) != hipSuccess) return XG_EHIP;
   l.t_launch = now_ns();
   for (xg_completion &c : l.reqs) c.t_launch_ns = l.t_launch;
   l.busy = true;
-  *admitted = k;
+  *admitted = nreq;
   ++s->stats.batches;
-  s->stats.admitted += k;
-  s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, k);
+  s->stats.admitted += nreq;
+  s->stats.max_batch_seen = std::max<uint64_t>(s->stats.max_batch_seen, nreq);
   s->stats.pool_high_water = std::max<uint64_t>(s->stats.pool_high_water, s->pool.used());
   uint64_t busy = 0;
   for (const Lane &x : s->lanes) busy += x.busy;
@@ -259,7 +303,8 @@ extern "C" {
 
 size_t xg_server_device_bytes(const xg_server_config *cfg) {
   if (!config_valid(cfg)) return 0;
-  return table_layout(cfg->max_batch).per_lane * cfg->num_lanes;
+  const TableLayout t = table_layout(cfg);
+  return t.per_lane * cfg->num_lanes + t.jump;
 }
 
 xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config *cfg, void *d_pool,
@@ -315,15 +360,32 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
       s->pos[i] = (uint64_t)w[130] | ((uint64_t)w[131] << 32);
     }
   }
-  const TableLayout tl = table_layout(cfg->max_batch);
+  const TableLayout tl = table_layout(cfg);
   s->lanes.resize(cfg->num_lanes);
   char *base = static_cast<char *>(d_tables);
+  if (cfg->segment_words) {
+    // z^(k L) mod P for k = 1 .. kJumpEntries, computed on the host once.
+    s->seg_words = cfg->segment_words;
+    s->d_jump = reinterpret_cast<uint64_t *>(base + tl.per_lane * cfg->num_lanes);
+    std::vector<uint64_t> table((size_t)kJumpEntries * 64);
+    for (uint32_t k = 1; k <= kJumpEntries; ++k) {
+      if (!xg::jump_polynomial((uint64_t)k * cfg->segment_words, table.data() + (size_t)(k - 1) * 64)) {
+        delete s;
+        return XG_ENOTSUP;
+      }
+    }
+    if (hipMemcpy(s->d_jump, table.data(), table.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) {
+      delete s;
+      return XG_EHIP;
+    }
+  }
   for (uint32_t li = 0; li < cfg->num_lanes; ++li) {
     Lane &l = s->lanes[li];
     char *lb = base + li * tl.per_lane;
     l.d_reqs = reinterpret_cast<xg_request *>(lb);
     l.d_groups = reinterpret_cast<uint32_t *>(lb + tl.reqs);
     l.d_work = reinterpret_cast<uint32_t *>(lb + tl.reqs + tl.groups);
+    l.d_stage = tl.stage ? reinterpret_cast<uint32_t *>(lb + tl.reqs + tl.groups + tl.work) : nullptr;
     l.h_scratch = new (std::nothrow) xg_request[cfg->max_batch];
     if (!l.h_scratch || hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||

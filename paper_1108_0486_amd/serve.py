@@ -35,13 +35,15 @@ class Completion:
 
 class Server:
     def __init__(self, streams: XorgensStreams, pool_elems: int, num_lanes: int = 4, max_batch: int = 1024,
-                 tune=None):
+                 tune=None, segment_words: int = 0):
         self.streams = streams
         self.pool = torch.empty(pool_elems, dtype=torch.int32, device=streams.device)
-        nbytes = xg.xg_server_device_bytes(num_lanes, max_batch)
+        nbytes = xg.xg_server_device_bytes(num_lanes, max_batch, segment_words)
+        if nbytes == 0:
+            raise ValueError("invalid server configuration")
         self.tables = torch.empty(nbytes, dtype=torch.uint8, device=streams.device)
         self.srv = xg.xg_server_create(streams.ctx, num_lanes, max_batch, tune, self.pool.data_ptr(), pool_elems,
-                                       self.tables.data_ptr(), nbytes)
+                                       self.tables.data_ptr(), nbytes, segment_words)
         self._cap = 4096
         self._buf = (xg.xg_completion * self._cap)()
 

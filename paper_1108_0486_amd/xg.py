@@ -55,7 +55,8 @@ class xg_tune(ctypes.Structure):
 
 
 class xg_server_config(ctypes.Structure):
-    _fields_ = [("num_lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("tune", xg_tune)]
+    _fields_ = [("num_lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("tune", xg_tune),
+                ("segment_words", ctypes.c_uint64)]
 
 
 class xg_completion(ctypes.Structure):
@@ -269,14 +270,14 @@ def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups
 
 # ---- serving -----------------------------------------------------------------
 
-def xg_server_device_bytes(num_lanes: int, max_batch: int) -> int:
-    cfg = xg_server_config(num_lanes, max_batch, xg_tune())
+def xg_server_device_bytes(num_lanes: int, max_batch: int, segment_words: int = 0) -> int:
+    cfg = xg_server_config(num_lanes, max_batch, xg_tune(), segment_words)
     return int(lib().xg_server_device_bytes(ctypes.byref(cfg)))
 
 
 def xg_server_create(ctx, num_lanes: int, max_batch: int, tune, d_pool: int, pool_elems: int,
-                     d_tables: int, tables_bytes: int):
-    cfg = xg_server_config(num_lanes, max_batch, xg_tune() if tune is None else xg_tune.of(tune))
+                     d_tables: int, tables_bytes: int, segment_words: int = 0):
+    cfg = xg_server_config(num_lanes, max_batch, xg_tune() if tune is None else xg_tune.of(tune), segment_words)
     srv = ctypes.c_void_p()
     _check(lib().xg_server_create(ctypes.byref(srv), ctx, ctypes.byref(cfg), d_pool, pool_elems, d_tables,
                                   tables_bytes), "xg_server_create")

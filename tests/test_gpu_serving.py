@@ -129,3 +129,48 @@ def test_plain_fifo_baseline_runs():
     trace = W.serving_trace(50, num_streams=S, rate=20_000.0, seed=2, lo_exp=8, hi_exp=14)
     summary = run_trace_plain_fifo(gs, trace, max_n=1 << 14)
     assert summary["requests"] == 50 and summary["p99_ms"] > 0
+
+
+@pytest.mark.parametrize("seg", [4096, 1 << 14])
+def test_segmented_serving_matches_oracle(seg):
+    """Requests longer than the segment length run as jumped segments on
+    separate wavefronts; every value still equals the oracle's from the
+    request's start position, and the stream ends where the unsplit request
+    would leave it."""
+    S = 24
+    gs = XorgensStreams(S, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 22, num_lanes=4, max_batch=512, segment_words=seg)
+    trace = W.serving_trace(150, num_streams=S, rate=30_000.0, seed=21, lo_exp=6, hi_exp=17)
+    trace[0].n, trace[0].dtype = (1 << 20) + 77, 2          # long, odd normal request
+    trace[1].n, trace[1].dtype = 5 * seg, 0                # an exact multiple of the segment
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True)
+    assert summary["server"]["completed"] == 150
+    _check_against_oracle(done, outputs, S)
+    _, _, pos = gs.host_state()
+    want = np.zeros(S, dtype=np.uint64)
+    for c in done:
+        want[c.stream] = max(want[c.stream], c.start_pos + c.n + (c.n & 1 if c.dtype == 2 else 0))
+    assert (pos == want).all()
+    srv.close()
+
+
+def test_segmented_alone_equals_in_the_mix():
+    S = 16
+    gs = XorgensStreams(S, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 22, num_lanes=2, max_batch=256, segment_words=8192)
+    trace = W.serving_trace(60, num_streams=S, rate=20_000.0, seed=4, lo_exp=10, hi_exp=17)
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True)
+    srv.close()
+    for c in sorted(done, key=lambda c: -c.n)[:10]:
+        alone = XorgensStreams(1, seed=SEED + c.stream)
+        if c.start_pos:
+            alone.skip(c.start_pos)
+        ref = {0: alone.u32, 1: alone.f32, 2: alone.normal}[c.dtype](c.n)[0]
+        assert torch.equal(ref.view(torch.int32), outputs[c.id].view(torch.int32)), c
+
+
+def test_invalid_segment_length_rejected():
+    gs = XorgensStreams(4, seed=SEED)
+    for seg in (100, 64, 1 << 31):
+        with pytest.raises(ValueError):
+            Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4, segment_words=seg)
