@@ -213,6 +213,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the ragged-batch, fused-moments and serving measurements")
     ap.add_argument("--serve-requests", type=int, default=200_000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -281,6 +283,13 @@ def main() -> int:
         fill_ms.append(a.elapsed_time(b))
     fill_gbs = bytes_per_launch / (sorted(fill_ms)[2] * 1e-3) / 1e9
 
+    if args.calibrate_copy:
+        src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     traffic = measured_traffic()
     threads = max(1, min(16, os.cpu_count() or 1))
     cpu = None if args.no_cpu_baseline else cpu_baseline(threads)
