@@ -1,0 +1,102 @@
+"""A small statistical battery (a regression guard, not TestU01) and the
+paper's linearity claim.
+
+Section 1.5: an xorgens x-part alone is GF(2)-linear, and adding a Weyl
+sequence with an integer add (Eq. (1)) removes that linearity.  The linear
+complexity of one output bit shows it directly: 4096 for the x-part (its
+minimal polynomial is the degree-4096 characteristic polynomial), about N/2
+for N bits of the combined output, as for a random sequence.
+
+The other checks use thresholds with false-alarm probabilities far below
+1e-6, so they flag gross defects (a stuck bit, a broken lag, correlated
+streams) without flaking.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+
+def _bits(words: np.ndarray, bit: int) -> np.ndarray:
+    return ((words >> np.uint32(bit)) & np.uint32(1)).astype(np.uint8)
+
+
+def test_weyl_combination_removes_linearity():
+    N = 20000
+    st = O.OracleStreams(42, 1)
+    ring = st.ring[0].copy()
+    out = st.u32(N)[0]
+    _, xbits = O.xpart_run(O.PAPER, ring, N, bit=0, want_bits=True)
+    lc_x = O.berlekamp_massey(xbits).bit_length() - 1
+    assert lc_x == 4096
+    for bit in (0, 15, 31):
+        lc = O.berlekamp_massey(_bits(out, bit)).bit_length() - 1
+        assert abs(lc - N / 2) <= 12, (bit, lc)   # random sequences: N/2 +- a few
+
+
+def battery(words: np.ndarray) -> dict:
+    """Monobit, byte chi-square, runs, lag-1 serial correlation, uniform moments."""
+    words = np.ascontiguousarray(words, dtype=np.uint32).ravel()
+    n = words.size
+    res = {}
+    ones = int(np.unpackbits(words.view(np.uint8)).sum())
+    nbits = 32 * n
+    res["monobit_z"] = (ones - nbits / 2) / math.sqrt(nbits / 4)
+    counts = np.bincount(words.view(np.uint8), minlength=256).astype(np.float64)
+    e = counts.sum() / 256
+    res["byte_chi2"] = float(((counts - e) ** 2 / e).sum())            # 255 dof
+    b0 = _bits(words, 0).astype(np.int8)
+    runs = 1 + int(np.count_nonzero(b0[1:] != b0[:-1]))
+    pi = b0.mean()
+    res["runs_z"] = (runs - 2 * n * pi * (1 - pi)) / (2 * math.sqrt(n) * pi * (1 - pi))
+    u = words.astype(np.float64) / 2**32
+    res["serial_r"] = float(np.corrcoef(u[:-1], u[1:])[0, 1]) * math.sqrt(n - 1)
+    res["mean_z"] = (u.mean() - 0.5) / math.sqrt(1 / 12 / n)
+    res["var_z"] = (u.var() - 1 / 12) / math.sqrt(1 / 180 / n)
+    return res
+
+
+def assert_battery(res: dict):
+    assert abs(res["monobit_z"]) < 6, res
+    assert 150 < res["byte_chi2"] < 400, res          # 255 dof: both tails beyond 1e-6
+    assert abs(res["runs_z"]) < 6, res
+    assert abs(res["serial_r"]) < 6, res
+    assert abs(res["mean_z"]) < 6, res
+    assert abs(res["var_z"]) < 6, res
+
+
+def test_battery_on_oracle_stream():
+    assert_battery(battery(O.OracleStreams(42, 1).u32(1 << 22)[0]))
+
+
+def test_battery_catches_a_stuck_bit():
+    w = O.OracleStreams(42, 1).u32(1 << 20)[0] | np.uint32(1 << 7)
+    with pytest.raises(AssertionError):
+        assert_battery(battery(w))
+
+
+def test_consecutive_seeds_are_uncorrelated():
+    """Section 4: blocks are seeded with consecutive values; the seeding must
+    keep neighbouring streams apart."""
+    u = O.OracleStreams(42, 64).u32(1 << 14).astype(np.float64) / 2**32
+    r = np.corrcoef(u)                      # 64 x 64 stream correlations
+    off = r[~np.eye(64, dtype=bool)]
+    assert np.abs(off).max() * math.sqrt(u.shape[1]) < 6
+    # the xor of neighbouring streams is still balanced bit by bit
+    x = (O.OracleStreams(42, 2).u32(1 << 18))
+    assert_battery(battery(x[0] ^ x[1]))
+
+
+@pytest.mark.gpu
+def test_battery_on_gpu_bulk_fill():
+    torch = pytest.importorskip("torch")
+    from gpu_helpers import HAVE_GPU
+    if not HAVE_GPU:
+        pytest.skip("no GPU visible")
+    from paper_1108_0486_amd.streams import XorgensStreams, as_u32
+    gs = XorgensStreams(1024, seed=42)
+    flat = as_u32(gs.fill_u32(1 << 16))
+    assert_battery(battery(flat))
+    del torch
