@@ -162,6 +162,13 @@ xg_status xg_fill_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
 xg_status xg_generate_normal(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                              float *d_out, void *stream);
 
+/* The Box-Muller map of xg_generate_normal on caller-supplied words: for
+ * m < pairs, d_out[2m] and d_out[2m + 1] are z_0 and z_1 of the pair
+ * (d_words[2m], d_words[2m + 1]), computed by the same device code.  Lets a
+ * caller (or a test) apply the map to any words, e.g. every possible u1.
+ * Errors: XG_EINVAL (NULL with pairs > 0), XG_ERANGE, XG_EALIGN, XG_EHIP. */
+xg_status xg_box_muller(const uint32_t *d_words, uint64_t pairs, float *d_out, void *stream);
+
 /* Fused generate-and-consume: each stream draws n normals exactly as
  * xg_generate_normal would (the same values, never written to memory) and
  * reduces them in-kernel to

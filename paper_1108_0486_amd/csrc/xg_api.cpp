@@ -261,6 +261,15 @@ xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void 
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
+xg_status xg_box_muller(const uint32_t *d_words, uint64_t pairs, float *d_out, void *stream) {
+  if (pairs == 0) return XG_OK;
+  if (!d_words || !d_out) return XG_EINVAL;
+  if (pairs > (UINT64_MAX / 16) || pairs / 256 >= 0xFFFFFFFFull) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(d_words) % 4 || reinterpret_cast<uintptr_t>(d_out) % 4) return XG_EALIGN;
+  return xg::launch_box_muller(d_words, pairs, d_out, static_cast<hipStream_t>(stream)) == hipSuccess ? XG_OK
+                                                                                                      : XG_EHIP;
+}
+
 xg_status xg_jump_polynomial(uint64_t J, uint64_t *h_g) {
   if (!h_g) return XG_EINVAL;
   return xg::jump_polynomial(J, h_g) ? XG_OK : XG_ENOTSUP;

@@ -42,6 +42,8 @@ hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint6
 hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t first, uint64_t count,
                        uint64_t n, uint32_t *out, hipStream_t stream);
 
+hipError_t launch_box_muller(const uint32_t *words, uint64_t pairs, float *out, hipStream_t stream);
+
 // Jump polynomial z^J mod P of the x-part's characteristic polynomial
 // (4096 bits, little-endian words).  False if P could not be derived.
 bool jump_polynomial(uint64_t J, uint64_t g[64]);

@@ -616,6 +616,18 @@ __global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ state, uint
   }
 }
 
+// Box-Muller on caller-supplied word pairs (the same device function the
+// generators use): out[2m], out[2m + 1] from words[2m], words[2m + 1].
+__global__ __launch_bounds__(256) void k_box_muller(const uint32_t *__restrict__ words, uint64_t pairs,
+                                                    float *__restrict__ out) {
+  const uint64_t m = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= pairs) return;
+  float z0, z1;
+  box_muller(words[2 * m], words[2 * m + 1], z0, z1);
+  out[2 * m] = z0;
+  out[2 * m + 1] = z1;
+}
+
 __global__ void k_clear_work(uint32_t *work) {
   if (threadIdx.x < 64) work[threadIdx.x] = 0u;
 }
@@ -766,6 +778,11 @@ hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t 
              else hipLaunchKernelGGL((k_fill<kU32, 8>), grid, block, 0, stream, state, first, count, n, out);
              break;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_box_muller(const uint32_t *words, uint64_t pairs, float *out, hipStream_t stream) {
+  hipLaunchKernelGGL(k_box_muller, dim3((uint32_t)((pairs + 255) / 256)), dim3(256), 0, stream, words, pairs, out);
   return hipGetLastError();
 }
 

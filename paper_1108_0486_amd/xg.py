@@ -103,6 +103,7 @@ def lib() -> ctypes.CDLL:
         "xg_normal_moments": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_fill_u32": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_skip": (st, [vp, u64, u64, u64, vp]),
+        "xg_box_muller": (st, [vp, u64, vp, vp]),
         "xg_jump_polynomial": (st, [u64, P(u64)]),
         "xg_fill_f32": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
@@ -213,6 +214,10 @@ def fill_index(count: int, n: int):
     head = (t // 64) * 64 * count + k * 64 + t % 64
     tail = 64 * full * count + k * rem + (t - 64 * full)
     return np.where(t < 64 * full, head, tail)
+
+
+def xg_box_muller(d_words: int, pairs: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_box_muller(d_words, pairs, d_out, stream), "xg_box_muller")
 
 
 def xg_skip(ctx, first: int, count: int, J: int, stream: int = 0) -> None:
