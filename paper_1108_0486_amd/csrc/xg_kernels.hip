@@ -324,12 +324,55 @@ __device__ __forceinline__ void serve_words_fill(uint32_t *__restrict__ st, uint
 // ---------------------------------------------------------------------------
 // normals: Box-Muller on consecutive output pairs of the call.
 // ---------------------------------------------------------------------------
+// sin(pi x) and cos(pi x) for x = 2 u2 in [0, 2), a multiple of 2^-23.  The
+// argument is reduced exactly: 2x = q + 2f with q = rint(2x), |f| <= 1/4, so
+// pi x = q pi / 2 + pi f.  sin(pi f) and cos(pi f) come from their Taylor
+// series in t = f^2 (the first omitted terms are below 2e-9 and 1.2e-10
+// relative at |f| = 1/4), the leading pi f of the sine formed with pi split
+// as pi_hi + pi_lo so that it is rounded once.  A quarter-turn rotation by q
+// finishes.  f = 0 gives exact zeros and ones.
+constexpr double kPi = 3.14159265358979323846;
+constexpr float kPiHi = (float)kPi;
+constexpr float kPiLo = (float)(kPi - (double)kPiHi);
+constexpr float kS3 = (float)(-kPi * kPi * kPi / 6.0);
+constexpr float kS5 = (float)(kPi * kPi * kPi * kPi * kPi / 120.0);
+constexpr float kS7 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi / 5040.0);
+constexpr float kS9 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 362880.0);
+constexpr float kC2 = (float)(-kPi * kPi / 2.0);
+constexpr float kC4 = (float)(kPi * kPi * kPi * kPi / 24.0);
+constexpr float kC6 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 720.0);
+constexpr float kC8 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 40320.0);
+constexpr float kC10 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 3628800.0);
+
+__device__ __forceinline__ void sincospi_unit(float x, float &s, float &c) {
+  const float y = 2.0f * x;            // exact
+  const float q = rintf(y);            // exact integer 0 .. 4
+  const float f = (y - q) * 0.5f;      // exact, |f| <= 1/4
+  const float t = f * f;
+  float p = fmaf(kS9, t, kS7);
+  p = fmaf(p, t, kS5);
+  p = fmaf(p, t, kS3);
+  const float tail = fmaf(p, t, kPiLo);          // pi_lo + t (S3 + t (S5 + t (S7 + t S9)))
+  const float sp = fmaf(f, kPiHi, f * tail);     // sin(pi f)
+  float r = fmaf(kC10, t, kC8);
+  r = fmaf(r, t, kC6);
+  r = fmaf(r, t, kC4);
+  r = fmaf(r, t, kC2);
+  const float cp = fmaf(r, t, 1.0f);             // cos(pi f)
+  const uint32_t qi = (uint32_t)(int)q;
+  const bool odd = (qi & 1u) != 0;
+  const float s0 = odd ? cp : sp, c0 = odd ? sp : cp;
+  // sin is negated in quadrants 2, 3; cos in quadrants 1, 2
+  s = __uint_as_float(__float_as_uint(s0) ^ ((qi & 2u) << 30));
+  c = __uint_as_float(__float_as_uint(c0) ^ (((qi + 1u) & 2u) << 30));
+}
+
 __device__ __forceinline__ void box_muller(uint32_t e, uint32_t o, float &z0, float &z1) {
   const float u1 = (float)((e >> 8) + 1u) * 0x1p-24f;  // (0, 1], exact
   const float u2 = (float)(o >> 8) * 0x1p-24f;         // [0, 1), exact
   const float rho = sqrtf(-2.0f * logf(u1));
   float s, c;
-  sincospif(2.0f * u2, &s, &c);                        // angle 2 pi u2 reduced exactly
+  sincospi_unit(2.0f * u2, s, c);                      // angle 2 pi u2 reduced exactly
   z0 = rho * c;
   z1 = rho * s;
 }
@@ -357,30 +400,32 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
   s = t;
 }
 
-// Stores (or accumulates) normals idx and idx + 1 of the call.  `pair_aligned`
+// Stores (or accumulates) normals idx and idx + 1 of the call.  CHECKED
+// compares them with n (blocks wholly inside n skip that).  `pair_aligned`
 // (wave-uniform) says out is 8-byte aligned, so a pair is one 8-byte store.
-template <bool MOMENTS>
+template <bool MOMENTS, bool CHECKED>
 __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t idx, uint64_t n,
                                              float *__restrict__ out, bool pair_aligned,
                                              Moments &m) {
   float z0, z1;
   box_muller(e, o, z0, z1);
+  const bool has0 = !CHECKED || idx < n, has1 = !CHECKED || idx + 1 < n;
   if constexpr (MOMENTS) {
-    if (idx < n) {
+    if (has0) {
       kahan_add(m.s1, m.c1, z0);
       kahan_add(m.s2, m.c2, z0 * z0);
     }
-    if (idx + 1 < n) {
+    if (has1) {
       kahan_add(m.s1, m.c1, z1);
       kahan_add(m.s2, m.c2, z1 * z1);
     }
   } else {
-    if (pair_aligned && idx + 1 < n) {
+    if (pair_aligned && has1) {
       const f32x2 pair = {z0, z1};
       __builtin_nontemporal_store(pair, reinterpret_cast<f32x2 *>(out + idx));
     } else {
-      if (idx < n) __builtin_nontemporal_store(z0, out + idx);
-      if (idx + 1 < n) __builtin_nontemporal_store(z1, out + idx + 1);
+      if (has0) __builtin_nontemporal_store(z0, out + idx);
+      if (has1) __builtin_nontemporal_store(z1, out + idx + 1);
     }
   }
 }
@@ -402,7 +447,8 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
   const uint32_t rw = (uint32_t)(words & 127u);
   Moments m = {0.f, 0.f, 0.f, 0.f};
   const bool pair_aligned = (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
-  const uint64_t nouter = nblk / UNROLL;
+  const uint64_t nsafe = n >> 7;        // blocks whose 128 normals are all below n
+  const uint64_t nouter = nsafe / UNROLL;
   uint64_t b = 0;
   for (uint64_t it = 0; it != nouter; ++it, b += UNROLL) {
 #pragma unroll
@@ -415,8 +461,19 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
       wbase += kChunkOmega;
       uint32_t e, o;
       gather_pair(oa, ob, lane, e, o);
-      consume_pair<MOMENTS>(e, o, ((b + u) << 7) + 2u * lane, n, out, pair_aligned, m);
+      consume_pair<MOMENTS, false>(e, o, ((b + u) << 7) + 2u * lane, n, out, pair_aligned, m);
     }
+  }
+  for (; b != nsafe; ++b) {
+    const uint32_t xa = ring_step(g, lane0);
+    const uint32_t oa = xa + temper_weyl(wbase + wlane);
+    wbase += kChunkOmega;
+    const uint32_t xb = ring_step(g, lane0);
+    const uint32_t ob = xb + temper_weyl(wbase + wlane);
+    wbase += kChunkOmega;
+    uint32_t e, o;
+    gather_pair(oa, ob, lane, e, o);
+    consume_pair<MOMENTS, false>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
   }
   for (; b != nblk; ++b) {
     const uint32_t xa = ring_step(g, lane0);
@@ -427,7 +484,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     wbase += kChunkOmega;
     uint32_t e, o;
     gather_pair(oa, ob, lane, e, o);
-    consume_pair<MOMENTS>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
+    consume_pair<MOMENTS, true>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
   }
   // Tail: rw (even, < 128) more words.
   uint32_t p0 = g.prev, c0 = g.cur, xl = 0u, rem = 0u;
@@ -452,7 +509,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     }
     uint32_t e, o;
     gather_pair(oa, ob, lane, e, o);
-    if (2u * lane < rw) consume_pair<MOMENTS>(e, o, (nblk << 7) + 2u * lane, n, out, pair_aligned, m);
+    if (2u * lane < rw) consume_pair<MOMENTS, true>(e, o, (nblk << 7) + 2u * lane, n, out, pair_aligned, m);
   }
   write_state(dst, p0, c0, xl, rem, w_start + (uint32_t)words * kOmega, pos + words, lane);
   if constexpr (MOMENTS) {
