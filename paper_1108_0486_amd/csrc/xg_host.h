@@ -1,0 +1,32 @@
+// Host-only internals of libxg (no HIP): the batch planner and the jump
+// polynomials.  Kept free of HIP headers so that they also build with a plain
+// host compiler (the sanitizer tests do that).
+#pragma once
+
+#include <stdint.h>
+
+#include "xg.h"
+
+namespace xg {
+
+// Request flags of server-built tables (the public batch call takes flags 0).
+// A segment covers words [k L, k L + n') of a longer request on its stream: it
+// reads the stream's state, jumps by k L (jump_table entry k - 1 holds
+// z^(k L) mod P) and generates its n values; it never writes the stream's
+// state.  The last segment writes the end state to staging slot (flags >> 16),
+// which k_commit copies into the stream's state after the batch.
+constexpr uint32_t kReqSegment = 1u;
+constexpr uint32_t kReqLast = 2u;
+constexpr uint32_t kReqUndefinedBits = 0x000000FCu;
+constexpr uint32_t kMaxSegments = 256;  // k in 0 .. 255
+
+// xg_plan_batch, with segment requests (kReqSegment) allowed when
+// allow_segments: each forms its own group.
+xg_status plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_streams, uint64_t out_elems,
+                     xg_request *h_sorted, uint32_t *h_groups, uint32_t *num_groups, bool allow_segments);
+
+// Jump polynomial z^J mod P of the x-part's characteristic polynomial
+// (4096 bits, little-endian words).  False if P could not be derived.
+bool jump_polynomial(uint64_t J, uint64_t g[64]);
+
+}  // namespace xg

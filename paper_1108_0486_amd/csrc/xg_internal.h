@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "xg.h"
+#include "xg_host.h"
 
 namespace xg {
 
@@ -44,10 +45,6 @@ hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t 
 
 hipError_t launch_box_muller(const uint32_t *words, uint64_t pairs, float *out, hipStream_t stream);
 
-// Jump polynomial z^J mod P of the x-part's characteristic polynomial
-// (4096 bits, little-endian words).  False if P could not be derived.
-bool jump_polynomial(uint64_t J, uint64_t g[64]);
-
 // Skips below this many words step through them; longer skips jump.
 constexpr uint64_t kJumpThreshold = 1ull << 15;
 
@@ -59,17 +56,6 @@ struct JumpPoly {
 // g == nullptr, else by evaluating g(T) on each state (g = z^J mod P).
 hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
                        hipStream_t stream);
-
-// Request flags of server-built tables (the public batch call takes flags 0).
-// A segment covers words [k L, k L + n') of a longer request on its stream: it
-// reads the stream's state, jumps by k L (jump_table entry k - 1 holds
-// z^(k L) mod P) and generates its n values; it never writes the stream's
-// state.  The last segment writes the end state to staging slot (flags >> 16),
-// which k_commit copies into the stream's state after the batch.
-constexpr uint32_t kReqSegment = 1u;
-constexpr uint32_t kReqLast = 2u;
-constexpr uint32_t kReqUndefinedBits = 0x000000FCu;
-constexpr uint32_t kMaxSegments = 256;  // k in 0 .. 255
 
 struct SegmentArgs {
   const uint64_t *jump_table;  // (max_k) x 64 words
@@ -89,10 +75,6 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
 hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
                          const SegmentArgs &seg, hipStream_t stream);
 
-// xg_plan_batch, with segment requests (kReqSegment) allowed: each forms its
-// own group.
-xg_status plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_streams, uint64_t out_elems,
-                     xg_request *h_sorted, uint32_t *h_groups, uint32_t *num_groups, bool allow_segments);
 
 }  // namespace xg
 

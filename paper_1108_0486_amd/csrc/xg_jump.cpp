@@ -14,7 +14,7 @@
 #include <mutex>
 #include <vector>
 
-#include "xg_internal.h"
+#include "xg_host.h"
 
 namespace xg {
 namespace {

@@ -1,0 +1,59 @@
+"""Host code under AddressSanitizer and UndefinedBehaviorSanitizer (CPU only).
+
+Two small driver programs are built with gcc/g++ and -fsanitize=address,
+undefined (any report aborts the program):
+  * the C oracle (seeding, every request kind on several threads, the x-part
+    stepping, Berlekamp-Massey, primitivity, polynomial jump-ahead);
+  * libxg's host-only sources (the batch planner and the jump polynomials,
+    which include no HIP header), whose jump polynomials must also equal the
+    oracle's z^J mod P.
+"""
+import os
+import shutil
+import subprocess
+
+import pytest
+
+from oracle import oracle as O
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+CSRC = os.path.join(ROOT, "paper_1108_0486_amd", "csrc")
+SAN = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=all", "-fno-omit-frame-pointer"]
+ENV = dict(os.environ, ASAN_OPTIONS="detect_leaks=1:abort_on_error=0", UBSAN_OPTIONS="print_stacktrace=1")
+
+
+def _need(tool):
+    if shutil.which(tool) is None:
+        pytest.skip(f"{tool} not available")
+
+
+def _run(cmd, tmp_path, *args):
+    exe = str(tmp_path / "a.out")
+    subprocess.run(cmd + ["-o", exe], check=True, cwd=ROOT)
+    p = subprocess.run([exe, *args], capture_output=True, text=True, timeout=120, env=ENV)
+    assert p.returncode == 0 and p.stdout.rstrip().endswith("OK"), p.stdout + p.stderr
+    assert "runtime error" not in p.stderr and "Sanitizer" not in p.stderr, p.stderr
+    return p.stdout
+
+
+def test_oracle_under_sanitizers(tmp_path):
+    _need("gcc")
+    cmd = ["gcc", "-std=gnu11", "-mpclmul", "-msse4.1", *SAN, os.path.join(HERE, "sanitize", "oracle_driver.c"),
+           os.path.join(ROOT, "oracle", "xorgens_oracle.c"), os.path.join(ROOT, "oracle", "gf2.c"),
+           "-lpthread", "-lm"]
+    _run(cmd, tmp_path)
+
+
+def test_host_library_code_under_sanitizers(tmp_path):
+    _need("g++")
+    cmd = ["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(HERE, "sanitize", "host_driver.cpp"), os.path.join(CSRC, "xg_plan.cpp"),
+           os.path.join(CSRC, "xg_jump.cpp")]
+    Js = [1, 63, 4095, 4096, 4097, 123456789, 10**12, (1 << 64) - 1]
+    out = _run(cmd, tmp_path, *map(str, Js))
+    P = O.charpoly(O.PAPER)
+    got = {int(t[1]): int(t[2], 16) for t in (l.split() for l in out.splitlines()) if t and t[0] == "J"}
+    assert sorted(got) == sorted(Js)
+    for J in Js:
+        assert got[J] == O.z_pow_mod(J, P), J
