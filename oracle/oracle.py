@@ -1,4 +1,5 @@
-"""Python face of the CPU oracle (plain C in xorgens_oracle.c and gf2.c).
+"""Python face of the CPU oracle (plain C in xorgens_oracle.c, xorgens64_oracle.c
+and gf2.c).
 
 TEST INFRASTRUCTURE ONLY: imported by tests/, by __graft_entry__.smoke() and
 by the CPU-baseline leg of bench.py.  The product package never imports it,
@@ -26,7 +27,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_SOURCES = ("xorgens_oracle.c", "gf2.c")
+_SOURCES = ("xorgens_oracle.c", "xorgens64_oracle.c", "gf2.c")
 
 U32, F32, NORMAL, MOMENTS, SKIP = 0, 1, 2, 3, 4
 
@@ -47,6 +48,11 @@ class _Params(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint32) for n in ("w", "r", "s", "a", "b", "c", "d", "gamma", "omega")]
 
 
+class _Params64(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint32) for n in ("w", "r", "s", "a", "b", "c", "d", "gamma")] + \
+        [("omega", ctypes.c_uint64)]
+
+
 @dataclass(frozen=True)
 class Params:
     """A member of the xorgens family: word size w, lags r > s, shifts a..d,
@@ -65,7 +71,9 @@ class Params:
     def n(self) -> int:
         return self.r * self.w
 
-    def c_struct(self) -> _Params:
+    def c_struct(self):
+        if self.w == 64:
+            return _Params64(self.w, self.r, self.s, self.a, self.b, self.c, self.d, self.gamma, self.omega)
         return _Params(self.w, self.r, self.s, self.a, self.b, self.c, self.d, self.gamma,
                        self.omega & 0xFFFFFFFF)
 
@@ -74,6 +82,14 @@ class Params:
 # integer nearest 2^31 (sqrt(5) - 1) (Section 1.5); gamma = w / 2 (Section 1.5
 # asks for a value close to w / 2).
 PAPER = Params(w=32, r=128, s=65, a=15, b=14, c=12, d=17, gamma=16, omega=0x9E3779B9)
+
+# Further members (Section 1.5: n = r w any power of two up to 4096; Section 2:
+# s = r/2 +- 1 for the GPU).  The paper gives no shifts for them: these are
+# the choices of family_search.py (shifts in [w/4, 3w/4], seeded order, the
+# primitive candidate whose characteristic polynomial weight is nearest n/2),
+# and the tests pin each by primitivity.
+R64 = Params(w=32, r=64, s=33, a=19, b=19, c=9, d=18, gamma=16, omega=0x9E3779B9)
+W64 = Params(w=64, r=64, s=33, a=24, b=22, c=37, d=45, gamma=32, omega=0x9E3779B97F4A7C15)
 
 _lib = None
 
@@ -101,6 +117,13 @@ def lib() -> ctypes.CDLL:
         L.xgo_full_period.restype = ctypes.c_uint64
         L.xgo_xpart_matrix.argtypes = [P(_Params), u64p]
         L.xgo_xpart_jump_poly.argtypes = [P(_Params), u32p, u64p]
+        P64 = P(_Params64)
+        L.xgo64_params_valid.argtypes = [P64]
+        L.xgo64_seed_streams.argtypes = [P64, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64, u64p, u64p, u64p]
+        L.xgo64_run_streams.argtypes = [P64, u64p, u64p, u64p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                                        ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int]
+        L.xgo64_xpart_run.argtypes = [P64, u64p, ctypes.c_uint64, ctypes.c_uint32, u8p]
+        L.xgo64_xpart_jump_poly.argtypes = [P64, u64p, u64p]
         L.gf2_clmul64.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p, u64p]
         L.gf2_clmul64_portable.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p, u64p]
         L.gf2_degree.argtypes = [u64p, ctypes.c_int]
@@ -199,6 +222,60 @@ class OracleStreams:
         self._run(SKIP, n, None, threads)
 
 
+class OracleStreams64:
+    """`count` streams of a 64-bit-word member (xorgens64_oracle.c); stream i
+    is seeded with seed + first + i.  ring[count, r] uint64, weyl, pos."""
+
+    def __init__(self, seed: int, count: int, params: "Params", first: int = 0):
+        if params.w != 64:
+            raise ValueError("OracleStreams64 needs w = 64")
+        self.params, self.count = params, count
+        self.ring = np.zeros((count, params.r), dtype=np.uint64)
+        self.weyl = np.zeros(count, dtype=np.uint64)
+        self.pos = np.zeros(count, dtype=np.uint64)
+        rc = lib().xgo64_seed_streams(ctypes.byref(params.c_struct()), seed & (2**64 - 1), first, count,
+                                      _ptr(self.ring, ctypes.c_uint64), _ptr(self.weyl, ctypes.c_uint64),
+                                      _ptr(self.pos, ctypes.c_uint64))
+        if rc != 0:
+            raise ValueError("invalid xorgens parameters")
+
+    @classmethod
+    def from_state(cls, ring, weyl, pos, params: "Params") -> "OracleStreams64":
+        self = cls.__new__(cls)
+        self.params = params
+        self.ring = np.ascontiguousarray(ring, dtype=np.uint64).reshape(-1, params.r).copy()
+        self.count = self.ring.shape[0]
+        self.weyl = np.ascontiguousarray(weyl, dtype=np.uint64).reshape(-1).copy()
+        self.pos = np.ascontiguousarray(pos, dtype=np.uint64).reshape(-1).copy()
+        return self
+
+    def copy(self) -> "OracleStreams64":
+        return OracleStreams64.from_state(self.ring, self.weyl, self.pos, self.params)
+
+    def _run(self, kind: int, n: int, out, threads):
+        stride = out.strides[0] if out is not None else 0
+        rc = lib().xgo64_run_streams(
+            ctypes.byref(self.params.c_struct()), _ptr(self.ring, ctypes.c_uint64),
+            _ptr(self.weyl, ctypes.c_uint64), _ptr(self.pos, ctypes.c_uint64), self.count, kind, n,
+            None if out is None else out.ctypes.data_as(ctypes.c_void_p), stride, threads or default_threads())
+        if rc != 0:
+            raise RuntimeError("oracle run failed (%d)" % rc)
+
+    def u64(self, n: int, threads: int | None = None) -> np.ndarray:
+        out = np.empty((self.count, n), dtype=np.uint64)
+        self._run(0, n, out, threads)
+        return out
+
+    def f64(self, n: int, threads: int | None = None) -> np.ndarray:
+        """(out >> 11) 2^-53 per word."""
+        out = np.empty((self.count, n), dtype=np.float64)
+        self._run(1, n, out, threads)
+        return out
+
+    def skip(self, n: int, threads: int | None = None) -> None:
+        self._run(SKIP, n, None, threads)
+
+
 def splitmix64_sequence(seed: int, k: int) -> list[int]:
     z = ctypes.c_uint64(seed & (2**64 - 1))
     return [int(lib().xgo_splitmix64(ctypes.byref(z))) for _ in range(k)]
@@ -217,6 +294,14 @@ def box_muller64(o_even: int, o_odd: int) -> tuple[float, float]:
 def xpart_run(params: Params, ring: np.ndarray, steps: int, bit: int = 0, want_bits: bool = False):
     """Steps one linear ring `steps` times (in place); optionally returns bit
     `bit` of every x_k produced."""
+    if params.w == 64:
+        ring = np.ascontiguousarray(ring, dtype=np.uint64)
+        bits = np.zeros(steps, dtype=np.uint8) if want_bits else None
+        rc = lib().xgo64_xpart_run(ctypes.byref(params.c_struct()), _ptr(ring, ctypes.c_uint64), steps, bit,
+                                   None if bits is None else _ptr(bits, ctypes.c_uint8))
+        if rc != 0:
+            raise ValueError("bad xpart_run arguments")
+        return ring, bits
     ring = np.ascontiguousarray(ring, dtype=np.uint32)
     cp = params.c_struct()
     bits = np.zeros(steps, dtype=np.uint8) if want_bits else None
@@ -279,8 +364,14 @@ def mat_pow_apply(M: np.ndarray, n: int, J: int, v: np.ndarray) -> np.ndarray:
 
 
 def xpart_jump_poly(params: Params, ring, g: np.ndarray) -> np.ndarray:
-    ring = np.ascontiguousarray(ring, dtype=np.uint32).copy()
     g = np.ascontiguousarray(g, dtype=np.uint64)
+    if params.w == 64:
+        ring = np.ascontiguousarray(ring, dtype=np.uint64).copy()
+        if lib().xgo64_xpart_jump_poly(ctypes.byref(params.c_struct()), _ptr(ring, ctypes.c_uint64),
+                                       _ptr(g, ctypes.c_uint64)) != 0:
+            raise ValueError("bad params")
+        return ring
+    ring = np.ascontiguousarray(ring, dtype=np.uint32).copy()
     rc = lib().xgo_xpart_jump_poly(ctypes.byref(params.c_struct()), _ptr(ring, ctypes.c_uint32),
                                    _ptr(g, ctypes.c_uint64))
     if rc != 0:
@@ -393,9 +484,10 @@ def charpoly(params: Params, ring=None, bit: int = 0, extra: int = 64) -> int:
     """Minimal polynomial of bit `bit` of the x-part sequence, from 2n + extra
     terms by Berlekamp-Massey.  For a nonzero start ring and a primitive
     characteristic polynomial it equals that polynomial."""
+    wt = np.uint64 if params.w == 64 else np.uint32
     if ring is None:
-        ring = np.arange(1, params.r + 1, dtype=np.uint32) & np.uint32((1 << params.w) - 1 if params.w < 32 else 0xFFFFFFFF)
-    _, bits = xpart_run(params, np.array(ring, dtype=np.uint32), 2 * params.n + extra, bit, want_bits=True)
+        ring = np.arange(1, params.r + 1, dtype=np.uint64) & np.uint64((1 << min(params.w, 64)) - 1)
+    _, bits = xpart_run(params, np.array(ring, dtype=wt), 2 * params.n + extra, bit, want_bits=True)
     return berlekamp_massey(bits)
 
 
