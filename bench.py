@@ -170,6 +170,51 @@ def extra_fused_moments(torch, dev):
             "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3)}
 
 
+def extra_family_members(torch, dev):
+    """The two further members (r = 64, s = 33; two streams per wavefront):
+    4 GiB per launch in the bulk-fill layout and stream-major, per output
+    type, at 2048 streams (1024 wavefronts, one per SIMD) and 1024 streams."""
+    from paper_1108_0486_amd import xg
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    res = {}
+    for fam, name, wbytes, kinds in [
+            (xg.XG_FAMILY_R64_W32, "r64_w32 (n=2048)", 4, ("u32", "f32")),
+            (xg.XG_FAMILY_R64_W64, "r64_w64 (n=4096)", 8, ("u64", "f64"))]:
+        rec = {}
+        for S in (2048, 1024):
+            n = (4 << 30) // (wbytes * S)
+            gs = XorgensStreams(S, seed=SEED, device=dev, family=fam)
+            dt = torch.int32 if wbytes == 4 else torch.int64
+            out = torch.empty(S * n, dtype=dt, device=dev)
+            row = {}
+            for kind in kinds:
+                for layout in ("fill", "stream_major"):
+                    f = getattr(gs, ("fill_" if layout == "fill" else "") + kind)
+                    o = out if layout == "fill" else out.view(S, n)
+                    if kind in ("f32", "f64"):
+                        o = o.view(torch.float32 if wbytes == 4 else torch.float64)
+                    for _ in range(3):
+                        f(n, out=o)
+                    reps = 20
+                    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                    torch.cuda.synchronize()
+                    a.record()
+                    for _ in range(reps):
+                        f(n, out=o)
+                    e.record()
+                    torch.cuda.synchronize()
+                    ms = a.elapsed_time(e) / reps
+                    gbs = wbytes * S * n / (ms * 1e-3) / 1e9
+                    row["%s_%s" % (layout, kind)] = {"ms": ms, "GBs": gbs, "frac_of_hbm_peak": gbs / HBM_PEAK_GBS,
+                                                     "values_per_s": S * n / (ms * 1e-3)}
+            rec["%d streams x %d" % (S, n)] = row
+            del out, gs
+            torch.cuda.empty_cache()
+        res[name] = rec
+    return res
+
+
 def extra_serving(torch, dev, num_requests: int):
     """10^5 device-resident streams; Poisson arrivals at 20k req/s (seed 11);
     N log-uniform in [2^8, 2^24]; dtype uniform over {u32, f32, normal};
@@ -307,6 +352,7 @@ def main() -> int:
     if not args.no_extras:
         extras = {"ragged_batch": extra_ragged_batch(torch, dev),
                   "fused_moments": extra_fused_moments(torch, dev),
+                  "family_members": extra_family_members(torch, dev),
                   "serving": extra_serving(torch, dev, args.serve_requests)}
 
     wpb, un, sw = gs.plain_tune()

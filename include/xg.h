@@ -55,7 +55,8 @@ typedef int32_t xg_status;
 #define XG_ERANGE   (-2)  /* stream range outside the context, or a size overflow  */
 #define XG_EALIGN   (-3)  /* device pointer not 4-byte (outputs) or 16-byte (state) aligned */
 #define XG_EHIP     (-4)  /* the HIP runtime reported an error */
-#define XG_ENOTSUP  (-5)  /* the current device is not gfx950 */
+#define XG_ENOTSUP  (-5)  /* the current device is not gfx950, or the stream family
+                              has no such operation */
 #define XG_ENOMEM   (-6)  /* a host-side allocation failed */
 #define XG_EBUSY    (-7)  /* workspace too small for the request table */
 
@@ -65,6 +66,26 @@ typedef int32_t xg_status;
 #define XG_U32     0u  /* out_k as uint32 */
 #define XG_F32     1u  /* (out_k >> 8) * 2^-24 as float, in [0, 1 - 2^-24]; exact */
 #define XG_NORMAL  2u  /* float standard normals by Box-Muller (see xg_generate_normal) */
+#define XG_U64     4u  /* out_k as uint64 (64-bit-word family only) */
+#define XG_F64     5u  /* (out_k >> 11) * 2^-53 as double, in [0, 1 - 2^-53]; exact */
+
+/* Members of the xorgens family (Section 1.5: period 2^n - 1 with n = r w a
+ * power of two up to 4096; Section 2: s = r/2 +- 1 for the GPU).  Every
+ * member uses omega = the odd integer nearest 2^{w-1}(sqrt 5 - 1) and
+ * gamma = w / 2.
+ *   XG_FAMILY_R128_W32  Section 2's member: w = 32, (r,s,a,b,c,d) =
+ *                       (128,65,15,14,12,17); n = 4096.  Every call of this
+ *                       header supports it.
+ *   XG_FAMILY_R64_W32   w = 32, (64,33,19,19,9,18); n = 2048, a 272-byte
+ *                       state.  Plain and bulk-fill u32 / f32 only.
+ *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
+ *                       (xg_generate_u64 / f64, xg_fill_u64 / f64) only.
+ * The paper gives shifts only for the first; those of the other two were
+ * chosen by a search for primitive characteristic polynomials.  Calls a
+ * member does not support return XG_ENOTSUP. */
+#define XG_FAMILY_R128_W32 0u
+#define XG_FAMILY_R64_W32  1u
+#define XG_FAMILY_R64_W64  2u
 
 typedef struct xg_ctx xg_ctx;
 
@@ -100,6 +121,26 @@ void xg_destroy(xg_ctx *ctx);
 /* Number of streams and state pointer of a handle (0 / NULL for NULL). */
 uint64_t xg_num_streams(const xg_ctx *ctx);
 void *xg_state_ptr(const xg_ctx *ctx);
+
+/* Bytes of device state for num_streams streams of a family (0 for an
+ * unknown family).  Per stream: R128_W32 528 (see XG_STATE_WORDS); R64_W32
+ * 272: ring uint32[64] (ring[t] = x_{pos-64+t}), W_{pos-1}, a zero word, pos
+ * (uint64); R64_W64 528: ring uint64[64], W_{pos-1} (uint64), pos (uint64). */
+size_t xg_family_state_bytes(uint32_t family, uint64_t num_streams);
+
+/* xg_init_streams / xg_attach_streams for a family.  Seeding of the 32-bit
+ * members is that of xg_init_streams with r ring words: SplitMix64(seed + i)
+ * outputs 1 .. r give x_{-r} .. x_{-1} (their high w bits), output r + 1 the
+ * Weyl start, an all-zero ring gets x_{-1} = 1, and 4 r steps are discarded;
+ * the 64-bit member takes all 64 bits of each output.
+ * Errors: those of xg_init_streams, and XG_EINVAL for an unknown family. */
+xg_status xg_init_family(xg_ctx **out, uint32_t family, void *d_state, size_t state_bytes,
+                         uint64_t num_streams, uint64_t seed, void *stream);
+xg_status xg_attach_family(xg_ctx **out, uint32_t family, void *d_state, size_t state_bytes,
+                           uint64_t num_streams);
+
+/* Family of a handle (XG_FAMILY_*; UINT32_MAX for NULL). */
+uint32_t xg_family(const xg_ctx *ctx);
 
 /* Launch shape of a kernel.  Any shape gives the same output bits;
  * xg_autotune_batch picks the fastest for a batch. */
@@ -145,12 +186,33 @@ xg_status xg_generate_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t 
  * so the count * n outputs fill d_out contiguously with no gaps, and the
  * wavefronts of a launch advance together through one dense region of HBM
  * (stream-major placement keeps count write fronts n words apart).  A chunk
- * of 64 words of one stream stays contiguous.  Same arguments and errors as
+ * of 64 words of one stream stays contiguous.  For XG_FAMILY_R64_W32 the chunk
+ * is 32 words (read 32 for 64 above).  Same arguments and errors as
  * xg_generate_u32; waves_per_block and unroll of the plain tune apply. */
 xg_status xg_fill_u32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                       uint32_t *d_out, void *stream);
 xg_status xg_fill_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                       float *d_out, void *stream);
+
+/* 64-bit outputs of the XG_FAMILY_R64_W64 member (Section 1.5: xorgens with
+ * w = 64).  Layouts and errors as xg_generate_u32 / xg_fill_u32 with 64-bit
+ * elements, except that the bulk-fill chunk is 32 words:
+ *   xg_generate_*: stream i's t-th value at d_out[(i - first) n + t];
+ *   xg_fill_*:     chunk c (values 32c .. 32c + 31) of the k-th stream of the
+ *                  call at d_out[(c count + k) 32 ..], then the ragged last
+ *                  chunks (n mod 32 values each) packed at
+ *                  d_out[32 (n / 32) count + k (n mod 32) ..].
+ * u64: out_k.  f64: (out_k >> 11) * 2^-53, exact.  d_out 8-byte aligned.
+ * Other families: XG_ENOTSUP.  (XG_FAMILY_R64_W32 uses xg_generate_u32 /
+ * f32 and xg_fill_u32 / f32, whose bulk-fill chunk is then 32 words.) */
+xg_status xg_generate_u64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                          uint64_t *d_out, void *stream);
+xg_status xg_generate_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                          double *d_out, void *stream);
+xg_status xg_fill_u64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                      uint64_t *d_out, void *stream);
+xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                      double *d_out, void *stream);
 
 /* Standard normals by the Box-Muller transform on consecutive pairs of
  * outputs (o_{2m}, o_{2m+1}) of the call: u1 = ((o_{2m} >> 8) + 1) 2^-24 in

@@ -28,11 +28,13 @@ xg_status current_gfx950(int *device, int *num_cus) {
   return XG_OK;
 }
 
-xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num_streams) {
+xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num_streams,
+                   uint32_t family = XG_FAMILY_R128_W32) {
   if (!out) return XG_EINVAL;
   *out = nullptr;
-  if (!d_state || num_streams == 0 || num_streams > kMaxStreams) return XG_EINVAL;
-  if (state_bytes / XG_STATE_WORDS / 4 < num_streams) return XG_ERANGE;
+  const uint32_t per_stream = xg::family_state_bytes(family);
+  if (!d_state || num_streams == 0 || num_streams > kMaxStreams || per_stream == 0) return XG_EINVAL;
+  if (state_bytes / per_stream < num_streams) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_state) % 16 != 0) return XG_EALIGN;
   int dev = 0, cus = 0;
   const xg_status st = current_gfx950(&dev, &cus);
@@ -44,6 +46,7 @@ xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num
   c->device = dev;
   c->num_cus = cus;
   c->plain = xg::kDefaultPlain;
+  c->family = family;
   *out = c;
   return XG_OK;
 }
@@ -55,27 +58,49 @@ xg_status check_ctx_device(const xg_ctx *ctx) {
 }
 
 // Validates a plain launch over streams [first, first + count) with
-// per_stream_elems elements of output each (out may be NULL when n == 0).
+// per_stream_elems elements of elem_bytes each (out may be NULL when n == 0).
 xg_status check_range(const xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
-                      const void *out, uint64_t per_stream_elems) {
+                      const void *out, uint64_t per_stream_elems, uint32_t elem_bytes = 4) {
   if (!ctx || count == 0) return XG_EINVAL;
   if (first > ctx->num_streams || count > ctx->num_streams - first) return XG_ERANGE;
   if (n == 0) return XG_OK;
   if (!out) return XG_EINVAL;
-  if (count > (UINT64_MAX / 4) / per_stream_elems) return XG_ERANGE;
-  if (reinterpret_cast<uintptr_t>(out) % 4 != 0) return XG_EALIGN;
+  if (count > (UINT64_MAX / elem_bytes) / per_stream_elems) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(out) % elem_bytes != 0) return XG_EALIGN;
   return check_ctx_device(ctx);
 }
 
-// The plain shape with an automatic waves_per_block resolved for this launch.
+// Calls that only Section 2's member supports.
+bool paper_member(const xg_ctx *ctx) { return ctx && ctx->family == XG_FAMILY_R128_W32; }
+
+// The plain shape with an automatic waves_per_block resolved for this launch
+// (the further members run two streams per wavefront).
 xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count) {
   xg::Shape s = ctx->plain;
-  if (s.waves_per_block == 0) s.waves_per_block = xg::auto_waves_per_block(count, ctx->num_cus);
+  const uint64_t waves = ctx->family == XG_FAMILY_R128_W32 ? count : (count + 1) / 2;
+  if (s.waves_per_block == 0) s.waves_per_block = xg::auto_waves_per_block(waves, ctx->num_cus);
   return s;
+}
+
+// u32 / f32 (and u64 / f64) of the further members, both layouts.
+xg_status family_words(xg_ctx *ctx, xg::Kind kind, bool fill_layout, uint64_t first, uint64_t count, uint64_t n,
+                       void *out, void *stream) {
+  const bool w64 = kind == xg::kU64 || kind == xg::kF64;
+  if (!ctx) return XG_EINVAL;
+  if (ctx->family != (w64 ? XG_FAMILY_R64_W64 : XG_FAMILY_R64_W32)) return XG_ENOTSUP;
+  xg_status st = check_range(ctx, first, count, n, out, n, w64 ? 8 : 4);
+  if (st != XG_OK || n == 0) return st;
+  const hipError_t e = xg::launch_family_generate(ctx->family, kind, fill_layout, plain_shape(ctx, count),
+                                                  reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
+                                                  n, out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
 xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, void *out,
                 void *stream) {
+  if (ctx && ctx->family == XG_FAMILY_R64_W32 && (kind == xg::kU32 || kind == xg::kF32))
+    return family_words(ctx, kind, false, first, count, n, out, stream);
+  if (ctx && !paper_member(ctx)) return XG_ENOTSUP;
   const uint64_t per_stream = kind == xg::kMoments ? 2 : n;
   xg_status st = check_range(ctx, first, count, n, out, per_stream);
   if (st != XG_OK || n == 0) return st;
@@ -86,6 +111,8 @@ xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint
 
 xg_status fill(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, void *out,
                void *stream) {
+  if (ctx && ctx->family == XG_FAMILY_R64_W32) return family_words(ctx, kind, true, first, count, n, out, stream);
+  if (ctx && !paper_member(ctx)) return XG_ENOTSUP;
   xg_status st = check_range(ctx, first, count, n, out, n);
   if (st != XG_OK || n == 0) return st;
   const hipError_t e = xg::launch_fill(kind, plain_shape(ctx, count), ctx->d_state, first, count, n,
@@ -126,6 +153,33 @@ xg_status xg_init_streams(xg_ctx **out, void *d_state, size_t state_bytes, uint6
 xg_status xg_attach_streams(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num_streams) {
   return make_ctx(out, d_state, state_bytes, num_streams);
 }
+
+size_t xg_family_state_bytes(uint32_t family, uint64_t num_streams) {
+  if (num_streams > kMaxStreams) return 0;
+  return (size_t)num_streams * xg::family_state_bytes(family);
+}
+
+xg_status xg_init_family(xg_ctx **out, uint32_t family, void *d_state, size_t state_bytes, uint64_t num_streams,
+                         uint64_t seed, void *stream) {
+  if (family == XG_FAMILY_R128_W32) return xg_init_streams(out, d_state, state_bytes, num_streams, seed, stream);
+  xg_status st = make_ctx(out, d_state, state_bytes, num_streams, family);
+  if (st != XG_OK) return st;
+  const hipError_t e = xg::launch_family_init(family, reinterpret_cast<unsigned char *>(d_state), num_streams,
+                                              seed, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) {
+    delete *out;
+    *out = nullptr;
+    return XG_EHIP;
+  }
+  return XG_OK;
+}
+
+xg_status xg_attach_family(xg_ctx **out, uint32_t family, void *d_state, size_t state_bytes,
+                           uint64_t num_streams) {
+  return make_ctx(out, d_state, state_bytes, num_streams, family);
+}
+
+uint32_t xg_family(const xg_ctx *ctx) { return ctx ? ctx->family : UINT32_MAX; }
 
 void xg_destroy(xg_ctx *ctx) { delete ctx; }
 
@@ -184,8 +238,27 @@ xg_status xg_fill_f32(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, f
   return fill(ctx, xg::kF32, first, count, n, d_out, stream);
 }
 
+xg_status xg_generate_u64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, uint64_t *d_out,
+                          void *stream) {
+  return family_words(ctx, xg::kU64, false, first, count, n, d_out, stream);
+}
+
+xg_status xg_generate_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, double *d_out,
+                          void *stream) {
+  return family_words(ctx, xg::kF64, false, first, count, n, d_out, stream);
+}
+
+xg_status xg_fill_u64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, uint64_t *d_out, void *stream) {
+  return family_words(ctx, xg::kU64, true, first, count, n, d_out, stream);
+}
+
+xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, double *d_out, void *stream) {
+  return family_words(ctx, xg::kF64, true, first, count, n, d_out, stream);
+}
+
 xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream) {
   if (!ctx || count == 0) return XG_EINVAL;
+  if (!paper_member(ctx)) return XG_ENOTSUP;
   if (first > ctx->num_streams || count > ctx->num_streams - first) return XG_ERANGE;
   xg_status st = check_ctx_device(ctx);
   if (st != XG_OK || J == 0) return st;
@@ -220,6 +293,7 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
                             const uint32_t *d_groups, uint32_t num_groups, void *d_out,
                             uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream) {
   if (!ctx || !d_reqs || !d_groups || !d_out || !d_work) return XG_EINVAL;
+  if (!paper_member(ctx)) return XG_ENOTSUP;
   if (num_groups > num_reqs) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_groups) % 4 ||
       reinterpret_cast<uintptr_t>(d_out) % 4 || reinterpret_cast<uintptr_t>(d_work) % 4)
@@ -243,6 +317,7 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
                             xg_tune *best, float *times_ms, uint32_t max_times,
                             uint32_t *num_times, void *stream) {
   if (!ctx || !best || !d_scratch_state || reps < 1 || reps > 100) return XG_EINVAL;
+  if (!paper_member(ctx)) return XG_ENOTSUP;
   if (num_times) *num_times = 0;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t state_bytes = xg_state_bytes(ctx->num_streams);

@@ -1,0 +1,335 @@
+// HIP kernels of libxg for two further xorgens members, both with r = 64 and
+// s = 33 (Section 2: s = r/2 + 1, gcd(r, s) = 1; Section 1.5: period
+// 2^n - 1 for n = r w a power of two up to 4096):
+//   n2048: w = 32, (a, b, c, d) = (19, 19,  9, 18), gamma = 16;
+//   w64:   w = 64, (a, b, c, d) = (24, 22, 37, 45), gamma = 32;
+// with x_i = x_{i-64} (I + L^a)(I + R^b) xor x_{i-33} (I + L^c)(I + R^d), the
+// Weyl sequence W_k = W_{k-1} + omega (omega the odd integer nearest
+// 2^{w-1}(sqrt 5 - 1)) and out_k = x_k + (W_k xor (W_k >> gamma)) mod 2^w
+// (Eq. (1)).  The paper gives no shifts for these members; each quadruple
+// makes the characteristic polynomial primitive of degree n.
+//
+// Parallel step: x_p .. x_{p+31} depend only on words older than x_p while
+// 32 <= s, so a step computes 32 words of a stream.  A 64-lane wavefront runs
+// two streams with interleaved lanes: lane 2j + h holds word j of stream h
+// (h = 0, 1), so every lane works and a step writes 64 words.  For the chunk
+// at p, lane 2j + h holds
+//   prev = x_{p-64+j},  cur = x_{p-32+j}          (of stream h)
+// and x_{p+j} = A(prev) xor B(x_{p+j-33}), where x_{p+j-33} is cur[j-1] for
+// j >= 1 and prev[31] for j = 0.  Rotating B(cur) up by two lanes moves word
+// j - 1 of each stream to word j of the same stream; lanes 0 and 1 receive
+// word 31 of their own stream, which is B(prev[31]) one step later, so they
+// keep the previous step's rotation (as the one-stream kernel does on lane 0).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xg_internal.h"
+
+namespace xg {
+namespace {
+
+struct MemberN2048 {
+  using word = uint32_t;
+  static constexpr uint32_t a = 19, b = 19, c = 9, d = 18, gamma = 16;
+  static constexpr word omega = 0x9E3779B9u;
+  // ring u32[64] | W | reserved | pos u64
+  static constexpr uint32_t state_bytes = 272, weyl_off = 256, pos_off = 264;
+};
+
+struct MemberW64 {
+  using word = uint64_t;
+  static constexpr uint32_t a = 24, b = 22, c = 37, d = 45, gamma = 32;
+  static constexpr word omega = 0x9E3779B97F4A7C15ull;
+  // ring u64[64] | W | pos
+  static constexpr uint32_t state_bytes = 528, weyl_off = 512, pos_off = 520;
+};
+
+constexpr uint32_t kStep = 32;  // words of one stream per wavefront step
+
+// Lane l receives lane l-2's value (mod 64): DPP wave_ror:1 twice.  Every lane
+// has a source, so bound_ctrl never applies.
+__device__ __forceinline__ uint32_t rot2(uint32_t v) {
+  v = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
+  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
+}
+__device__ __forceinline__ uint64_t rot2(uint64_t v) {
+  return (uint64_t)rot2((uint32_t)v) | ((uint64_t)rot2((uint32_t)(v >> 32)) << 32);
+}
+
+// a xor b xor c with gfx950 v_bitop3_b32 (truth table 0x96 on a = 0xF0,
+// b = 0xCC, c = 0xAA).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+__device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c) {
+  return (uint64_t)xor3((uint32_t)a, (uint32_t)b, (uint32_t)c) |
+         ((uint64_t)xor3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
+}
+
+__device__ __forceinline__ uint32_t shfl_word(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
+__device__ __forceinline__ uint64_t shfl_word(uint64_t v, int src) {
+  return (uint64_t)(uint32_t)__shfl((int)(uint32_t)v, src) |
+         ((uint64_t)(uint32_t)__shfl((int)(uint32_t)(v >> 32), src) << 32);
+}
+
+template <class M>
+__device__ __forceinline__ typename M::word op_b(typename M::word v) {
+  v ^= v << M::c;
+  return v ^ (v >> M::d);
+}
+
+template <class M>
+struct Ring2 {
+  using word = typename M::word;
+  word prev, cur, rprev;
+
+  __device__ __forceinline__ void open(word p, word c) {
+    prev = p;
+    cur = c;
+    rprev = rot2(op_b<M>(p));  // word 0: B(prev[31]) = B(x_{p-33})
+  }
+
+  // x_{p+j} on lane 2j + h; advances the ring by one chunk.
+  __device__ __forceinline__ word step(bool word0) {
+    const word bc = op_b<M>(cur);
+    const word rc = rot2(bc);              // word j >= 1: B(x_{p+j-33}); word 0: B(x_{p-1})
+    const word bs = word0 ? rprev : rc;
+    const word t = prev ^ (prev << M::a);  // prev (I + L^a) (I + R^b) = t xor (t >> b)
+    const word x = xor3(t, t >> M::b, bs);
+    prev = cur;
+    cur = x;
+    rprev = rc;                            // word 0: B(x_{p-1}) = B(x_{p'-33}), p' = p + 32
+    return x;
+  }
+};
+
+// Output word of KIND for generator output o, as stored (FP as bit pattern).
+//   w = 32: u32 o; f32 (o >> 8) 2^-24.   w = 64: u64 o; f64 (o >> 11) 2^-53.
+// Both FP maps are exact (an integer of at most 24 / 53 bits times a power of 2).
+template <class M, uint32_t KIND>
+__device__ __forceinline__ typename M::word map_out(typename M::word o) {
+  if constexpr (sizeof(typename M::word) == 4) {
+    if constexpr (KIND == kU32) return o;
+    else return __float_as_uint((float)(o >> 8) * 0x1p-24f);
+  } else {
+    if constexpr (KIND == kU64) return o;
+    else return (uint64_t)__double_as_longlong((double)(o >> 11) * 0x1p-53);
+  }
+}
+
+// k-th output (k >= 1) of SplitMix64 started at s: finalise s + k * golden gamma.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t s, uint64_t k) {
+  uint64_t z = s + k * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+template <class M>
+__device__ __forceinline__ typename M::word seed_word(uint64_t v) {
+  if constexpr (sizeof(typename M::word) == 4) return (uint32_t)(v >> 32);  // the high w bits
+  else return v;
+}
+
+struct Lanes {
+  uint32_t lane, h, j;
+  uint64_t k;    // stream index within the launch
+  bool active;   // k < count
+};
+
+__device__ __forceinline__ Lanes lanes_of(uint64_t count) {
+  Lanes L;
+  L.lane = threadIdx.x & 63u;
+  L.h = L.lane & 1u;
+  L.j = L.lane >> 1;
+  const uint64_t pair = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  L.k = 2 * pair + L.h;
+  L.active = L.k < count;
+  return L;
+}
+
+// Writes the 64-word window that ends `rem` words into chunk x (rem in 0..31)
+// as stream h's new linear ring, then W and pos.
+template <class M>
+__device__ __forceinline__ void store_state(unsigned char *st, const Lanes &L, typename M::word prev,
+                                            typename M::word cur, typename M::word x, uint32_t rem,
+                                            typename M::word weyl, uint64_t pos) {
+  using word = typename M::word;
+  word lo = prev, hi = cur;
+  if (rem) {  // wave-uniform
+    const uint32_t js = (rem + L.j) & 31u;
+    const int src = (int)(2 * js + L.h);
+    const word a = shfl_word(prev, src), b = shfl_word(cur, src), c = shfl_word(x, src);
+    const bool wrap = rem + L.j >= 32u;
+    lo = wrap ? b : a;
+    hi = wrap ? c : b;
+  }
+  if (!L.active) return;
+  word *ring = reinterpret_cast<word *>(st);
+  ring[L.j] = lo;
+  ring[32 + L.j] = hi;
+  if (L.j == 0) {
+    *reinterpret_cast<word *>(st + M::weyl_off) = weyl;
+    if constexpr (sizeof(word) == 4) *reinterpret_cast<uint32_t *>(st + M::weyl_off + 4) = 0u;
+    *reinterpret_cast<uint64_t *>(st + M::pos_off) = pos;
+  }
+}
+
+// Seeds streams [0, num_streams): stream k from SplitMix64(seed + k) outputs
+// 1 .. 64 (ring x_{-64} .. x_{-1}, high w bits) and 65 (the Weyl start); an
+// all-zero ring gets x_{-1} = 1; then 4 r = 256 steps are discarded.
+template <class M>
+__global__ __launch_bounds__(256) void k_fam_init(unsigned char *__restrict__ state, uint64_t num_streams,
+                                                  uint64_t seed) {
+  using word = typename M::word;
+  const Lanes L = lanes_of(num_streams);
+  if (2 * (L.k >> 1) >= num_streams) return;  // wave-uniform: both streams of the pair absent
+  const uint64_t s = seed + L.k;
+  word prev = seed_word<M>(splitmix64_at(s, L.j + 1u));
+  word cur = seed_word<M>(splitmix64_at(s, L.j + 33u));
+  const word w0 = seed_word<M>(splitmix64_at(s, 65u));
+  const uint64_t nz = __ballot((prev | cur) != 0);
+  const uint64_t mine = L.h ? 0xAAAAAAAAAAAAAAAAull : 0x5555555555555555ull;
+  if ((nz & mine) == 0 && L.j == 31u) cur = 1;  // x_{-1} = 1
+  Ring2<M> g;
+  g.open(prev, cur);
+  const bool word0 = L.j == 0;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) (void)g.step(word0);
+  store_state<M>(state + L.k * M::state_bytes, L, g.prev, g.cur, word(0), 0u, w0 + word(256) * M::omega, 0ull);
+}
+
+// n words of each of `count` streams (launch index k = stream first + k).
+// FILL = false: stream-major, out[k n + t].  FILL = true: chunk c (words
+// 32c .. 32c + 31) of stream k at out[(c count + k) 32 ..], the ragged last
+// chunks (rem = n mod 32 words each) packed after them at
+// out[32 (n / 32) count + k rem ..]; a wavefront's step then writes 64
+// adjacent words.  CHECK: the wavefront's second stream is absent (odd count,
+// last pair), so that half's loads and stores are masked.
+template <class M, uint32_t KIND, int UNROLL, bool FILL, bool CHECK>
+__device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, const Lanes &L, uint64_t first,
+                                          uint64_t count, uint64_t n, typename M::word *__restrict__ out) {
+  using word = typename M::word;
+  const bool on = !CHECK || L.active;
+  unsigned char *st = state + (first + L.k) * M::state_bytes;
+  const word *ring = reinterpret_cast<const word *>(st);
+  word prev = 0, cur = 0, w_start = 0;
+  uint64_t pos = 0;
+  if (on) {
+    prev = ring[L.j];
+    cur = ring[32 + L.j];
+    w_start = *reinterpret_cast<const word *>(st + M::weyl_off);
+    pos = *reinterpret_cast<const uint64_t *>(st + M::pos_off);
+  }
+  Ring2<M> g;
+  g.open(prev, cur);
+  const bool word0 = L.j == 0;
+  const word wlane = word(L.j + 1u) * M::omega;  // W_{p+j} = W_{p-1} + (j + 1) omega
+  word wbase = w_start;
+  const uint64_t nfull = n / kStep;
+  const uint32_t rem = (uint32_t)(n % kStep);
+  const uint64_t stride = FILL ? count * kStep : kStep;
+  word *o = FILL ? out + L.k * kStep + L.j : out + L.k * n + L.j;
+  const uint64_t nouter = nfull / UNROLL;
+  for (uint64_t it = 0; it != nouter; ++it) {
+#pragma unroll
+    for (int u = 0; u < UNROLL; ++u) {
+      const word x = g.step(word0);
+      const word w = wbase + wlane;
+      wbase += word(kStep) * M::omega;
+      if (on) __builtin_nontemporal_store(map_out<M, KIND>(x + (word)(w ^ (w >> M::gamma))), o + u * stride);
+    }
+    o += UNROLL * stride;
+  }
+  for (uint64_t c = nouter * UNROLL; c != nfull; ++c) {
+    const word x = g.step(word0);
+    const word w = wbase + wlane;
+    wbase += word(kStep) * M::omega;
+    if (on) __builtin_nontemporal_store(map_out<M, KIND>(x + (word)(w ^ (w >> M::gamma))), o);
+    o += stride;
+  }
+  const word p0 = g.prev, c0 = g.cur;
+  word x = 0;
+  if (rem) {  // wave-uniform
+    x = g.step(word0);
+    const word w = wbase + wlane;
+    word *tail = FILL ? out + nfull * count * kStep + L.k * rem + L.j : o;
+    if (on && L.j < rem) __builtin_nontemporal_store(map_out<M, KIND>(x + (word)(w ^ (w >> M::gamma))), tail);
+  }
+  store_state<M>(st, L, p0, c0, x, rem, w_start + (word)n * M::omega, pos + n);
+}
+
+template <class M, uint32_t KIND, int UNROLL, bool FILL>
+__global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict__ state, uint64_t first,
+                                                       uint64_t count, uint64_t n, void *__restrict__ out) {
+  const Lanes L = lanes_of(count);
+  const uint64_t pair = L.k >> 1;
+  if (2 * pair >= count) return;  // wave-uniform
+  using word = typename M::word;
+  if (2 * pair + 1 < count)
+    fam_serve<M, KIND, UNROLL, FILL, false>(state, L, first, count, n, reinterpret_cast<word *>(out));
+  else
+    fam_serve<M, KIND, UNROLL, FILL, true>(state, L, first, count, n, reinterpret_cast<word *>(out));
+}
+
+template <class M, uint32_t KIND, bool FILL>
+void launch_fam_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t first,
+                  uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL((k_fam_generate<M, KIND, 1, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 2: hipLaunchKernelGGL((k_fam_generate<M, KIND, 2, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 4: hipLaunchKernelGGL((k_fam_generate<M, KIND, 4, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    default: hipLaunchKernelGGL((k_fam_generate<M, KIND, 8, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+  }
+}
+
+template <class M, uint32_t KIND>
+void launch_fam_layout(bool fill, uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t first,
+                       uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  if (fill) launch_fam_k<M, KIND, true>(unroll, grid, block, state, first, count, n, out, stream);
+  else launch_fam_k<M, KIND, false>(unroll, grid, block, state, first, count, n, out, stream);
+}
+
+}  // namespace
+
+uint32_t family_state_bytes(uint32_t family) {
+  switch (family) {
+    case XG_FAMILY_R128_W32: return XG_STATE_WORDS * 4;
+    case XG_FAMILY_R64_W32: return MemberN2048::state_bytes;
+    case XG_FAMILY_R64_W64: return MemberW64::state_bytes;
+    default: return 0;
+  }
+}
+
+hipError_t launch_family_init(uint32_t family, unsigned char *state, uint64_t num_streams, uint64_t seed,
+                              hipStream_t stream) {
+  const uint64_t pairs = (num_streams + 1) / 2;
+  const dim3 grid((uint32_t)((pairs + 3) / 4)), block(256);
+  if (family == XG_FAMILY_R64_W32)
+    hipLaunchKernelGGL(k_fam_init<MemberN2048>, grid, block, 0, stream, state, num_streams, seed);
+  else if (family == XG_FAMILY_R64_W64)
+    hipLaunchKernelGGL(k_fam_init<MemberW64>, grid, block, 0, stream, state, num_streams, seed);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const Shape &shape, unsigned char *state,
+                                  uint64_t first, uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  const uint64_t pairs = (count + 1) / 2;
+  const uint64_t wpb = shape.waves_per_block;
+  const dim3 grid((uint32_t)((pairs + wpb - 1) / wpb)), block((uint32_t)(wpb * kWave));
+  if (family == XG_FAMILY_R64_W32 && kind == kU32)
+    launch_fam_layout<MemberN2048, kU32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+  else if (family == XG_FAMILY_R64_W32 && kind == kF32)
+    launch_fam_layout<MemberN2048, kF32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+  else if (family == XG_FAMILY_R64_W64 && kind == kU64)
+    launch_fam_layout<MemberW64, kU64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+  else if (family == XG_FAMILY_R64_W64 && kind == kF64)
+    launch_fam_layout<MemberW64, kF64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+}  // namespace xg

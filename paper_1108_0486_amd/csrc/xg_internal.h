@@ -15,7 +15,7 @@ constexpr uint32_t kWave = 64;
 
 // Request kinds of the plain launch (the three output types of xg.h plus the
 // fused normal-moments reduction).
-enum Kind : uint32_t { kU32 = XG_U32, kF32 = XG_F32, kNormal = XG_NORMAL, kMoments = 3 };
+enum Kind : uint32_t { kU32 = XG_U32, kF32 = XG_F32, kNormal = XG_NORMAL, kMoments = 3, kU64 = XG_U64, kF64 = XG_F64 };
 
 struct Shape {
   uint32_t waves_per_block;  // 1, 2, 4, 8, 16; 0 (plain launches only): chosen per launch
@@ -75,6 +75,17 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
 hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
                          const SegmentArgs &seg, hipStream_t stream);
 
+// Further family members (r = 64, s = 33; two streams per wavefront).
+// Bytes of one stream's state (0: unknown family).
+uint32_t family_state_bytes(uint32_t family);
+hipError_t launch_family_init(uint32_t family, unsigned char *state, uint64_t num_streams, uint64_t seed,
+                              hipStream_t stream);
+// kind: kU32 / kF32 for XG_FAMILY_R64_W32, kU64 / kF64 for XG_FAMILY_R64_W64;
+// fill selects the bulk-fill layout (32-word chunks).  shape.waves_per_block
+// counts wavefronts, i.e. pairs of streams.
+hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const Shape &shape, unsigned char *state,
+                                  uint64_t first, uint64_t count, uint64_t n, void *out, hipStream_t stream);
+
 
 }  // namespace xg
 
@@ -85,4 +96,5 @@ struct xg_ctx {
   int device;
   int num_cus;
   xg::Shape plain;
+  uint32_t family;  // XG_FAMILY_*
 };

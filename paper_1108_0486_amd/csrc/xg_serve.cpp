@@ -312,6 +312,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
   if (!out) return XG_EINVAL;
   *out = nullptr;
   if (!ctx || !config_valid(cfg) || !d_pool || !d_tables || pool_elems == 0) return XG_EINVAL;
+  if (ctx->family != XG_FAMILY_R128_W32) return XG_ENOTSUP;
   if (tables_bytes < xg_server_device_bytes(cfg)) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_pool) % kAlignBytes || reinterpret_cast<uintptr_t>(d_tables) % kAlignBytes)
     return XG_EALIGN;

@@ -17,28 +17,33 @@ def _stream_handle(stream: torch.cuda.Stream | None) -> int:
 
 
 class XorgensStreams:
-    """num_streams streams; stream i is seeded from seed + i."""
+    """num_streams streams of one family member (xg.XG_FAMILY_*, default
+    Section 2's); stream i is seeded from seed + i."""
 
     def __init__(self, num_streams: int, seed: int, device: str | torch.device = "cuda",
-                 stream: torch.cuda.Stream | None = None, state: torch.Tensor | None = None):
+                 stream: torch.cuda.Stream | None = None, state: torch.Tensor | None = None,
+                 family: int = xg.XG_FAMILY_R128_W32):
         self.device = torch.device(device)
         self.num_streams = int(num_streams)
-        nbytes = xg.xg_state_bytes(self.num_streams)
+        self.family = int(family)
+        nbytes = xg.xg_family_state_bytes(self.family, self.num_streams)
+        if nbytes == 0:
+            raise ValueError("unknown family %r" % family)
         if state is None:
             self.state = torch.empty(nbytes // 4, dtype=torch.int32, device=self.device)
             with torch.cuda.device(self.device):
-                self.ctx = xg.xg_init_streams(self.state.data_ptr(), nbytes, self.num_streams, seed,
-                                              _stream_handle(stream))
+                self.ctx = xg.xg_init_family(self.family, self.state.data_ptr(), nbytes, self.num_streams, seed,
+                                             _stream_handle(stream))
         else:
             if state.numel() * state.element_size() < nbytes or not state.is_cuda:
                 raise ValueError("state buffer too small or not on a GPU")
             self.state = state
             with torch.cuda.device(self.device):
-                self.ctx = xg.xg_attach_streams(self.state.data_ptr(), nbytes, self.num_streams)
+                self.ctx = xg.xg_attach_family(self.family, self.state.data_ptr(), nbytes, self.num_streams)
 
     @classmethod
-    def attach(cls, state: torch.Tensor, num_streams: int) -> "XorgensStreams":
-        return cls(num_streams, 0, device=state.device, state=state)
+    def attach(cls, state: torch.Tensor, num_streams: int, family: int = xg.XG_FAMILY_R128_W32) -> "XorgensStreams":
+        return cls(num_streams, 0, device=state.device, state=state, family=family)
 
     def close(self) -> None:
         if getattr(self, "ctx", None) is not None:
@@ -97,6 +102,36 @@ class XorgensStreams:
         xg.xg_fill_f32(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
         return out
 
+    def u64(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+            stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """[count, n] int64 tensor holding the uint64 outputs' bits (64-bit member)."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count, n), torch.int64)
+        xg.xg_generate_u64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def f64(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+            stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        first, count = self._range(first, count)
+        out = self._out(out, (count, n), torch.float64)
+        xg.xg_generate_f64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def fill_u64(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """count * n int64 (uint64 bits) in the bulk-fill layout (xg.fill_index, chunk 32)."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count * n,), torch.int64)
+        xg.xg_fill_u64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def fill_f64(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                 stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        first, count = self._range(first, count)
+        out = self._out(out, (count * n,), torch.float64)
+        xg.xg_fill_f64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
     def normal(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
                stream: torch.cuda.Stream | None = None) -> torch.Tensor:
         first, count = self._range(first, count)
@@ -120,7 +155,19 @@ class XorgensStreams:
 
     # ---- state --------------------------------------------------------------
     def host_state(self, idx=None):
-        """(ring[k, 128] uint32, weyl[k] uint32, pos[k] uint64) of the selected streams."""
+        """(ring[k, r], weyl[k], pos[k] uint64) of the selected streams: ring
+        and weyl uint32 for the 32-bit members (r = 128 or 64), uint64 for
+        the 64-bit member (r = 64)."""
+        if self.family != xg.XG_FAMILY_R128_W32:
+            per = xg.xg_family_state_bytes(self.family, 1) // 4
+            words = self.state[: self.num_streams * per].view(self.num_streams, per)
+            if idx is not None:
+                words = words[torch.as_tensor(idx, device=self.device)]
+            a = words.cpu().numpy().view(np.uint32)
+            if self.family == xg.XG_FAMILY_R64_W64:
+                q = a.view(np.uint64)
+                return q[:, :64].copy(), q[:, 64].copy(), q[:, 65].copy()
+            return a[:, :64].copy(), a[:, 64].copy(), a.view(np.uint64)[:, 33].copy()
         words = self.state.view(self.num_streams, xg.XG_STATE_WORDS)
         if idx is not None:
             words = words[torch.as_tensor(idx, device=self.device)]

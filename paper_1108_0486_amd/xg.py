@@ -27,6 +27,8 @@ XG_EBUSY = -7
 
 XG_STATE_WORDS = 132
 XG_U32, XG_F32, XG_NORMAL = 0, 1, 2
+XG_U64, XG_F64 = 4, 5
+XG_FAMILY_R128_W32, XG_FAMILY_R64_W32, XG_FAMILY_R64_W64 = 0, 1, 2
 
 
 class XgError(RuntimeError):
@@ -106,6 +108,14 @@ def lib() -> ctypes.CDLL:
         "xg_box_muller": (st, [vp, u64, vp, vp]),
         "xg_jump_polynomial": (st, [u64, P(u64)]),
         "xg_fill_f32": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_family_state_bytes": (ctypes.c_size_t, [u32, u64]),
+        "xg_init_family": (st, [P(vp), u32, vp, ctypes.c_size_t, u64, u64, vp]),
+        "xg_attach_family": (st, [P(vp), u32, vp, ctypes.c_size_t, u64]),
+        "xg_family": (u32, [vp]),
+        "xg_generate_u64": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_generate_f64": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_fill_u64": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_fill_f64": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
         "xg_plan_batch": (st, [P(xg_request), u32, u64, u64, P(xg_request), P(u32), P(u32)]),
         "xg_generate_batch": (st, [vp, vp, u32, vp, u32, vp, u64, P(xg_tune), vp, vp]),
@@ -205,15 +215,54 @@ def xg_fill_f32(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0
     _check(lib().xg_fill_f32(ctx, first, count, n, d_out, stream), "xg_fill_f32")
 
 
-def fill_index(count: int, n: int):
-    """numpy index array idx[k, t]: where xg_fill_* put value t of the k-th stream."""
+def fill_index(count: int, n: int, chunk: int = 64):
+    """numpy index array idx[k, t]: where xg_fill_* put value t of the k-th
+    stream (chunk = 64 words for Section 2's member, 32 for the others)."""
     import numpy as np
-    full, rem = n // 64, n % 64
+    full, rem = n // chunk, n % chunk
     t = np.arange(n, dtype=np.int64)
     k = np.arange(count, dtype=np.int64)[:, None]
-    head = (t // 64) * 64 * count + k * 64 + t % 64
-    tail = 64 * full * count + k * rem + (t - 64 * full)
-    return np.where(t < 64 * full, head, tail)
+    head = (t // chunk) * chunk * count + k * chunk + t % chunk
+    tail = chunk * full * count + k * rem + (t - chunk * full)
+    return np.where(t < chunk * full, head, tail)
+
+
+def xg_family_state_bytes(family: int, num_streams: int) -> int:
+    return int(lib().xg_family_state_bytes(family, num_streams))
+
+
+def xg_init_family(family: int, d_state: int, state_bytes: int, num_streams: int, seed: int, stream: int = 0):
+    ctx = ctypes.c_void_p()
+    _check(lib().xg_init_family(ctypes.byref(ctx), family, d_state, state_bytes, num_streams,
+                                seed & (2**64 - 1), stream), "xg_init_family")
+    return ctx
+
+
+def xg_attach_family(family: int, d_state: int, state_bytes: int, num_streams: int):
+    ctx = ctypes.c_void_p()
+    _check(lib().xg_attach_family(ctypes.byref(ctx), family, d_state, state_bytes, num_streams),
+           "xg_attach_family")
+    return ctx
+
+
+def xg_family(ctx) -> int:
+    return int(lib().xg_family(ctx))
+
+
+def xg_generate_u64(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_generate_u64(ctx, first, count, n, d_out, stream), "xg_generate_u64")
+
+
+def xg_generate_f64(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_generate_f64(ctx, first, count, n, d_out, stream), "xg_generate_f64")
+
+
+def xg_fill_u64(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_fill_u64(ctx, first, count, n, d_out, stream), "xg_fill_u64")
+
+
+def xg_fill_f64(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
+    _check(lib().xg_fill_f64(ctx, first, count, n, d_out, stream), "xg_fill_f64")
 
 
 def xg_box_muller(d_words: int, pairs: int, d_out: int, stream: int = 0) -> None:

@@ -125,3 +125,35 @@ def test_jump_polynomial_matches_oracle(J):
     from oracle import oracle as O
     P = O.charpoly(O.PAPER)
     assert xg.xg_jump_polynomial(J) == O.z_pow_mod(J, P)
+
+
+def test_family_entry_points_without_gpu():
+    """Family state sizes, the family of a NULL handle, and argument errors
+    that are caught before any device call."""
+    assert xg.xg_family_state_bytes(xg.XG_FAMILY_R128_W32, 3) == 3 * 528
+    assert xg.xg_family_state_bytes(xg.XG_FAMILY_R64_W32, 3) == 3 * 272
+    assert xg.xg_family_state_bytes(xg.XG_FAMILY_R64_W64, 3) == 3 * 528
+    assert xg.xg_family_state_bytes(7, 3) == 0
+    assert xg.xg_family_state_bytes(xg.XG_FAMILY_R64_W32, 2**33) == 0
+    L = xg.lib()
+    assert L.xg_family(None) == 0xFFFFFFFF
+    ctx = ctypes.c_void_p()
+    buf = ctypes.create_string_buffer(4096 + 16)
+    aligned = (ctypes.addressof(buf) + 15) // 16 * 16
+    assert L.xg_init_family(ctypes.byref(ctx), 7, aligned, 4096, 1, 0, None) == xg.XG_EINVAL
+    assert L.xg_attach_family(ctypes.byref(ctx), 7, aligned, 4096, 1) == xg.XG_EINVAL
+    assert L.xg_attach_family(ctypes.byref(ctx), xg.XG_FAMILY_R64_W32, aligned, 271, 1) == xg.XG_ERANGE
+    assert L.xg_attach_family(ctypes.byref(ctx), xg.XG_FAMILY_R64_W64, aligned, 528 * 8 - 1, 8) == xg.XG_ERANGE
+    assert L.xg_attach_family(None, xg.XG_FAMILY_R64_W32, aligned, 4096, 1) == xg.XG_EINVAL
+    for f in (L.xg_generate_u64, L.xg_generate_f64, L.xg_fill_u64, L.xg_fill_f64):
+        assert f(None, 0, 1, 16, None, None) == xg.XG_EINVAL
+
+
+def test_fill_index_chunk32_is_a_permutation():
+    import numpy as np
+    for count, n in [(1, 1), (3, 31), (5, 32), (7, 33), (4, 1000)]:
+        idx = xg.fill_index(count, n, chunk=32)
+        assert np.array_equal(np.sort(idx.ravel()), np.arange(count * n))
+        full = n // 32
+        if full:   # chunk c of stream k is contiguous at (c count + k) 32
+            assert idx[count - 1, 32 * full - 1] == (full - 1) * 32 * count + (count - 1) * 32 + 31

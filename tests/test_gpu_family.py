@@ -1,0 +1,194 @@
+"""The further family members on the GPU against the oracle, through the C ABI.
+
+XG_FAMILY_R64_W32 (w = 32, r = 64, s = 33) and XG_FAMILY_R64_W64 (w = 64,
+r = 64, s = 33) run two streams per wavefront, 32 words per stream per step.
+Sizes span several steps, unroll groups and ragged tails, odd stream counts
+(a wavefront with one stream) and offsets; every value is bit-exact against
+the oracle, and so is the state left behind.
+"""
+import numpy as np
+import pytest
+
+from gpu_helpers import needs_gpu
+from oracle import oracle as O
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+torch = pytest.importorskip("torch")
+
+from paper_1108_0486_amd import xg  # noqa: E402
+from paper_1108_0486_amd.streams import XorgensStreams  # noqa: E402
+
+R64W32, R64W64 = xg.XG_FAMILY_R64_W32, xg.XG_FAMILY_R64_W64
+PARAMS = {R64W32: O.R64, R64W64: O.W64}
+FAMS = [R64W32, R64W64]
+RAGGED = [1, 2, 31, 32, 33, 63, 64, 65, 255, 256, 257, 1000, 4133]
+
+
+def _oracle(fam, seed, count, first=0):
+    p = PARAMS[fam]
+    if p.w == 64:
+        return O.OracleStreams64(seed, count, p, first=first)
+    return O.OracleStreams(seed, count, first=first, params=p)
+
+
+def _sub(ref, lo, hi):
+    if isinstance(ref, O.OracleStreams64):
+        return O.OracleStreams64.from_state(ref.ring[lo:hi], ref.weyl[lo:hi], ref.pos[lo:hi], ref.params)
+    return ref.subset(range(lo, hi))
+
+
+def _bits(t):
+    a = t.cpu().numpy()
+    return a.view(np.uint64) if a.dtype.itemsize == 8 else a.view(np.uint32)
+
+
+def _words(gs, fam, n, first=0, count=None, fp=False, fill=False):
+    if fam == R64W64:
+        f = {(False, False): gs.u64, (True, False): gs.f64, (False, True): gs.fill_u64, (True, True): gs.fill_f64}
+    else:
+        f = {(False, False): gs.u32, (True, False): gs.f32, (False, True): gs.fill_u32, (True, True): gs.fill_f32}
+    return f[(fp, fill)](n, first=first, count=count)
+
+
+def _ref_words(ref, fam, n, fp=False):
+    if fam == R64W64:
+        return ref.f64(n) if fp else ref.u64(n)
+    return ref.f32(n) if fp else ref.u32(n)
+
+
+def _assert_state(gs, ref, idx=None):
+    ring, weyl, pos = gs.host_state(idx)
+    assert (ring == ref.ring).all() and (weyl == ref.weyl).all() and (pos == ref.pos).all()
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("count", [1, 2, 7, 258])
+def test_family_seeding_matches_oracle(fam, count):
+    gs = XorgensStreams(count, seed=42, family=fam)
+    torch.cuda.synchronize()
+    assert xg.xg_family(gs.ctx) == fam
+    _assert_state(gs, _oracle(fam, 42, count))
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_family_seed_wraps(fam):
+    gs = XorgensStreams(3, seed=2**64 - 2, family=fam)
+    torch.cuda.synchronize()
+    _assert_state(gs, _oracle(fam, 2**64 - 2, 3))
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("n", RAGGED)
+def test_family_words_ragged(fam, n):
+    """Streams 3 .. 35 of 37 (33 streams: the last wavefront holds one)."""
+    gs = XorgensStreams(37, seed=1234, family=fam)
+    ref = _oracle(fam, 1234, 37)
+    sub = _sub(ref, 3, 36)
+    got = _bits(_words(gs, fam, n, first=3, count=33))
+    assert (got == _ref_words(sub, fam, n)).all()
+    gotf = _words(gs, fam, n, first=3, count=33, fp=True).cpu().numpy()
+    assert (gotf == _ref_words(sub, fam, n, fp=True)).all()
+    torch.cuda.synchronize()
+    _assert_state(gs, sub, idx=list(range(3, 36)))
+    _assert_state(gs, _sub(ref, 0, 3), idx=[0, 1, 2])          # untouched neighbours
+    _assert_state(gs, _sub(ref, 36, 37), idx=[36])
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("n", [1, 31, 32, 33, 100, 1024, 4133])
+@pytest.mark.parametrize("count", [1, 6, 9])
+def test_family_fill_layout(fam, n, count):
+    gs = XorgensStreams(count + 2, seed=5, family=fam)
+    ref = _sub(_oracle(fam, 5, count + 2), 1, count + 1)
+    flat = _bits(_words(gs, fam, n, first=1, count=count, fill=True))
+    idx = xg.fill_index(count, n, chunk=32)
+    assert (flat[idx] == _ref_words(ref, fam, n)).all()
+    assert np.array_equal(np.sort(idx.ravel()), np.arange(count * n))
+    flatf = _words(gs, fam, n, first=1, count=count, fp=True, fill=True).cpu().numpy()
+    assert (flatf[idx] == _ref_words(ref, fam, n, fp=True)).all()
+    torch.cuda.synchronize()
+    _assert_state(gs, ref, idx=list(range(1, count + 1)))
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_family_launch_shapes_identical(fam):
+    outs = []
+    for wpb, unroll in [(1, 1), (2, 2), (4, 4), (16, 8), (0, 8)]:
+        gs = XorgensStreams(45, seed=9, family=fam)
+        gs.set_plain_tune(wpb, unroll, 1)
+        outs.append(_bits(_words(gs, fam, 2049)))
+        outs.append(_bits(_words(gs, fam, 300, fill=True)))
+    for k in range(2, len(outs), 2):
+        assert (outs[k] == outs[0]).all() and (outs[k + 1] == outs[1]).all()
+    ref = _oracle(fam, 9, 45)
+    assert (outs[0] == _ref_words(ref, fam, 2049)).all()
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_family_split_calls_and_checkpoint(fam):
+    gs = XorgensStreams(10, seed=3, family=fam)
+    saved = gs.checkpoint()
+    whole = _bits(_words(gs, fam, 1000))
+    gs.restore(saved)
+    parts = np.concatenate([_bits(_words(gs, fam, k)) for k in (31, 1, 500, 468)], axis=1)
+    assert (parts == whole).all()
+    again = XorgensStreams.attach(saved.clone(), 10, family=fam)
+    assert (_bits(_words(again, fam, 1000)) == whole).all()
+
+
+@pytest.mark.parametrize("fam", FAMS)
+def test_family_unsupported_calls_are_rejected(fam):
+    gs = XorgensStreams(4, seed=1, family=fam)
+    out = torch.empty(4 * 64, dtype=torch.float64, device="cuda")
+    p = out.data_ptr()
+    calls = [lambda: xg.xg_generate_normal(gs.ctx, 0, 4, 8, p), lambda: xg.xg_normal_moments(gs.ctx, 0, 4, 8, p),
+             lambda: xg.xg_skip(gs.ctx, 0, 4, 100)]
+    if fam == R64W64:
+        calls += [lambda: xg.xg_generate_u32(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f32(gs.ctx, 0, 4, 8, p)]
+    else:
+        calls += [lambda: xg.xg_generate_u64(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f64(gs.ctx, 0, 4, 8, p)]
+    for c in calls:
+        with pytest.raises(xg.XgError) as e:
+            c()
+        assert e.value.status == xg.XG_ENOTSUP
+    work = torch.zeros(64, dtype=torch.int32, device="cuda")
+    with pytest.raises(xg.XgError) as e:
+        xg.xg_generate_batch(gs.ctx, p, 1, p, 1, p, 8, None, work.data_ptr())
+    assert e.value.status == xg.XG_ENOTSUP
+    from paper_1108_0486_amd.serve import Server
+    with pytest.raises(xg.XgError) as e:
+        Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4)
+    assert e.value.status == xg.XG_ENOTSUP
+    paper = XorgensStreams(4, seed=1)
+    with pytest.raises(xg.XgError) as e:
+        xg.xg_generate_u64(paper.ctx, 0, 4, 8, p)
+    assert e.value.status == xg.XG_ENOTSUP
+    torch.cuda.synchronize()
+    _assert_state(gs, _oracle(fam, 1, 4))                      # nothing ran
+
+
+def test_w64_bulk_full_size_sampled():
+    """2048 streams x 2^18 uint64 in the bulk-fill layout (4 GiB, the launch
+    the benchmark times), then FP64; sampled streams against the oracle, and
+    every stream's end position."""
+    count, n = 2048, 1 << 18
+    gs = XorgensStreams(count, seed=42, family=R64W64)
+    flat = gs.fill_u64(n)
+    picks = [0, 1, 2, 777, 1024, 2046, 2047]
+    t = np.arange(n, dtype=np.int64)                          # n is a multiple of 32: no ragged tail
+    idx = np.stack([(t // 32) * 32 * count + k * 32 + t % 32 for k in picks])
+    ref = O.OracleStreams64(42, count, O.W64)
+    sel = O.OracleStreams64.from_state(ref.ring[picks], ref.weyl[picks], ref.pos[picks], O.W64)
+    want = sel.u64(n)
+    pos = torch.as_tensor(idx.ravel(), device="cuda")
+    got = flat[pos].cpu().numpy().view(np.uint64).reshape(len(picks), n)
+    assert (got == want).all()
+    del flat
+    f = gs.fill_f64(n)
+    gotf = f[pos].cpu().numpy().reshape(len(picks), n)
+    assert (gotf == sel.f64(n)).all()
+    del f
+    torch.cuda.synchronize()
+    _, _, p = gs.host_state()
+    assert (p == 2 * n).all()
