@@ -9,6 +9,7 @@ latency statistics.
 from __future__ import annotations
 
 import ctypes
+import gc
 import time
 from dataclasses import dataclass
 
@@ -87,11 +88,30 @@ class Server:
             pass
 
 
-def latency_summary(lat_s: np.ndarray, total_rn: int, span_s: float) -> dict:
-    return {"requests": int(lat_s.size), "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
-            "p99_ms": float(np.percentile(lat_s, 99) * 1e3), "max_ms": float(lat_s.max() * 1e3),
-            "mean_ms": float(lat_s.mean() * 1e3), "rn": int(total_rn), "span_s": span_s,
-            "rn_per_s": total_rn / span_s if span_s > 0 else 0.0}
+def latency_summary(lat_s: np.ndarray, total_rn: int, span_s: float, arrival_s: np.ndarray | None = None) -> dict:
+    out = {"requests": int(lat_s.size), "p50_ms": float(np.percentile(lat_s, 50) * 1e3),
+           "p99_ms": float(np.percentile(lat_s, 99) * 1e3), "max_ms": float(lat_s.max() * 1e3),
+           "mean_ms": float(lat_s.mean() * 1e3), "rn": int(total_rn), "span_s": span_s,
+           "rn_per_s": total_rn / span_s if span_s > 0 else 0.0,
+           "over_10ms": int((lat_s > 0.010).sum())}
+    if arrival_s is not None and lat_s.size:
+        out["worst_arrival_s"] = float(arrival_s[int(lat_s.argmax())])
+    return out
+
+
+class _NoCollector:
+    """Keeps Python's cyclic garbage collector off for a timed replay: a full
+    collection over the hundreds of thousands of completion records would
+    stall the polling loop (and so every request in flight) for tens of ms."""
+
+    def __enter__(self):
+        self.was = gc.isenabled()
+        gc.collect()
+        gc.disable()
+
+    def __exit__(self, *exc):
+        if self.was:
+            gc.enable()
 
 
 def run_trace(server: Server, trace, keep_outputs: bool = False, timeout_s: float = 120.0):
@@ -106,23 +126,25 @@ def run_trace(server: Server, trace, keep_outputs: bool = False, timeout_s: floa
     outputs = {}
     arrival_ns = {}
     deadline = t0 + int(timeout_s * 1e9)
-    while len(done) < len(reqs):
-        now = time.monotonic_ns()
-        if now > deadline:
-            raise TimeoutError("serving trace did not finish in %.0f s" % timeout_s)
-        while idx < len(reqs) and t0 + int(reqs[idx].arrival_s * 1e9) <= now:
-            r = reqs[idx]
-            arrival_ns[r.rid] = t0 + int(r.arrival_s * 1e9)
-            server.submit(r.rid, r.stream, r.n, r.dtype)
-            idx += 1
-        for c in server.poll():
-            if keep_outputs:
-                outputs[c.id] = server.output(c).clone()
-            server.release(c.id)
-            done.append(c)
+    with _NoCollector():
+        while len(done) < len(reqs):
+            now = time.monotonic_ns()
+            if now > deadline:
+                raise TimeoutError("serving trace did not finish in %.0f s" % timeout_s)
+            while idx < len(reqs) and t0 + int(reqs[idx].arrival_s * 1e9) <= now:
+                r = reqs[idx]
+                arrival_ns[r.rid] = t0 + int(r.arrival_s * 1e9)
+                server.submit(r.rid, r.stream, r.n, r.dtype)
+                idx += 1
+            for c in server.poll():
+                if keep_outputs:
+                    outputs[c.id] = server.output(c).clone()
+                server.release(c.id)
+                done.append(c)
     lat = np.array([(c.t_done_ns - arrival_ns[c.id]) * 1e-9 for c in done])
+    arr = np.array([(arrival_ns[c.id] - t0) * 1e-9 for c in done])
     span = (max(c.t_done_ns for c in done) - t0) * 1e-9
-    summary = latency_summary(lat, sum(c.n for c in done), span)
+    summary = latency_summary(lat, sum(c.n for c in done), span, arr)
     summary["server"] = server.stats()
     return summary, done, outputs
 
@@ -141,20 +163,21 @@ def run_trace_plain_fifo(streams: XorgensStreams, trace, max_n: int, timeout_s: 
     inflight = []  # (event, request, arrival_ns)
     lat = []
     deadline = t0 + int(timeout_s * 1e9)
-    while len(lat) < len(reqs):
-        now = time.monotonic_ns()
-        if now > deadline:
-            raise TimeoutError("plain FIFO trace did not finish in %.0f s" % timeout_s)
-        while idx < len(reqs) and t0 + int(reqs[idx].arrival_s * 1e9) <= now:
-            r = reqs[idx]
-            launch[r.dtype](streams.ctx, r.stream, 1, r.n, out.data_ptr(), h)
-            ev = torch.cuda.Event()
-            ev.record(stream)
-            inflight.append((ev, r, t0 + int(r.arrival_s * 1e9)))
-            idx += 1
-        while inflight and inflight[0][0].query():
-            _, r, a = inflight.pop(0)
-            lat.append((time.monotonic_ns() - a) * 1e-9)
+    with _NoCollector():
+        while len(lat) < len(reqs):
+            now = time.monotonic_ns()
+            if now > deadline:
+                raise TimeoutError("plain FIFO trace did not finish in %.0f s" % timeout_s)
+            while idx < len(reqs) and t0 + int(reqs[idx].arrival_s * 1e9) <= now:
+                r = reqs[idx]
+                launch[r.dtype](streams.ctx, r.stream, 1, r.n, out.data_ptr(), h)
+                ev = torch.cuda.Event()
+                ev.record(stream)
+                inflight.append((ev, r, t0 + int(r.arrival_s * 1e9)))
+                idx += 1
+            while inflight and inflight[0][0].query():
+                _, r, a = inflight.pop(0)
+                lat.append((time.monotonic_ns() - a) * 1e-9)
     span = (time.monotonic_ns() - t0) * 1e-9
     return latency_summary(np.array(lat), sum(r.n for r in reqs), span)
 
