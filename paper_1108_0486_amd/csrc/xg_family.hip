@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "xg_device.h"
 #include "xg_internal.h"
 
 namespace xg {
@@ -46,24 +47,19 @@ struct MemberW64 {
 
 constexpr uint32_t kStep = 32;  // words of one stream per wavefront step
 
-// Lane l receives lane l-2's value (mod 64): DPP wave_ror:1 twice.  Every lane
-// has a source, so bound_ctrl never applies.
-__device__ __forceinline__ uint32_t rot2(uint32_t v) {
-  v = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
-  return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x13C, 0xF, 0xF, true);
-}
+using dev::splitmix64_at;
+using dev::xcd_block;
+
+// Lane l receives lane l-2's value (mod 64): two one-lane rotations.
+__device__ __forceinline__ uint32_t rot2(uint32_t v) { return dev::lanes_rotate_up(dev::lanes_rotate_up(v)); }
 __device__ __forceinline__ uint64_t rot2(uint64_t v) {
   return (uint64_t)rot2((uint32_t)v) | ((uint64_t)rot2((uint32_t)(v >> 32)) << 32);
 }
 
-// a xor b xor c with gfx950 v_bitop3_b32 (truth table 0x96 on a = 0xF0,
-// b = 0xCC, c = 0xAA).
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
-  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
-}
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) { return dev::xor3(a, b, c); }
 __device__ __forceinline__ uint64_t xor3(uint64_t a, uint64_t b, uint64_t c) {
-  return (uint64_t)xor3((uint32_t)a, (uint32_t)b, (uint32_t)c) |
-         ((uint64_t)xor3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
+  return (uint64_t)dev::xor3((uint32_t)a, (uint32_t)b, (uint32_t)c) |
+         ((uint64_t)dev::xor3((uint32_t)(a >> 32), (uint32_t)(b >> 32), (uint32_t)(c >> 32)) << 32);
 }
 
 __device__ __forceinline__ uint32_t shfl_word(uint32_t v, int src) { return (uint32_t)__shfl((int)v, src); }
@@ -117,14 +113,6 @@ __device__ __forceinline__ typename M::word map_out(typename M::word o) {
   }
 }
 
-// k-th output (k >= 1) of SplitMix64 started at s: finalise s + k * golden gamma.
-__device__ __forceinline__ uint64_t splitmix64_at(uint64_t s, uint64_t k) {
-  uint64_t z = s + k * 0x9E3779B97F4A7C15ull;
-  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-  return z ^ (z >> 31);
-}
-
 template <class M>
 __device__ __forceinline__ typename M::word seed_word(uint64_t v) {
   if constexpr (sizeof(typename M::word) == 4) return (uint32_t)(v >> 32);  // the high w bits
@@ -137,12 +125,12 @@ struct Lanes {
   bool active;   // k < count
 };
 
-__device__ __forceinline__ Lanes lanes_of(uint64_t count) {
+__device__ __forceinline__ Lanes lanes_of(uint64_t count, uint32_t block) {
   Lanes L;
   L.lane = threadIdx.x & 63u;
   L.h = L.lane & 1u;
   L.j = L.lane >> 1;
-  const uint64_t pair = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  const uint64_t pair = ((uint64_t)block * blockDim.x + threadIdx.x) >> 6;
   L.k = 2 * pair + L.h;
   L.active = L.k < count;
   return L;
@@ -182,7 +170,7 @@ template <class M>
 __global__ __launch_bounds__(256) void k_fam_init(unsigned char *__restrict__ state, uint64_t num_streams,
                                                   uint64_t seed) {
   using word = typename M::word;
-  const Lanes L = lanes_of(num_streams);
+  const Lanes L = lanes_of(num_streams, blockIdx.x);
   if (2 * (L.k >> 1) >= num_streams) return;  // wave-uniform: both streams of the pair absent
   const uint64_t s = seed + L.k;
   word prev = seed_word<M>(splitmix64_at(s, L.j + 1u));
@@ -262,7 +250,10 @@ __device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, con
 template <class M, uint32_t KIND, int UNROLL, bool FILL>
 __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict__ state, uint64_t first,
                                                        uint64_t count, uint64_t n, void *__restrict__ out) {
-  const Lanes L = lanes_of(count);
+  // Stream-major: each XCD takes a contiguous range of streams; bulk fill:
+  // plain order, so every XCD's writes spread over the whole dense front
+  // (each measured the faster for its layout).
+  const Lanes L = lanes_of(count, FILL ? blockIdx.x : xcd_block());
   const uint64_t pair = L.k >> 1;
   if (2 * pair >= count) return;  // wave-uniform
   using word = typename M::word;
