@@ -258,7 +258,12 @@ def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    # Untimed warm-up: from an idle GPU the first few dozen bulk launches run
+    # through a power-management transient (measured: a dip from ~600 to
+    # ~900 us per launch that settles back over ~40 launches), so the default
+    # warm-up (4 launches per step) is long enough for the timed region to see
+    # the settled state.
+    ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--waves-per-block", type=int, default=None)
     ap.add_argument("--unroll", type=int, default=None)
