@@ -33,6 +33,12 @@ N = 1 << 20
 SEED = 42
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_u32.json")
+VALU_FILE = os.path.join(ROOT, "profiles", "valu_fused_moments.json")
+# VALU issue capacity: 256 CUs x 4 SIMDs at 2.4 GHz, each SIMD issuing one
+# wave64 instruction per 4 cycles for 32-bit integer and conversion work (16
+# lanes per cycle, 39.3e12 lane operations/s), per 2 cycles for FP32 add /
+# mul / FMA (the published 157.3 TFLOP/s) and per 8 cycles for transcendentals.
+SIMD_CYCLES_PER_S = 256 * 4 * 2.4e9
 KERNEL_SOURCE = os.path.join(ROOT, "paper_1108_0486_amd", "csrc", "xg_kernels.hip")
 
 
@@ -52,6 +58,22 @@ def measured_traffic():
     if rec.get("kernel_source_sha256_16") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def measured_valu():
+    """VALU wave instructions per fused-moments launch (SQ_INSTS_VALU, from
+    the committed rocprofv3 counter run) and the minimum issue time of that
+    instruction mix, or None when absent or taken on another kernel source."""
+    try:
+        with open(VALU_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    insts = rec["valu_wave_insts_per_launch"]
+    mix, cyc = rec["main_loop_valu_mix"], rec["issue_cycles_per_wave_instruction"]
+    return insts, insts * sum(f * cyc[k] for k, f in mix.items()) / SIMD_CYCLES_PER_S
 
 
 def cpu_baseline(threads: int):
@@ -165,8 +187,16 @@ def extra_fused_moments(torch, dev):
     unfused_ms = a.elapsed_time(e) / 5
     del zs, gs
     torch.cuda.empty_cache()
+    valu = measured_valu()
+    roof = None
+    if valu is not None:
+        insts, t_min = valu
+        lane_ops = 64 * insts
+        roof = {"bound": "alu", "achieved": lane_ops / (ms * 1e-3) / 1e12, "peak": lane_ops / t_min / 1e12,
+                "unit": "TOP/s (32-bit VALU lane operations; peak = this instruction mix at full issue)",
+                "frac": t_min / (ms * 1e-3), "valu_wave_insts_per_launch": insts, "min_issue_ms": t_min * 1e3}
     return {"workload": "4096 streams x 2^18 FP32 normals (Box-Muller), sums of z and z^2 in-kernel",
-            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3),
+            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3), "roofline": roof,
             "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3)}
 
 
@@ -269,7 +299,9 @@ def main() -> int:
     ap.add_argument("--unroll", type=int, default=None)
     ap.add_argument("--store-words", type=int, default=None)
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the ragged-batch, fused-moments and serving measurements")
+                    help="skip the ragged-batch, fused-moments, family and serving measurements")
+    ap.add_argument("--extras", default="ragged,fused,family,serving",
+                    help="comma-separated subset of the extra measurements to run")
     ap.add_argument("--serve-requests", type=int, default=200_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -355,10 +387,12 @@ def main() -> int:
     torch.cuda.empty_cache()
     extras = None
     if not args.no_extras:
-        extras = {"ragged_batch": extra_ragged_batch(torch, dev),
-                  "fused_moments": extra_fused_moments(torch, dev),
-                  "family_members": extra_family_members(torch, dev),
-                  "serving": extra_serving(torch, dev, args.serve_requests)}
+        chosen = set(args.extras.split(","))
+        run = [("ragged_batch", "ragged", lambda: extra_ragged_batch(torch, dev)),
+               ("fused_moments", "fused", lambda: extra_fused_moments(torch, dev)),
+               ("family_members", "family", lambda: extra_family_members(torch, dev)),
+               ("serving", "serving", lambda: extra_serving(torch, dev, args.serve_requests))]
+        extras = {key: f() for key, name, f in run if name in chosen}
 
     wpb, un, sw = gs.plain_tune()
     line = {
