@@ -224,7 +224,7 @@ def extra_family_members(torch, dev):
                     o = out if layout == "fill" else out.view(S, n)
                     if kind in ("f32", "f64"):
                         o = o.view(torch.float32 if wbytes == 4 else torch.float64)
-                    for _ in range(3):
+                    for _ in range(30):        # past the clock transient of a fresh launch series
                         f(n, out=o)
                     reps = 20
                     a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

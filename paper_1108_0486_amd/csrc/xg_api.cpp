@@ -74,11 +74,14 @@ xg_status check_range(const xg_ctx *ctx, uint64_t first, uint64_t count, uint64_
 bool paper_member(const xg_ctx *ctx) { return ctx && ctx->family == XG_FAMILY_R128_W32; }
 
 // The plain shape with an automatic waves_per_block resolved for this launch
-// (the further members run two streams per wavefront).
+// (the further members run two streams per wavefront).  The 64-bit member
+// takes one wavefront per block: measured ~10 % faster than four for its bulk
+// fill and equal for stream-major, where the 32-bit kernels want four.
 xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count) {
   xg::Shape s = ctx->plain;
   const uint64_t waves = ctx->family == XG_FAMILY_R128_W32 ? count : (count + 1) / 2;
-  if (s.waves_per_block == 0) s.waves_per_block = xg::auto_waves_per_block(waves, ctx->num_cus);
+  if (s.waves_per_block == 0)
+    s.waves_per_block = ctx->family == XG_FAMILY_R64_W64 ? 1u : xg::auto_waves_per_block(waves, ctx->num_cus);
   return s;
 }
 
