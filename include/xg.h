@@ -77,9 +77,9 @@ typedef int32_t xg_status;
  *                       (128,65,15,14,12,17); n = 4096.  Every call of this
  *                       header supports it.
  *   XG_FAMILY_R64_W32   w = 32, (64,33,19,19,9,18); n = 2048, a 272-byte
- *                       state.  Plain and bulk-fill u32 / f32 only.
+ *                       state.  Plain and bulk-fill u32 / f32, and xg_skip.
  *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
- *                       (xg_generate_u64 / f64, xg_fill_u64 / f64) only.
+ *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), and xg_skip.
  * The paper gives shifts only for the first; those of the other two were
  * chosen by a search for primitive characteristic polynomials.  Calls a
  * member does not support return XG_ENOTSUP. */
@@ -250,6 +250,8 @@ xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_
  * the characteristic polynomial of T (degree 4096, primitive); the host
  * computes g and each wavefront evaluates g(T) on its stream's state by
  * Horner's rule in steps of 64 words.  The Weyl value advances by J omega.
+ * Every family member is supported: for the r = 64 members P has degree n
+ * (2048 or 4096) and the Horner steps are 32 words.
  * Errors: XG_EINVAL, XG_ERANGE, XG_ENOTSUP (P unavailable), XG_EHIP.  J == 0
  * enqueues nothing. */
 xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream);

@@ -261,18 +261,19 @@ xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, d
 
 xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream) {
   if (!ctx || count == 0) return XG_EINVAL;
-  if (!paper_member(ctx)) return XG_ENOTSUP;
   if (first > ctx->num_streams || count > ctx->num_streams - first) return XG_ERANGE;
   xg_status st = check_ctx_device(ctx);
   if (st != XG_OK || J == 0) return st;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool step = J < xg::kJumpThreshold;
+  xg::JumpPoly g{};
+  if (!step && !xg::jump_polynomial(ctx->family, J, g.w)) return XG_ENOTSUP;
   hipError_t e;
-  if (J < xg::kJumpThreshold) {
-    e = xg::launch_skip(ctx->d_state, first, count, J, nullptr, static_cast<hipStream_t>(stream));
-  } else {
-    xg::JumpPoly g;
-    if (!xg::jump_polynomial(J, g.w)) return XG_ENOTSUP;
-    e = xg::launch_skip(ctx->d_state, first, count, J, &g, static_cast<hipStream_t>(stream));
-  }
+  if (paper_member(ctx))
+    e = xg::launch_skip(ctx->d_state, first, count, J, step ? nullptr : &g, s);
+  else
+    e = xg::launch_family_skip(ctx->family, reinterpret_cast<unsigned char *>(ctx->d_state), first, count, J,
+                               step ? nullptr : &g, s);
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 

@@ -38,6 +38,16 @@ __device__ __forceinline__ uint32_t xcd_block() {
   return b < full ? (b % kXcds) * (full / kXcds) + b / kXcds : b;
 }
 
+// Orders a wavefront's LDS accesses before it against those after it.  Lanes
+// read words other lanes wrote; without a fence the compiler may move (or
+// drop) such accesses as if each lane only ever read its own writes.  The
+// fences cover LDS only, so outstanding global stores are not waited for.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
 // k-th output (k >= 1) of SplitMix64 (Steele, Lea & Flood 2014) started at
 // s: after k increments the state is s + k * gamma, gamma the golden-ratio
 // constant, then the finaliser.

@@ -263,6 +263,83 @@ __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict
     fam_serve<M, KIND, UNROLL, FILL, true>(state, L, first, count, n, reinterpret_cast<word *>(out));
 }
 
+// ---------------------------------------------------------------------------
+// skip: advance each stream by J words without producing them.
+//
+// JUMP = false: the x-part steps through the J words (J small).
+// JUMP = true: T^J = g(T), g = z^J mod P of degree < n (Cayley-Hamilton), is
+// evaluated on the state S0 by Horner's rule in steps of 32 words:
+//   S <- T^32 S  xor  sum_{i < 32} g_{32c + i} T^i S0,   c = n/32 - 1 .. 0.
+// T^32 S is one generator step of the x-part.  T^i S0 is the 64-word window
+// starting i words into S0's continuation E = ring | the next 32 words, so
+// lane 2j + h needs E[j .. j + 63] of its stream: E is staged through LDS once
+// and kept in registers.  The bits of g are wave-uniform (both streams of a
+// wavefront jump by the same J).  W advances by J omega and pos by J.
+// ---------------------------------------------------------------------------
+extern __shared__ __align__(16) unsigned char fam_lds[];
+
+template <class M, bool JUMP>
+__global__ __launch_bounds__(256) void k_fam_skip(unsigned char *__restrict__ state, uint64_t first,
+                                                  uint64_t count, uint64_t J, JumpPoly g) {
+  using word = typename M::word;
+  constexpr uint32_t kN = 64u * 8u * sizeof(word);  // n = r w with r = 64
+  const Lanes L = lanes_of(count, blockIdx.x);
+  if (2 * (L.k >> 1) >= count) return;  // wave-uniform
+  unsigned char *st = state + (first + L.k) * M::state_bytes;
+  word prev = 0, cur = 0, w_start = 0;
+  uint64_t pos = 0;
+  if (L.active) {
+    const word *ring = reinterpret_cast<const word *>(st);
+    prev = ring[L.j];
+    cur = ring[32 + L.j];
+    w_start = *reinterpret_cast<const word *>(st + M::weyl_off);
+    pos = *reinterpret_cast<const uint64_t *>(st + M::pos_off);
+  }
+  const bool word0 = L.j == 0;
+  const word w_end = w_start + (word)J * M::omega;
+  if constexpr (!JUMP) {
+    Ring2<M> r;
+    r.open(prev, cur);
+    const uint64_t nfull = J / kStep;
+    const uint32_t rem = (uint32_t)(J % kStep);
+    for (uint64_t c = 0; c != nfull; ++c) (void)r.step(word0);
+    const word p0 = r.prev, c0 = r.cur;
+    word x = 0;
+    if (rem) x = r.step(word0);
+    store_state<M>(st, L, p0, c0, x, rem, w_end, pos + J);
+  } else {
+    Ring2<M> r;
+    r.open(prev, cur);
+    const word nxt = r.step(word0);            // x_{p+j}: the continuation's next 32 words
+    word *E = reinterpret_cast<word *>(fam_lds) + (threadIdx.x >> 6) * 192u + L.h * 96u;
+    E[L.j] = prev;
+    E[32 + L.j] = cur;
+    E[64 + L.j] = nxt;
+    dev::wave_lds_sync();                      // the reads below take other lanes' words
+    word e[64];
+#pragma unroll
+    for (int i = 0; i < 64; ++i) e[i] = E[L.j + i];
+    word sp = 0, sc = 0;                       // S: words j and 32 + j of the accumulated state
+    for (int c = (int)(kN / kStep) - 1; c >= 0; --c) {
+      if (c != (int)(kN / kStep) - 1) {
+        Ring2<M> t;
+        t.open(sp, sc);
+        const word x = t.step(word0);
+        sp = sc;
+        sc = x;
+      }
+      const uint32_t bits = (uint32_t)(g.w[c >> 1] >> ((c & 1) * 32));
+#pragma unroll
+      for (int i = 0; i < 32; ++i) {
+        const word m = (word)0 - (word)((bits >> i) & 1u);
+        sp ^= e[i] & m;
+        sc ^= e[32 + i] & m;
+      }
+    }
+    store_state<M>(st, L, sp, sc, word(0), 0u, w_end, pos + J);
+  }
+}
+
 template <class M, uint32_t KIND, bool FILL>
 void launch_fam_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t first,
                   uint64_t count, uint64_t n, void *out, hipStream_t stream) {
@@ -302,6 +379,24 @@ hipError_t launch_family_init(uint32_t family, unsigned char *state, uint64_t nu
     hipLaunchKernelGGL(k_fam_init<MemberW64>, grid, block, 0, stream, state, num_streams, seed);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_family_skip(uint32_t family, unsigned char *state, uint64_t first, uint64_t count, uint64_t J,
+                              const JumpPoly *g, hipStream_t stream) {
+  const uint64_t pairs = (count + 1) / 2;
+  const dim3 grid((uint32_t)((pairs + 3) / 4)), block(256);
+  JumpPoly zero{};
+  const JumpPoly &gp = g ? *g : zero;
+  if (family == XG_FAMILY_R64_W32) {
+    if (g) hipLaunchKernelGGL((k_fam_skip<MemberN2048, true>), grid, block, 4 * 192 * 4, stream, state, first, count, J, gp);
+    else hipLaunchKernelGGL((k_fam_skip<MemberN2048, false>), grid, block, 0, stream, state, first, count, J, gp);
+  } else if (family == XG_FAMILY_R64_W64) {
+    if (g) hipLaunchKernelGGL((k_fam_skip<MemberW64, true>), grid, block, 4 * 192 * 8, stream, state, first, count, J, gp);
+    else hipLaunchKernelGGL((k_fam_skip<MemberW64, false>), grid, block, 0, stream, state, first, count, J, gp);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

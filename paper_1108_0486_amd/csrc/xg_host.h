@@ -26,7 +26,13 @@ xg_status plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_s
                      xg_request *h_sorted, uint32_t *h_groups, uint32_t *num_groups, bool allow_segments);
 
 // Jump polynomial z^J mod P of the x-part's characteristic polynomial
-// (4096 bits, little-endian words).  False if P could not be derived.
+// (4096 bits, little-endian words) of Section 2's member.  False if P could
+// not be derived.
 bool jump_polynomial(uint64_t J, uint64_t g[64]);
+
+// The same for a member XG_FAMILY_*: g receives member_degree(family) / 64
+// words.  False for an unknown family or if P could not be derived.
+int member_degree(uint32_t family);
+bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g);
 
 }  // namespace xg

@@ -85,6 +85,11 @@ hipError_t launch_family_init(uint32_t family, unsigned char *state, uint64_t nu
 // counts wavefronts, i.e. pairs of streams.
 hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const Shape &shape, unsigned char *state,
                                   uint64_t first, uint64_t count, uint64_t n, void *out, hipStream_t stream);
+// Advances streams [first, first + count) of a further member by J words: by
+// stepping when g == nullptr, else by evaluating g(T) (g = z^J mod P, its
+// member_degree / 64 low words used).
+hipError_t launch_family_skip(uint32_t family, unsigned char *state, uint64_t first, uint64_t count, uint64_t J,
+                              const JumpPoly *g, hipStream_t stream);
 
 
 }  // namespace xg

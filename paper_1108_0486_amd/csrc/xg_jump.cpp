@@ -1,13 +1,13 @@
-// Host side of jump-ahead (libxg): the characteristic polynomial P of the
-// x-part's step and the jump polynomials z^J mod P.
+// Host side of jump-ahead (libxg): the characteristic polynomial P of each
+// family member's x-part step and the jump polynomials z^J mod P.
 //
 // The x-part of xorgens is GF(2)-linear (Section 1.5 / Section 2 of
-// arXiv:1108.0486): its 4096-bit state moves by a fixed matrix T, and by
-// Cayley-Hamilton T^J = g(T) with g = z^J mod P, deg g < 4096.  The device
-// evaluates g(T) applied to a stream's state (k_skip).  P is obtained once per
-// process from the library's own host stepping of the recurrence, by
+// arXiv:1108.0486): its n-bit state (n = r w) moves by a fixed matrix T, and
+// by Cayley-Hamilton T^J = g(T) with g = z^J mod P, deg g < n.  The device
+// evaluates g(T) applied to a stream's state.  P is obtained once per process
+// and member from the library's own host stepping of the recurrence, by
 // Berlekamp-Massey on one output bit (the minimal polynomial of that bit
-// sequence is P because P is irreducible of degree 4096).
+// sequence is P because P is irreducible of degree n).
 #include <atomic>
 #include <cstdint>
 #include <cstring>
@@ -19,9 +19,9 @@
 namespace xg {
 namespace {
 
-constexpr int kDeg = 4096;          // r w
-constexpr int kW = kDeg / 64;       // words of a residue (degree < 4096)
-constexpr int kPW = kW + 1;         // words of P (degree 4096)
+constexpr int kMaxDeg = 4096;
+constexpr int kMaxW = kMaxDeg / 64;  // words of a residue (degree < 4096)
+constexpr int kMaxPW = kMaxW + 1;    // words of P (degree 4096)
 
 // Carry-less 64 x 64 -> 128 product: with the CPU instruction when present.
 __attribute__((target("pclmul,sse4.1"))) void clmul_hw(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
@@ -63,21 +63,34 @@ void pmul(const uint64_t *a, int wa, const uint64_t *b, int wb, uint64_t *out) {
   }
 }
 
-// Host stepping of the x-part (Section 2) from a fixed non-zero ring; writes
-// bit 0 of x_0 .. x_{nbits-1}.
-void xpart_bit0(std::vector<uint8_t> &bits) {
-  uint32_t ring[128];
-  for (uint32_t i = 0; i < 128; ++i) ring[i] = 0x9E3779B9u * (i + 1) ^ (i << 7);
-  uint32_t head = 0;  // slot of x_{k-128}
+// A member's x-part (Section 2): w-bit words, lags r > s, shifts a..d.
+struct Member {
+  int w, r, s, a, b, c, d;
+  int n() const { return w * r; }
+};
+
+constexpr Member kMembers[3] = {
+    {32, 128, 65, 15, 14, 12, 17},  // XG_FAMILY_R128_W32 (Section 2's parameter set)
+    {32, 64, 33, 19, 19, 9, 18},    // XG_FAMILY_R64_W32
+    {64, 64, 33, 24, 22, 37, 45},   // XG_FAMILY_R64_W64
+};
+
+// Host stepping of a member's x-part from a fixed non-zero ring; writes bit 0
+// of x_0 .. x_{nbits-1}.  Words are held in 64 bits and masked to w bits.
+void xpart_bit0(const Member &m, std::vector<uint8_t> &bits) {
+  const uint64_t mask = m.w == 64 ? ~0ull : (1ull << m.w) - 1;
+  std::vector<uint64_t> ring((size_t)m.r);
+  for (int i = 0; i < m.r; ++i) ring[(size_t)i] = (0x9E3779B97F4A7C15ull * (uint64_t)(i + 1) ^ ((uint64_t)i << 7)) & mask;
+  int head = 0;  // slot of x_{k-r}
   for (size_t k = 0; k < bits.size(); ++k) {
-    const uint32_t xr = ring[head], xs = ring[(head + 63) & 127];  // x_{k-128}, x_{k-65}
-    uint32_t t = xr ^ (xr << 15);
-    t ^= t >> 14;
-    uint32_t v = xs ^ (xs << 12);
-    v ^= v >> 17;
-    const uint32_t x = t ^ v;
-    ring[head] = x;
-    head = (head + 1) & 127;
+    const uint64_t xr = ring[(size_t)head], xs = ring[(size_t)((head + m.r - m.s) % m.r)];  // x_{k-r}, x_{k-s}
+    uint64_t t = xr ^ ((xr << m.a) & mask);
+    t ^= t >> m.b;
+    uint64_t v = xs ^ ((xs << m.c) & mask);
+    v ^= v >> m.d;
+    const uint64_t x = t ^ v;
+    ring[(size_t)head] = x;
+    head = (head + 1) % m.r;
     bits[k] = (uint8_t)(x & 1u);
   }
 }
@@ -113,32 +126,40 @@ int min_poly(const std::vector<uint8_t> &s, std::vector<uint64_t> &poly) {
 }
 
 struct Modulus {
-  uint64_t P[kPW];
-  uint64_t mu[kPW];  // floor(z^8192 / P)
+  int deg = 0, w = 0, pw = 0;   // n, words of a residue, words of P
+  uint64_t P[kMaxPW];
+  uint64_t mu[kMaxPW];          // floor(z^(2n) / P)
   bool ok = false;
 };
 
-Modulus g_mod;
-std::once_flag g_once;
+Modulus g_mod[3];
+std::once_flag g_once[3];
 
-void init_modulus() {
-  std::vector<uint8_t> bits(2 * kDeg + 128);
-  xpart_bit0(bits);
+void init_modulus(int f) {
+  const Member &m = kMembers[f];
+  Modulus &M = g_mod[f];
+  const int n = m.n();
+  M.deg = n;
+  M.w = n / 64;
+  M.pw = M.w + 1;
+  std::vector<uint8_t> bits((size_t)(2 * n + 128));
+  xpart_bit0(m, bits);
   std::vector<uint64_t> poly;
-  if (min_poly(bits, poly) != kDeg || poly.size() != (size_t)kPW) return;
-  std::memcpy(g_mod.P, poly.data(), sizeof(g_mod.P));
-  // mu by long division of z^(2 deg) by P
-  std::vector<uint64_t> rem(2 * kPW + 1, 0);
-  rem[(2 * kDeg) / 64] |= 1ull << ((2 * kDeg) % 64);
-  std::memset(g_mod.mu, 0, sizeof(g_mod.mu));
-  for (int i = 2 * kDeg; i >= kDeg; --i) {
-    if (!((rem[i / 64] >> (i % 64)) & 1u)) continue;
-    g_mod.mu[(i - kDeg) / 64] |= 1ull << ((i - kDeg) % 64);
-    const int sh = i - kDeg;
-    for (int j = 0; j <= kDeg; ++j)
-      if ((g_mod.P[j / 64] >> (j % 64)) & 1u) rem[(j + sh) / 64] ^= 1ull << ((j + sh) % 64);
+  if (min_poly(bits, poly) != n || poly.size() != (size_t)M.pw) return;
+  std::memset(M.P, 0, sizeof(M.P));
+  std::memcpy(M.P, poly.data(), sizeof(uint64_t) * (size_t)M.pw);
+  // mu by long division of z^(2n) by P
+  std::vector<uint64_t> rem((size_t)(2 * M.pw + 1), 0);
+  rem[(size_t)(2 * n) / 64] |= 1ull << ((2 * n) % 64);
+  std::memset(M.mu, 0, sizeof(M.mu));
+  for (int i = 2 * n; i >= n; --i) {
+    if (!((rem[(size_t)i / 64] >> (i % 64)) & 1u)) continue;
+    M.mu[(i - n) / 64] |= 1ull << ((i - n) % 64);
+    const int sh = i - n;
+    for (int j = 0; j <= n; ++j)
+      if ((M.P[j / 64] >> (j % 64)) & 1u) rem[(size_t)(j + sh) / 64] ^= 1ull << ((j + sh) % 64);
   }
-  g_mod.ok = true;
+  M.ok = true;
 }
 
 // out = a >> sh for a of wa words, ow output words.
@@ -151,37 +172,44 @@ void shr(const uint64_t *a, int wa, int sh, uint64_t *out, int ow) {
 }
 
 // out = a * b mod P (exact Barrett reduction: q = floor(floor(ab / z^n) mu / z^n)).
-void mulmod(const uint64_t *a, const uint64_t *b, uint64_t *out) {
-  uint64_t prod[2 * kW], h[kPW], t[2 * kPW], q[kPW], qp[2 * kPW];
-  pmul(a, kW, b, kW, prod);
-  shr(prod, 2 * kW, kDeg, h, kPW);
-  pmul(h, kPW, g_mod.mu, kPW, t);
-  shr(t, 2 * kPW, kDeg, q, kPW);
-  pmul(q, kPW, g_mod.P, kPW, qp);
-  for (int i = 0; i < kW; ++i) out[i] = prod[i] ^ qp[i];
+void mulmod(const Modulus &M, const uint64_t *a, const uint64_t *b, uint64_t *out) {
+  uint64_t prod[2 * kMaxW], h[kMaxPW], t[2 * kMaxPW], q[kMaxPW], qp[2 * kMaxPW];
+  pmul(a, M.w, b, M.w, prod);
+  shr(prod, 2 * M.w, M.deg, h, M.pw);
+  pmul(h, M.pw, M.mu, M.pw, t);
+  shr(t, 2 * M.pw, M.deg, q, M.pw);
+  pmul(q, M.pw, M.P, M.pw, qp);
+  for (int i = 0; i < M.w; ++i) out[i] = prod[i] ^ qp[i];
 }
 
 }  // namespace
 
-bool jump_polynomial(uint64_t J, uint64_t g[64]) {
-  std::call_once(g_once, init_modulus);
-  if (!g_mod.ok) return false;
-  uint64_t base[kW] = {0}, acc[kW] = {0}, tmp[kW];
+int member_degree(uint32_t family) { return family < 3 ? kMembers[family].n() : 0; }
+
+bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g) {
+  if (family >= 3) return false;
+  std::call_once(g_once[family], init_modulus, (int)family);
+  const Modulus &M = g_mod[family];
+  if (!M.ok) return false;
+  uint64_t base[kMaxW] = {0}, acc[kMaxW] = {0}, tmp[kMaxW];
   base[0] = 2;  // z
   acc[0] = 1;
+  const size_t bytes = sizeof(uint64_t) * (size_t)M.w;
   while (J) {
     if (J & 1u) {
-      mulmod(acc, base, tmp);
-      std::memcpy(acc, tmp, sizeof(acc));
+      mulmod(M, acc, base, tmp);
+      std::memcpy(acc, tmp, bytes);
     }
     J >>= 1;
     if (J) {
-      mulmod(base, base, tmp);
-      std::memcpy(base, tmp, sizeof(base));
+      mulmod(M, base, base, tmp);
+      std::memcpy(base, tmp, bytes);
     }
   }
-  std::memcpy(g, acc, sizeof(acc));
+  std::memcpy(g, acc, bytes);
   return true;
 }
+
+bool jump_polynomial(uint64_t J, uint64_t g[64]) { return jump_polynomial(XG_FAMILY_R128_W32, J, g); }
 
 }  // namespace xg

@@ -1,8 +1,8 @@
 // Exercises libxg's host-only code (the batch planner and the jump
 // polynomials) under AddressSanitizer/UndefinedBehaviorSanitizer.  Checks the
 // planner's contract on random tables and its error codes, and prints the
-// jump polynomials of the J given on the command line as hex words
-// (most-significant word first) for comparison with the oracle.
+// jump polynomials of the (member, J) pairs given on the command line as hex
+// words (most-significant word first) for comparison with the oracle.
 #include <cinttypes>
 #include <cstdio>
 #include <cstdlib>
@@ -90,14 +90,27 @@ static int plan_checks() {
   return 0;
 }
 
+// Arguments "f:J": the jump polynomial of member f (XG_FAMILY_*) for J.
 int main(int argc, char **argv) {
   if (plan_checks()) return 1;
+  uint64_t g0[64];
+  CHECK(!xg::jump_polynomial(3u, 1, g0) && xg::member_degree(3u) == 0);  // unknown member
   for (int i = 1; i < argc; ++i) {
-    const uint64_t J = std::strtoull(argv[i], nullptr, 0);
+    char *rest = nullptr;
+    const uint32_t f = (uint32_t)std::strtoul(argv[i], &rest, 0);
+    CHECK(rest && *rest == ':');
+    const uint64_t J = std::strtoull(rest + 1, nullptr, 0);
+    const int words = xg::member_degree(f) / 64;
+    CHECK(words == 32 || words == 64);
     uint64_t gp[64];
-    CHECK(xg::jump_polynomial(J, gp));
-    std::printf("J %" PRIu64 " ", J);
-    for (int w = 63; w >= 0; --w) std::printf("%016" PRIx64, gp[w]);
+    CHECK(xg::jump_polynomial(f, J, gp));
+    if (f == XG_FAMILY_R128_W32) {  // the member-less entry point agrees
+      uint64_t gq[64];
+      CHECK(xg::jump_polynomial(J, gq));
+      for (int w = 0; w < 64; ++w) CHECK(gq[w] == gp[w]);
+    }
+    std::printf("J %u %" PRIu64 " ", f, J);
+    for (int w = words - 1; w >= 0; --w) std::printf("%016" PRIx64, gp[w]);
     std::printf("\n");
   }
   std::printf("OK\n");

@@ -142,8 +142,7 @@ def test_family_unsupported_calls_are_rejected(fam):
     gs = XorgensStreams(4, seed=1, family=fam)
     out = torch.empty(4 * 64, dtype=torch.float64, device="cuda")
     p = out.data_ptr()
-    calls = [lambda: xg.xg_generate_normal(gs.ctx, 0, 4, 8, p), lambda: xg.xg_normal_moments(gs.ctx, 0, 4, 8, p),
-             lambda: xg.xg_skip(gs.ctx, 0, 4, 100)]
+    calls = [lambda: xg.xg_generate_normal(gs.ctx, 0, 4, 8, p), lambda: xg.xg_normal_moments(gs.ctx, 0, 4, 8, p)]
     if fam == R64W64:
         calls += [lambda: xg.xg_generate_u32(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f32(gs.ctx, 0, 4, 8, p)]
     else:
@@ -192,3 +191,42 @@ def test_w64_bulk_full_size_sampled():
     torch.cuda.synchronize()
     _, _, p = gs.host_state()
     assert (p == 2 * n).all()
+
+
+def _oracle_after_skip(fam, seed, count, J, idx):
+    """Oracle state of streams idx after skipping J words: by stepping for
+    small J, else by the oracle's own polynomial jump (pinned to stepping by
+    the oracle tests) with W advanced by J omega."""
+    p = PARAMS[fam]
+    ref = _oracle(fam, seed, count)
+    if J <= 2_000_000:
+        sub = _sub(ref, idx[0], idx[-1] + 1)
+        sub.skip(J)
+        return sub
+    P = O.charpoly(p)
+    g = O.poly_to_words(O.z_pow_mod(J, P), p.n // 64)
+    mask = (1 << p.w) - 1
+    wt = np.uint64 if p.w == 64 else np.uint32
+    rings = np.stack([O.xpart_jump_poly(p, ref.ring[i], g) for i in idx]).astype(wt)
+    weyl = np.array([(int(ref.weyl[i]) + J * p.omega) & mask for i in idx], dtype=wt)
+    pos = np.array([int(ref.pos[i]) + J for i in idx], dtype=np.uint64)
+    if p.w == 64:
+        return O.OracleStreams64.from_state(rings, weyl, pos, p)
+    return O.OracleStreams.from_state(rings, weyl, pos, params=p)
+
+
+@pytest.mark.parametrize("fam", FAMS)
+@pytest.mark.parametrize("J", [1, 31, 32, 33, 1000, (1 << 15) - 1, 1 << 15, 10**6 + 7, 2**40 + 5, 2**63 + 1])
+def test_family_skip_matches_oracle(fam, J):
+    """xg_skip on the further members: stepping below 2^15 words, jump-ahead
+    (z^J mod P evaluated on the device in 32-word Horner steps) above; streams
+    1 .. 5 of 7, so an odd count and untouched neighbours are covered."""
+    gs = XorgensStreams(7, seed=21, family=fam)
+    gs.skip(J, first=1, count=5)
+    idx = [1, 2, 3, 4, 5]
+    want = _oracle_after_skip(fam, 21, 7, J, idx)
+    torch.cuda.synchronize()
+    _assert_state(gs, want, idx=idx)
+    _assert_state(gs, _sub(_oracle(fam, 21, 7), 6, 7), idx=[6])
+    got = _bits(_words(gs, fam, 1000, first=1, count=5))
+    assert (got == _ref_words(want, fam, 1000)).all()

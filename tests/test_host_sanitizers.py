@@ -50,10 +50,12 @@ def test_host_library_code_under_sanitizers(tmp_path):
     cmd = ["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            os.path.join(HERE, "sanitize", "host_driver.cpp"), os.path.join(CSRC, "xg_plan.cpp"),
            os.path.join(CSRC, "xg_jump.cpp")]
-    Js = [1, 63, 4095, 4096, 4097, 123456789, 10**12, (1 << 64) - 1]
-    out = _run(cmd, tmp_path, *map(str, Js))
-    P = O.charpoly(O.PAPER)
-    got = {int(t[1]): int(t[2], 16) for t in (l.split() for l in out.splitlines()) if t and t[0] == "J"}
-    assert sorted(got) == sorted(Js)
-    for J in Js:
-        assert got[J] == O.z_pow_mod(J, P), J
+    Js = [1, 63, 2047, 2048, 4095, 4096, 4097, 123456789, 10**12, (1 << 64) - 1]
+    members = {0: O.PAPER, 1: O.R64, 2: O.W64}               # XG_FAMILY_* -> the oracle's parameters
+    out = _run(cmd, tmp_path, *["%d:%d" % (f, J) for f in members for J in Js])
+    got = {(int(t[1]), int(t[2])): int(t[3], 16) for t in (l.split() for l in out.splitlines()) if t and t[0] == "J"}
+    assert sorted(got) == sorted((f, J) for f in members for J in Js)
+    for f, p in members.items():
+        P = O.charpoly(p)
+        for J in Js:
+            assert got[(f, J)] == O.z_pow_mod(J, P), (f, J)
