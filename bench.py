@@ -93,8 +93,28 @@ def cpu_baseline(threads: int):
     dt = time.perf_counter() - t0
     del np
     return {"value": total / dt, "unit": "RN/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": "one full step: 1024 streams x (2^20 uint32 + 2^20 FP32), plain sequential C oracle, "
                       "one POSIX thread per share of streams (includes per-slice seeding, %.1f s)" % dt}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# The paper's own throughput (Section 3, Table 1), for context only: other
+# hardware (NVIDIA GTX 480 and one GPU of a GTX 295, CUDA 3.2), repeated
+# generation of 10^8 numbers; the paper does not say what was stored.
+PAPER_TABLE1 = {"source": "Section 3, Table 1 (context, not a target)",
+                "xorgensGP_GTX480_rn_per_s": 17.7e9, "xorgensGP_GTX295_rn_per_s": 9.1e9,
+                "hardware": "NVIDIA GeForce GTX 480; one GPU of a GeForce GTX 295; CUDA 3.2"}
 
 
 def extra_ragged_batch(torch, dev):
@@ -187,6 +207,16 @@ def extra_fused_moments(torch, dev):
     unfused_ms = a.elapsed_time(e) / 5
     del zs, gs
     torch.cuda.empty_cache()
+    # the FP64 oracle on a sample of the same workload (host cores)
+    from oracle import oracle as O
+    threads = max(1, min(16, os.cpu_count() or 1))
+    sample = 64
+    st = O.OracleStreams(SEED, sample)
+    t0 = time.perf_counter()
+    st.moments(N, threads=threads)
+    dt = time.perf_counter() - t0
+    cpu = {"value": sample * N / dt, "unit": "normals/s", "cores": threads, "kind": "oracle",
+           "sample": "64 of the 4096 streams x 2^18 FP64 Box-Muller normals and their sums (%.2f s)" % dt}
     valu = measured_valu()
     roof = None
     if valu is not None:
@@ -196,7 +226,7 @@ def extra_fused_moments(torch, dev):
                 "unit": "TOP/s (32-bit VALU lane operations; peak = this instruction mix at full issue)",
                 "frac": t_min / (ms * 1e-3), "valu_wave_insts_per_launch": insts, "min_issue_ms": t_min * 1e3}
     return {"workload": "4096 streams x 2^18 FP32 normals (Box-Muller), sums of z and z^2 in-kernel",
-            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3), "roofline": roof,
+            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3), "roofline": roof, "cpu_oracle": cpu,
             "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3)}
 
 
@@ -442,6 +472,7 @@ def main() -> int:
         "fill_ceiling_GBs": fill_gbs,
         "frac_of_fill_ceiling": achieved / fill_gbs,
         "cpu_baseline": cpu,
+        "paper_context": dict(PAPER_TABLE1, value_over_gtx480=rn_per_step / (ms_per_step * 1e-3) / 17.7e9),
         "extras": extras,
     }
     print(json.dumps(line), flush=True)

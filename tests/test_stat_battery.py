@@ -100,3 +100,49 @@ def test_battery_on_gpu_bulk_fill():
     flat = as_u32(gs.fill_u32(1 << 16))
     assert_battery(battery(flat))
     del torch
+
+
+@pytest.mark.parametrize("member", ["r64_w32", "r64_w64"])
+def test_further_members_linearity_and_battery(member):
+    """The same claims for the further family members: the x-part alone has
+    linear complexity n (2048 or 4096), the Weyl-combined output about N/2
+    (Section 1.5), and the outputs pass the battery."""
+    p = O.R64 if member == "r64_w32" else O.W64
+    N = 2 * p.n + 4000
+    if p.w == 64:
+        st = O.OracleStreams64(42, 1, p)
+        ring = st.ring[0].copy()
+        out = st.u64(N)[0]
+        words = out.view(np.uint32)                       # both halves of every 64-bit output
+        bits = [((out >> np.uint64(b)) & np.uint64(1)).astype(np.uint8) for b in (0, 31, 63)]
+    else:
+        st = O.OracleStreams(42, 1, params=p)
+        ring = st.ring[0].copy()
+        words = st.u32(N)[0]
+        bits = [_bits(words, b) for b in (0, 15, 31)]
+    _, xbits = O.xpart_run(p, ring, N, bit=0, want_bits=True)
+    assert O.berlekamp_massey(xbits).bit_length() - 1 == p.n
+    for b in bits:
+        lc = O.berlekamp_massey(b).bit_length() - 1
+        assert abs(lc - N / 2) <= 12, (member, lc)
+    more = O.OracleStreams64(7, 1, p).u64(1 << 21)[0].view(np.uint32) if p.w == 64 else \
+        O.OracleStreams(7, 1, params=p).u32(1 << 22)[0]
+    assert_battery(battery(more))
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("member", ["r64_w32", "r64_w64"])
+def test_battery_on_gpu_further_members(member):
+    pytest.importorskip("torch")
+    from gpu_helpers import HAVE_GPU
+    if not HAVE_GPU:
+        pytest.skip("no GPU visible")
+    from paper_1108_0486_amd import xg
+    from paper_1108_0486_amd.streams import XorgensStreams
+    if member == "r64_w32":
+        gs = XorgensStreams(2048, seed=42, family=xg.XG_FAMILY_R64_W32)
+        flat = gs.fill_u32(1 << 12).cpu().numpy().view(np.uint32)
+    else:
+        gs = XorgensStreams(2048, seed=42, family=xg.XG_FAMILY_R64_W64)
+        flat = gs.fill_u64(1 << 11).cpu().numpy().view(np.uint32)
+    assert_battery(battery(flat))
