@@ -28,6 +28,7 @@ namespace xg {
 namespace {
 
 using dev::lanes_rotate_up;
+using dev::wave_lds_sync;
 using dev::splitmix64_at;
 using dev::xcd_block;
 using dev::xor3;
@@ -132,16 +133,6 @@ extern __shared__ __align__(16) uint32_t xg_lds[];
 
 __device__ __forceinline__ uint32_t *wave_stage() { return xg_lds + (threadIdx.x >> 6) * 256u; }
 
-// Orders the LDS accesses of a wavefront's lanes before it against those after
-// it.  Lanes read words other lanes wrote; without a fence the compiler may
-// move (or drop) such accesses as if each lane only ever read its own writes.
-// The fences cover LDS only, so outstanding global stores are not waited for;
-// the wavefront's LDS instructions execute in order.
-__device__ __forceinline__ void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-}
 
 // ---------------------------------------------------------------------------
 // A stream's state held by a wavefront: lane j has ring words j and 64 + j;
@@ -401,13 +392,13 @@ __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t id
   box_muller(e, o, z0, z1);
   const bool has0 = !CHECKED || idx < n, has1 = !CHECKED || idx + 1 < n;
   if constexpr (MOMENTS) {
+    // One compensated update per sum and pair: z0 + z1 (one rounding) and
+    // z0^2 + z1^2 as one FMA over the rounded z0^2 (two roundings).  has1
+    // implies has0.
     if (has0) {
-      kahan_add(m.s1, m.c1, z0);
-      kahan_add(m.s2, m.c2, z0 * z0);
-    }
-    if (has1) {
-      kahan_add(m.s1, m.c1, z1);
-      kahan_add(m.s2, m.c2, z1 * z1);
+      const float b = has1 ? z1 : 0.0f;
+      kahan_add(m.s1, m.c1, z0 + b);
+      kahan_add(m.s2, m.c2, __builtin_fmaf(b, b, z0 * z0));
     }
   } else {
     if (pair_aligned && has1) {
