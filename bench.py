@@ -402,6 +402,20 @@ def main() -> int:
         torch.cuda.synchronize()
         fill_ms.append(a.elapsed_time(b))
     fill_gbs = bytes_per_launch / (sorted(fill_ms)[2] * 1e-3) / 1e9
+    # ... and the library's hand-written write-only kernel (16-byte nt stores).
+    from paper_1108_0486_amd import xg as _xg
+    h = stream.cuda_stream
+    for _ in range(10):
+        _xg.xg_fill_value(out_u.data_ptr(), STREAMS * N, 7, h)
+    wv = []
+    for _ in range(10):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        _xg.xg_fill_value(out_u.data_ptr(), STREAMS * N, 7, h)
+        b.record(stream)
+        torch.cuda.synchronize()
+        wv.append(a.elapsed_time(b))
+    write_only_gbs = bytes_per_launch / (sorted(wv)[5] * 1e-3) / 1e9
 
     if args.calibrate_copy:
         src = torch.empty(1 << 28, dtype=torch.int32, device=dev).fill_(1)
@@ -471,6 +485,8 @@ def main() -> int:
         },
         "fill_ceiling_GBs": fill_gbs,
         "frac_of_fill_ceiling": achieved / fill_gbs,
+        "write_only_kernel_GBs": write_only_gbs,
+        "frac_of_write_only_kernel": achieved / write_only_gbs,
         "cpu_baseline": cpu,
         "paper_context": dict(PAPER_TABLE1, value_over_gtx480=rn_per_step / (ms_per_step * 1e-3) / 17.7e9),
         "extras": extras,

@@ -413,6 +413,15 @@ xg_status xg_server_get_stats(const xg_server *srv, xg_server_stats *out);
  * streams (never the caller's buffers).  NULL is accepted. */
 void xg_server_destroy(xg_server *srv);
 
+/* Write-only reference for the generators' store path: d_out[0 .. words)
+ * receive `value`, written with 16-byte stores, each 256-thread block one
+ * contiguous 4 KB piece in dispatch order.  It generates nothing; its
+ * bandwidth is the practical HBM write ceiling the benchmark reports the
+ * generators against.  d_out must be 16-byte aligned.  words == 0 enqueues
+ * nothing.  Errors: XG_EINVAL (NULL), XG_ERANGE, XG_EALIGN, XG_ENOTSUP,
+ * XG_EHIP. */
+xg_status xg_fill_value(void *d_out, uint64_t words, uint32_t value, void *stream);
+
 /* Human-readable name of a status. */
 const char *xg_strerror(xg_status status);
 

@@ -277,6 +277,19 @@ xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void 
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
+xg_status xg_fill_value(void *d_out, uint64_t words, uint32_t value, void *stream) {
+  if (words == 0) return XG_OK;
+  if (!d_out) return XG_EINVAL;
+  if (words > UINT64_MAX / 4) return XG_ERANGE;
+  if (reinterpret_cast<uintptr_t>(d_out) % 16 != 0) return XG_EALIGN;
+  int dev = 0, cus = 0;
+  const xg_status st = current_gfx950(&dev, &cus);
+  if (st != XG_OK) return st;
+  const hipError_t e = xg::launch_fill_value(static_cast<uint32_t *>(d_out), words, value, cus,
+                                             static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
 xg_status xg_box_muller(const uint32_t *d_words, uint64_t pairs, float *d_out, void *stream) {
   if (pairs == 0) return XG_OK;
   if (!d_words || !d_out) return XG_EINVAL;

@@ -75,6 +75,10 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
 hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
                          const SegmentArgs &seg, hipStream_t stream);
 
+// Write-only reference: out[0 .. words) = value with 16-byte non-temporal
+// stores (out 16-byte aligned).
+hipError_t launch_fill_value(uint32_t *out, uint64_t words, uint32_t value, int num_cus, hipStream_t stream);
+
 // Further family members (r = 64, s = 33; two streams per wavefront).
 // Bytes of one stream's state (0: unknown family).
 uint32_t family_state_bytes(uint32_t family);

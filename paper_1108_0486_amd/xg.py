@@ -108,6 +108,7 @@ def lib() -> ctypes.CDLL:
         "xg_box_muller": (st, [vp, u64, vp, vp]),
         "xg_jump_polynomial": (st, [u64, P(u64)]),
         "xg_fill_f32": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_fill_value": (st, [vp, u64, u32, vp]),
         "xg_family_state_bytes": (ctypes.c_size_t, [u32, u64]),
         "xg_init_family": (st, [P(vp), u32, vp, ctypes.c_size_t, u64, u64, vp]),
         "xg_attach_family": (st, [P(vp), u32, vp, ctypes.c_size_t, u64]),
@@ -225,6 +226,10 @@ def fill_index(count: int, n: int, chunk: int = 64):
     head = (t // chunk) * chunk * count + k * chunk + t % chunk
     tail = chunk * full * count + k * rem + (t - chunk * full)
     return np.where(t < chunk * full, head, tail)
+
+
+def xg_fill_value(d_out: int, words: int, value: int, stream: int = 0) -> None:
+    _check(lib().xg_fill_value(d_out, words, value & 0xFFFFFFFF, stream), "xg_fill_value")
 
 
 def xg_family_state_bytes(family: int, num_streams: int) -> int:

@@ -81,3 +81,14 @@ def test_offsets_beyond_2p32_elements(layout):
     torch.cuda.synchronize()
     _, _, pos = gs.host_state()
     assert (pos == n).all()
+
+
+@pytest.mark.parametrize("words", [1, 3, 4, 5, 1000, 1 << 20, (1 << 26) + 7])
+def test_fill_value_reference_kernel(words):
+    out = torch.full((words + 8,), -1, dtype=torch.int32, device="cuda")
+    xg.xg_fill_value(out.data_ptr(), words, 0x12345678, torch.cuda.current_stream().cuda_stream)
+    a = out.cpu().numpy().view(np.uint32)
+    assert (a[:words] == 0x12345678).all() and (a[words:] == 0xFFFFFFFF).all()
+    with pytest.raises(xg.XgError) as e:
+        xg.xg_fill_value(out.data_ptr() + 4, 8, 1)
+    assert e.value.status == xg.XG_EALIGN
