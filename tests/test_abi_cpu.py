@@ -157,3 +157,13 @@ def test_fill_index_chunk32_is_a_permutation():
         full = n // 32
         if full:   # chunk c of stream k is contiguous at (c count + k) 32
             assert idx[count - 1, 32 * full - 1] == (full - 1) * 32 * count + (count - 1) * 32 + 31
+
+
+def test_fill_value_arguments_without_gpu():
+    L = xg.lib()
+    assert L.xg_fill_value(None, 0, 7, None) == xg.XG_OK          # nothing to do
+    assert L.xg_fill_value(None, 16, 7, None) == xg.XG_EINVAL
+    buf = ctypes.create_string_buffer(64 + 16)
+    aligned = (ctypes.addressof(buf) + 15) // 16 * 16
+    assert L.xg_fill_value(aligned + 4, 4, 7, None) == xg.XG_EALIGN
+    assert L.xg_fill_value(aligned, 2**63, 7, None) == xg.XG_ERANGE
