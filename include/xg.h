@@ -77,7 +77,8 @@ typedef int32_t xg_status;
  *                       (128,65,15,14,12,17); n = 4096.  Every call of this
  *                       header supports it.
  *   XG_FAMILY_R64_W32   w = 32, (64,33,19,19,9,18); n = 2048, a 272-byte
- *                       state.  Plain and bulk-fill u32 / f32, and xg_skip.
+ *                       state.  Plain and bulk-fill u32 / f32, normals and
+ *                       fused moments (as for Section 2's member), and xg_skip.
  *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
  *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), and xg_skip.
  * The paper gives shifts only for the first; those of the other two were

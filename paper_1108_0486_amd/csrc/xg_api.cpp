@@ -101,8 +101,16 @@ xg_status family_words(xg_ctx *ctx, xg::Kind kind, bool fill_layout, uint64_t fi
 
 xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, void *out,
                 void *stream) {
-  if (ctx && ctx->family == XG_FAMILY_R64_W32 && (kind == xg::kU32 || kind == xg::kF32))
-    return family_words(ctx, kind, false, first, count, n, out, stream);
+  if (ctx && ctx->family == XG_FAMILY_R64_W32) {
+    if (kind == xg::kU32 || kind == xg::kF32) return family_words(ctx, kind, false, first, count, n, out, stream);
+    // normals and their fused moments (kNormal, kMoments)
+    xg_status st = check_range(ctx, first, count, n, out, kind == xg::kMoments ? 2 : n);
+    if (st != XG_OK || n == 0) return st;
+    const hipError_t e = xg::launch_family_generate(ctx->family, kind, false, plain_shape(ctx, count),
+                                                    reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
+                                                    n, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? XG_OK : XG_EHIP;
+  }
   if (ctx && !paper_member(ctx)) return XG_ENOTSUP;
   const uint64_t per_stream = kind == xg::kMoments ? 2 : n;
   xg_status st = check_range(ctx, first, count, n, out, per_stream);

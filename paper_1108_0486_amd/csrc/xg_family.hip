@@ -24,6 +24,7 @@
 #include <stdint.h>
 
 #include "xg_device.h"
+#include "xg_normal.h"
 #include "xg_internal.h"
 
 namespace xg {
@@ -247,6 +248,135 @@ __device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, con
   store_state<M>(st, L, p0, c0, x, rem, w_start + (word)n * M::omega, pos + n);
 }
 
+// ---------------------------------------------------------------------------
+// normals of the 32-bit member: Box-Muller on consecutive pairs (o_{2m},
+// o_{2m+1}) of each stream's outputs of the call, as for Section 2's member.
+// Two steps give 64 words of each stream, i.e. 32 pairs: lane 2m + h takes
+// pair m of stream h, whose words sit on lanes (4m + h) mod 64 and
+// (4m + 2 + h) mod 64 of the first step (m < 16) or of the second.  MOMENTS:
+// per-lane compensated sums of z and z^2, reduced over the lanes of each
+// stream (their lane parity), instead of storing the variates.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void fam_gather_pair(uint32_t a, uint32_t b, uint32_t m, uint32_t h, uint32_t &e,
+                                                uint32_t &o) {
+  const int se = (int)((4u * m + h) & 63u), so = (int)((4u * m + 2u + h) & 63u);
+  const uint32_t ea = shfl_word(a, se), eb = shfl_word(b, se), oa = shfl_word(a, so), ob = shfl_word(b, so);
+  const bool upper = m >= 16u;
+  e = upper ? eb : ea;
+  o = upper ? ob : oa;
+}
+
+template <bool MOMENTS>
+__device__ __forceinline__ void fam_consume_pair(uint32_t e, uint32_t o, uint64_t idx, uint64_t n, bool on,
+                                                 float *__restrict__ out, bool pair_aligned, dev::Moments &m) {
+  float z0, z1;
+  dev::box_muller(e, o, z0, z1);
+  const bool has0 = on && idx < n, has1 = on && idx + 1 < n;
+  if constexpr (MOMENTS) {
+    if (has0) {  // one compensated update per sum and pair (has1 implies has0)
+      const float b = has1 ? z1 : 0.0f;
+      dev::kahan_add(m.s1, m.c1, z0 + b);
+      dev::kahan_add(m.s2, m.c2, __builtin_fmaf(b, b, z0 * z0));
+    }
+  } else {
+    if (pair_aligned && has1) {
+      typedef float f32x2 __attribute__((ext_vector_type(2)));
+      const f32x2 pair = {z0, z1};
+      __builtin_nontemporal_store(pair, reinterpret_cast<f32x2 *>(out + idx));
+    } else {
+      if (has0) __builtin_nontemporal_store(z0, out + idx);
+      if (has1) __builtin_nontemporal_store(z1, out + idx + 1);
+    }
+  }
+}
+
+// n normals of each of `count` streams (launch index k = stream first + k)
+// at out[k n + t], or their sums at sums[2k], sums[2k + 1].  Consumes
+// 2 ceil(n / 2) words per stream.
+template <bool MOMENTS>
+__global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict__ state, uint64_t first,
+                                                      uint64_t count, uint64_t n, float *__restrict__ out,
+                                                      float *__restrict__ sums) {
+  using M = MemberN2048;
+  const Lanes L = lanes_of(count, xcd_block());
+  if (2 * (L.k >> 1) >= count) return;  // wave-uniform
+  const bool on = L.active;
+  unsigned char *st = state + (first + L.k) * M::state_bytes;
+  uint32_t prev = 0, cur = 0, w_start = 0;
+  uint64_t pos = 0;
+  if (on) {
+    const uint32_t *ring = reinterpret_cast<const uint32_t *>(st);
+    prev = ring[L.j];
+    cur = ring[32 + L.j];
+    w_start = *reinterpret_cast<const uint32_t *>(st + M::weyl_off);
+    pos = *reinterpret_cast<const uint64_t *>(st + M::pos_off);
+  }
+  Ring2<M> g;
+  g.open(prev, cur);
+  const bool word0 = L.j == 0;
+  const uint32_t wlane = (L.j + 1u) * M::omega;
+  uint32_t wbase = w_start;
+  auto next = [&]() {
+    const uint32_t x = g.step(word0);
+    const uint32_t w = wbase + wlane;
+    wbase += kStep * M::omega;
+    return x + (w ^ (w >> M::gamma));
+  };
+  const uint64_t words = n + (n & 1u);
+  const uint64_t nblk = words >> 6;  // 64-word blocks: 32 pairs of each stream
+  const uint32_t rw = (uint32_t)(words & 63u);
+  const uint32_t m = L.j;
+  float *o_s = MOMENTS ? nullptr : out + L.k * n;
+  const bool pair_aligned = !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
+  dev::Moments mo{0.0f, 0.0f, 0.0f, 0.0f};
+  for (uint64_t b = 0; b != nblk; ++b) {
+    const uint32_t oa = next();
+    const uint32_t ob = next();
+    uint32_t e, o;
+    fam_gather_pair(oa, ob, m, L.h, e, o);
+    fam_consume_pair<MOMENTS>(e, o, (b << 6) + 2u * m, n, on, o_s, pair_aligned, mo);
+  }
+  // Tail: rw (even, < 64) more words.
+  uint32_t p0 = g.prev, c0 = g.cur, xl = 0u, rem = 0u;
+  if (rw) {  // wave-uniform
+    uint32_t oa, ob = 0u;
+    if (rw <= 32u) {
+      const uint32_t w = wbase + wlane;
+      xl = g.step(word0);
+      oa = xl + (w ^ (w >> M::gamma));
+      rem = rw & 31u;  // rw == 32 completes the step
+      if (!rem) {
+        p0 = g.prev;
+        c0 = g.cur;
+      }
+    } else {
+      oa = next();
+      p0 = g.prev;
+      c0 = g.cur;
+      const uint32_t w = wbase + wlane;
+      xl = g.step(word0);
+      ob = xl + (w ^ (w >> M::gamma));
+      rem = rw - 32u;
+    }
+    uint32_t e, o;
+    fam_gather_pair(oa, ob, m, L.h, e, o);
+    if (2u * m < rw) fam_consume_pair<MOMENTS>(e, o, (nblk << 6) + 2u * m, n, on, o_s, pair_aligned, mo);
+  }
+  store_state<M>(st, L, p0, c0, xl, rem, w_start + (uint32_t)words * M::omega, pos + words);
+  if constexpr (MOMENTS) {
+    float v1 = mo.s1 - mo.c1, v2 = mo.s2 - mo.c2;
+#pragma unroll
+    for (int off = 32; off >= 2; off >>= 1) {  // even offsets keep each stream's lanes apart
+      v1 += __shfl_xor(v1, off);
+      v2 += __shfl_xor(v2, off);
+    }
+    if (on && L.j == 0) {
+      sums[2 * L.k] = v1;
+      sums[2 * L.k + 1] = v2;
+    }
+  }
+}
+
 template <class M, uint32_t KIND, int UNROLL, bool FILL>
 __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict__ state, uint64_t first,
                                                        uint64_t count, uint64_t n, void *__restrict__ out) {
@@ -405,6 +535,14 @@ hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const S
   const uint64_t pairs = (count + 1) / 2;
   const uint64_t wpb = shape.waves_per_block;
   const dim3 grid((uint32_t)((pairs + wpb - 1) / wpb)), block((uint32_t)(wpb * kWave));
+  if (family == XG_FAMILY_R64_W32 && (kind == kNormal || kind == kMoments)) {
+    float *o = static_cast<float *>(out);
+    if (kind == kNormal)
+      hipLaunchKernelGGL((k_fam_normals<false>), grid, block, 0, stream, state, first, count, n, o, nullptr);
+    else
+      hipLaunchKernelGGL((k_fam_normals<true>), grid, block, 0, stream, state, first, count, n, nullptr, o);
+    return hipGetLastError();
+  }
   if (family == XG_FAMILY_R64_W32 && kind == kU32)
     launch_fam_layout<MemberN2048, kU32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
   else if (family == XG_FAMILY_R64_W32 && kind == kF32)

@@ -9,7 +9,7 @@ the oracle, and so is the state left behind.
 import numpy as np
 import pytest
 
-from gpu_helpers import needs_gpu
+from gpu_helpers import needs_gpu, ulp32_error
 from oracle import oracle as O
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -142,11 +142,11 @@ def test_family_unsupported_calls_are_rejected(fam):
     gs = XorgensStreams(4, seed=1, family=fam)
     out = torch.empty(4 * 64, dtype=torch.float64, device="cuda")
     p = out.data_ptr()
-    calls = [lambda: xg.xg_generate_normal(gs.ctx, 0, 4, 8, p), lambda: xg.xg_normal_moments(gs.ctx, 0, 4, 8, p)]
     if fam == R64W64:
-        calls += [lambda: xg.xg_generate_u32(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f32(gs.ctx, 0, 4, 8, p)]
+        calls = [lambda: xg.xg_generate_normal(gs.ctx, 0, 4, 8, p), lambda: xg.xg_normal_moments(gs.ctx, 0, 4, 8, p),
+                 lambda: xg.xg_generate_u32(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f32(gs.ctx, 0, 4, 8, p)]
     else:
-        calls += [lambda: xg.xg_generate_u64(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f64(gs.ctx, 0, 4, 8, p)]
+        calls = [lambda: xg.xg_generate_u64(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f64(gs.ctx, 0, 4, 8, p)]
     for c in calls:
         with pytest.raises(xg.XgError) as e:
             c()
@@ -230,3 +230,34 @@ def test_family_skip_matches_oracle(fam, J):
     _assert_state(gs, _sub(_oracle(fam, 21, 7), 6, 7), idx=[6])
     got = _bits(_words(gs, fam, 1000, first=1, count=5))
     assert (got == _ref_words(want, fam, 1000)).all()
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 63, 64, 65, 127, 128, 1000, 4133])
+def test_r64w32_normals_match_oracle(n):
+    """Box-Muller normals of the 32-bit member on consecutive output pairs:
+    within 4 FP32 ulp of the FP64 oracle; odd n consumes 2 ceil(n / 2) words.
+    Streams 3 .. 35 of 37 (the last wavefront holds one stream)."""
+    gs = XorgensStreams(37, seed=11, family=R64W32)
+    ref = _sub(_oracle(R64W32, 11, 37), 3, 36)
+    z = gs.normal(n, first=3, count=33).cpu().numpy()
+    zr = ref.normal(n)
+    assert ulp32_error(z, zr).max() <= 4.0
+    torch.cuda.synchronize()
+    _assert_state(gs, ref, idx=list(range(3, 36)))
+    # the words after the normals continue the stream
+    assert (_bits(gs.u32(100, first=3, count=33)) == ref.u32(100)).all()
+
+
+@pytest.mark.parametrize("n", [1, 64, 65, 1000, 4133, 1 << 16])
+def test_r64w32_moments_within_bound(n):
+    """Fused sums of z and z^2 within tau = 27 u of the FP64 oracle's (relative
+    to sum |z| and sum z^2), as for Section 2's member."""
+    gs = XorgensStreams(21, seed=5, family=R64W32)
+    ref = _oracle(R64W32, 5, 21)
+    m = gs.moments(n).cpu().numpy().astype(np.float64)
+    mr = ref.moments(n)
+    tau = 27 * 2.0**-24
+    assert (np.abs(m[:, 0] - mr[:, 0]) <= tau * mr[:, 2]).all()
+    assert (np.abs(m[:, 1] - mr[:, 1]) <= tau * mr[:, 1]).all()
+    torch.cuda.synchronize()
+    _assert_state(gs, ref)
