@@ -216,7 +216,9 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
     const uint8_t bs = s->busy_stream[p.stream];
     const uint64_t words = words_consumed(p.n, p.dtype);
     const uint64_t parts = s->seg_words ? (words + s->seg_words - 1) / s->seg_words : 1;
-    const bool split = parts > 1 && parts <= xg::kMaxSegments;  // longer ones run unsplit
+    // Split only when the segments fit one table (and the jump table): a request of
+    // more parts than max_batch would otherwise never be admitted.  Others run unsplit.
+    const bool split = parts > 1 && parts <= xg::kMaxSegments && parts <= s->max_batch;
     const uint64_t nseg = split ? parts : 1;
     // Wait (keeping this stream's order) when the stream is busy elsewhere,
     // closed by a split request in this batch, or would mix a split request

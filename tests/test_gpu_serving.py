@@ -1,6 +1,8 @@
 """The request server: continuous batching with memory admission and
 per-stream order.  Every request's values equal the oracle's from the
 position it was admitted at, and equal the same request run alone."""
+import time
+
 import numpy as np
 import pytest
 
@@ -174,3 +176,23 @@ def test_invalid_segment_length_rejected():
     for seg in (100, 64, 1 << 31):
         with pytest.raises(ValueError):
             Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4, segment_words=seg)
+
+
+def test_request_with_more_segments_than_a_batch_runs_unsplit():
+    """A request that would split into more segments than one batch table
+    holds (max_batch = 4, 10 segments) is served unsplit instead of waiting
+    forever, and the requests behind it still complete."""
+    gs = XorgensStreams(3, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 17, num_lanes=1, max_batch=4, segment_words=4096)
+    for rid, (stream, n, dt) in enumerate([(0, 10 * 4096, 0), (1, 3 * 4096 + 5, 1), (2, 100, 2), (0, 77, 0)]):
+        srv.submit(rid, stream, n, dt)
+    done, outputs = [], {}
+    deadline = time.monotonic() + 20.0
+    while len(done) < 4 and time.monotonic() < deadline:
+        for c in srv.poll():
+            outputs[c.id] = srv.output(c).clone()
+            srv.release(c.id)
+            done.append(c)
+    assert len(done) == 4, [c.id for c in done]
+    _check_against_oracle(done, outputs, 3)
+    srv.close()
