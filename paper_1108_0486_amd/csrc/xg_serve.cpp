@@ -29,6 +29,7 @@
 #include <map>
 #include <new>
 #include <unordered_map>
+#include <unordered_set>
 #include <vector>
 
 #include "xg.h"
@@ -161,6 +162,7 @@ struct xg_server {
   std::vector<uint8_t> busy_stream;
   std::vector<uint64_t> pos;          // each stream's position after all admitted work
   std::unordered_map<uint64_t, std::pair<uint64_t, uint64_t>> finished;  // id -> (offset, n)
+  std::unordered_set<uint64_t> live;  // ids submitted and not yet released
   std::deque<xg_completion> ready;    // completions not yet handed out
   xg_server_stats stats{};
   uint64_t outstanding = 0;
@@ -409,9 +411,12 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
 xg_status xg_server_submit(xg_server *s, uint64_t id, uint64_t stream, uint64_t n, uint32_t dtype) {
   if (!s || n == 0 || dtype > XG_NORMAL) return XG_EINVAL;
   if (stream >= s->ctx->num_streams || n > s->pool_elems) return XG_ERANGE;
+  if (s->live.count(id)) return XG_EINVAL;
   try {
+    s->live.insert(id);
     s->pending.push_back(Pending{id, stream, n, dtype, now_ns()});
   } catch (const std::bad_alloc &) {
+    s->live.erase(id);
     return XG_ENOMEM;
   }
   ++s->stats.submitted;
@@ -446,6 +451,7 @@ xg_status xg_server_release(xg_server *s, uint64_t id) {
   if (it == s->finished.end()) return XG_EINVAL;
   s->pool.release(it->second.first, it->second.second);
   s->finished.erase(it);
+  s->live.erase(id);
   return XG_OK;
 }
 

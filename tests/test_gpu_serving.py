@@ -122,6 +122,20 @@ def test_oversize_and_bad_requests_rejected():
         srv.release(12345)
     assert e.value.status == xg.XG_EINVAL
     assert srv.outstanding == 0
+    # an id may not be reused until its request is released
+    srv.submit(7, 0, 16, 0)
+    with pytest.raises(xg.XgError) as e:
+        srv.submit(7, 1, 16, 0)
+    assert e.value.status == xg.XG_EINVAL
+    deadline = time.monotonic() + 20.0
+    got = []
+    while not got and time.monotonic() < deadline:
+        got = srv.poll()
+    assert [c.id for c in got] == [7]
+    with pytest.raises(xg.XgError):
+        srv.submit(7, 1, 16, 0)                                    # completed, not yet released
+    srv.release(7)
+    srv.submit(7, 1, 16, 0)                                        # free again
     srv.close()
 
 
