@@ -146,3 +146,55 @@ def test_battery_on_gpu_further_members(member):
         gs = XorgensStreams(2048, seed=42, family=xg.XG_FAMILY_R64_W64)
         flat = gs.fill_u64(1 << 11).cpu().numpy().view(np.uint32)
     assert_battery(battery(flat))
+
+
+def birthday_spacings_collisions(words: np.ndarray, m: int = 512, k_bits: int = 24, rounds: int = 400) -> float:
+    """Birthday spacings (Marsaglia): draw m birthdays in a year of 2^k_bits
+    days (the top k_bits of each word), sort, take the spacings and count the
+    values that occur more than once.  The count is approximately Poisson
+    with mean m^3 / (4 2^k_bits); returns the z-score of the total over
+    `rounds` independent groups."""
+    d = (words[: m * rounds] >> np.uint32(32 - k_bits)).reshape(rounds, m).astype(np.int64)
+    d.sort(axis=1)
+    sp = np.diff(d, axis=1, prepend=0)
+    sp.sort(axis=1)
+    coll = int((np.diff(sp, axis=1) == 0).sum())
+    lam = rounds * m**3 / (4 * 2**k_bits)
+    return (coll - lam) / math.sqrt(lam)
+
+
+def gap_test_chi2(words: np.ndarray, lo: float = 0.0, hi: float = 0.5, classes: int = 12) -> float:
+    """Knuth's gap test: lengths of runs between successive uniforms falling
+    in [lo, hi); a gap of length g has probability p (1 - p)^g, the last
+    class collecting g >= classes - 1.  Returns the chi-square statistic
+    (classes - 1 degrees of freedom)."""
+    u = words.astype(np.float64) / 2**32
+    hits = np.flatnonzero((u >= lo) & (u < hi))
+    gaps = np.diff(hits) - 1
+    p = hi - lo
+    counts = np.bincount(np.minimum(gaps, classes - 1), minlength=classes).astype(np.float64)
+    probs = np.array([p * (1 - p) ** g for g in range(classes - 1)] + [(1 - p) ** (classes - 1)])
+    e = probs * gaps.size
+    return float(((counts - e) ** 2 / e).sum())
+
+
+def test_birthday_spacings_and_gap_on_oracle_streams():
+    """Two more classical tests on the paper's member and the further members;
+    thresholds far in the tails (false alarm << 1e-6)."""
+    for words in (O.OracleStreams(42, 1).u32(1 << 21)[0],
+                  O.OracleStreams(42, 1, params=O.R64).u32(1 << 21)[0],
+                  O.OracleStreams64(42, 1, O.W64).u64(1 << 20)[0].view(np.uint32)):
+        assert abs(birthday_spacings_collisions(words)) < 6
+        assert gap_test_chi2(words) < 60                       # 11 dof: P(chi2 > 60) ~ 1e-8
+
+
+def test_birthday_spacings_and_gap_catch_defects():
+    """The two tests reject sequences with known defects: a lattice
+    (k 69069 + 1 mod 2^32, whose spacings repeat) for birthday spacings, and
+    a sequence whose uniforms avoid long gaps for the gap test."""
+    lattice = ((np.arange(1 << 18, dtype=np.uint64) * np.uint64(69069) + np.uint64(1)) & np.uint64(0xFFFFFFFF))
+    assert abs(birthday_spacings_collisions(lattice.astype(np.uint32))) > 6
+    u = O.OracleStreams(42, 1).u32(1 << 20)[0]
+    alternating = u.copy()
+    alternating[::2] = alternating[::2] >> np.uint32(1)        # every other uniform < 1/2: gaps stay short
+    assert gap_test_chi2(alternating) > 100
