@@ -381,23 +381,25 @@ typedef struct {
 /* Device bytes of request tables and workspaces a server needs. */
 size_t xg_server_device_bytes(const xg_server_config *cfg);
 
-/* Creates a server.  d_pool (pool_elems 4-byte elements, 256-byte aligned)
- * holds request outputs; d_tables (xg_server_device_bytes(cfg) bytes,
- * 256-byte aligned) holds request tables.  Both stay owned by the caller.
- * Creates num_lanes HIP streams (default priority) and pinned host staging;
- * synchronises the device once and reads the streams' positions.  The server
- * keeps those positions on the host, so while it exists no other call may
- * advance the streams of ctx.  Section 2's member only (others: XG_ENOTSUP).
- * Errors: XG_EINVAL, XG_ERANGE (a buffer too small), XG_EALIGN, XG_ENOMEM,
- * XG_ENOTSUP, XG_EHIP. */
+/* Creates a server.  d_pool (pool_elems >= 64 4-byte elements, 256-byte
+ * aligned) holds request outputs: the server hands out 64-element-aligned
+ * ranges of its first floor(pool_elems / 64) * 64 elements.  d_tables
+ * (xg_server_device_bytes(cfg) bytes, 256-byte aligned) holds request tables.
+ * Both stay owned by the caller.  Creates num_lanes HIP streams (default
+ * priority) and pinned host staging; synchronises the device once and reads
+ * the streams' positions.  The server keeps those positions on the host, so
+ * while it exists no other call may advance the streams of ctx.  Section 2's
+ * member only (others: XG_ENOTSUP).
+ * Errors: XG_EINVAL (among others pool_elems < 64), XG_ERANGE (a buffer too
+ * small), XG_EALIGN, XG_ENOMEM, XG_ENOTSUP, XG_EHIP. */
 xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config *cfg,
                            void *d_pool, uint64_t pool_elems, void *d_tables, size_t tables_bytes);
 
 /* Queues a request of n >= 1 values under the caller's tag id, which must not
  * belong to a request still pending, in flight, or completed and not yet
  * released.  Errors: XG_EINVAL (NULL server, n == 0, bad dtype, id in use),
- * XG_ERANGE (stream out of range, or n larger than the whole pool: such a
- * request could never be admitted). */
+ * XG_ERANGE (stream out of range, or n rounded up to a multiple of 64 larger
+ * than the usable pool: such a request could never be admitted). */
 xg_status xg_server_submit(xg_server *srv, uint64_t id, uint64_t stream, uint64_t n, uint32_t dtype);
 
 /* Makes progress without blocking: reaps finished batches, admits and

@@ -34,10 +34,10 @@
 
 #include "xg.h"
 #include "xg_internal.h"
+#include "xg_pool.h"
 
 namespace {
 
-constexpr uint64_t kAlignElems = 64;  // pool allocations in 256-byte units
 constexpr size_t kAlignBytes = 256;
 
 uint64_t now_ns() {
@@ -49,53 +49,6 @@ uint64_t now_ns() {
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 uint64_t words_consumed(uint64_t n, uint32_t dtype) { return dtype == XG_NORMAL ? n + (n & 1) : n; }
-
-// First-fit allocator over [0, capacity) elements with coalescing frees.
-class Pool {
- public:
-  explicit Pool(uint64_t capacity) : capacity_(capacity) {
-    if (capacity_) free_[0] = capacity_;
-  }
-  // Returns the offset, or UINT64_MAX if no free range fits.
-  uint64_t alloc(uint64_t n) {
-    const uint64_t need = (n + kAlignElems - 1) / kAlignElems * kAlignElems;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= need) {
-        const uint64_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > need) free_[off + need] = len - need;
-        used_ += need;
-        return off;
-      }
-    }
-    return UINT64_MAX;
-  }
-  void release(uint64_t off, uint64_t n) {
-    const uint64_t len = (n + kAlignElems - 1) / kAlignElems * kAlignElems;
-    used_ -= len;
-    auto next = free_.lower_bound(off);
-    uint64_t start = off, size = len;
-    if (next != free_.begin()) {
-      auto prev = std::prev(next);
-      if (prev->first + prev->second == start) {
-        start = prev->first;
-        size += prev->second;
-        free_.erase(prev);
-      }
-    }
-    if (next != free_.end() && start + size == next->first) {
-      size += next->second;
-      free_.erase(next);
-    }
-    free_[start] = size;
-  }
-  uint64_t used() const { return used_; }
-
- private:
-  uint64_t capacity_;
-  uint64_t used_ = 0;
-  std::map<uint64_t, uint64_t> free_;  // offset -> length
-};
 
 struct Pending {
   uint64_t id, stream, n;
@@ -154,7 +107,7 @@ struct xg_server {
   uint32_t max_batch = 0;
   xg_tune tune{};
   bool default_tune = true;
-  Pool pool{0};
+  xg::Pool pool{0};
   std::vector<Lane> lanes;
   std::deque<Pending> pending;
   // 0 free; 1 inside an in-flight batch; 2 in the batch being built;
@@ -315,7 +268,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
                            uint64_t pool_elems, void *d_tables, size_t tables_bytes) {
   if (!out) return XG_EINVAL;
   *out = nullptr;
-  if (!ctx || !config_valid(cfg) || !d_pool || !d_tables || pool_elems == 0) return XG_EINVAL;
+  if (!ctx || !config_valid(cfg) || !d_pool || !d_tables || pool_elems < xg::kPoolAlignElems) return XG_EINVAL;
   if (ctx->family != XG_FAMILY_R128_W32) return XG_ENOTSUP;
   if (tables_bytes < xg_server_device_bytes(cfg)) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_pool) % kAlignBytes || reinterpret_cast<uintptr_t>(d_tables) % kAlignBytes)
@@ -336,7 +289,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
     s->max_batch = cfg->max_batch;
     s->tune = cfg->tune;
     s->default_tune = default_tune;
-    s->pool = Pool(pool_elems);
+    s->pool = xg::Pool(pool_elems);
     s->busy_stream.assign(ctx->num_streams, 0);
     s->pos.assign(ctx->num_streams, 0);
   } catch (const std::bad_alloc &) {
@@ -410,7 +363,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
 
 xg_status xg_server_submit(xg_server *s, uint64_t id, uint64_t stream, uint64_t n, uint32_t dtype) {
   if (!s || n == 0 || dtype > XG_NORMAL) return XG_EINVAL;
-  if (stream >= s->ctx->num_streams || n > s->pool_elems) return XG_ERANGE;
+  if (stream >= s->ctx->num_streams || xg::round_elems(n) > s->pool.capacity()) return XG_ERANGE;
   if (s->live.count(id)) return XG_EINVAL;
   try {
     s->live.insert(id);

@@ -210,3 +210,31 @@ def test_request_with_more_segments_than_a_batch_runs_unsplit():
     assert len(done) == 4, [c.id for c in done]
     _check_against_oracle(done, outputs, 3)
     srv.close()
+
+
+def test_pool_not_a_multiple_of_64():
+    """The server uses floor(pool_elems / 64) * 64 elements of its pool (its
+    ranges are 64-element aligned): a request that rounds up past that is
+    rejected at submit instead of waiting forever, one that fits is served,
+    and a pool of fewer than 64 elements is refused."""
+    gs = XorgensStreams(2, seed=SEED)
+    with pytest.raises(xg.XgError) as e:
+        Server(gs, pool_elems=63, num_lanes=1, max_batch=4)
+    assert e.value.status == xg.XG_EINVAL
+    srv = Server(gs, pool_elems=100, num_lanes=1, max_batch=4)
+    with pytest.raises(xg.XgError) as e:
+        srv.submit(0, 0, 65, 0)
+    assert e.value.status == xg.XG_ERANGE
+    for rid, (stream, n, dt) in enumerate([(0, 64, 0), (1, 1, 1), (0, 33, 2)]):
+        srv.submit(rid, stream, n, dt)
+    done, outputs = [], {}
+    deadline = time.monotonic() + 20.0
+    while len(done) < 3 and time.monotonic() < deadline:
+        for c in srv.poll():
+            assert c.out_offset + c.n <= 64
+            outputs[c.id] = srv.output(c).clone()
+            srv.release(c.id)
+            done.append(c)
+    assert len(done) == 3, [c.id for c in done]
+    _check_against_oracle(done, outputs, 2)
+    srv.close()

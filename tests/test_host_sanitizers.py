@@ -6,7 +6,8 @@ undefined (any report aborts the program):
     stepping, Berlekamp-Massey, primitivity, polynomial jump-ahead);
   * libxg's host-only sources (the batch planner and the jump polynomials,
     which include no HIP header), whose jump polynomials must also equal the
-    oracle's z^J mod P.
+    oracle's z^J mod P;
+  * the request server's output pool, fuzzed against a brute-force model.
 """
 import os
 import shutil
@@ -59,3 +60,10 @@ def test_host_library_code_under_sanitizers(tmp_path):
         P = O.charpoly(p)
         for J in Js:
             assert got[(f, J)] == O.z_pow_mod(J, P), (f, J)
+
+
+def test_server_pool_under_sanitizers(tmp_path):
+    """The server's output pool against a brute-force occupancy model."""
+    _need("g++")
+    cmd = ["g++", "-std=c++17", *SAN, "-I", CSRC, os.path.join(HERE, "sanitize", "pool_driver.cpp")]
+    _run(cmd, tmp_path)
