@@ -27,6 +27,11 @@ __device__ __forceinline__ uint32_t xor_and(uint32_t a, uint32_t b, uint32_t m) 
   return __builtin_amdgcn_bitop3_b32(a, b, m, 0x78);
 }
 
+// Bits of a where m is set, of b elsewhere: (a & m) | (b & ~m), 0xE4.
+__device__ __forceinline__ uint32_t select_bits(uint32_t a, uint32_t b, uint32_t m) {
+  return __builtin_amdgcn_bitop3_b32(a, b, m, 0xE4);
+}
+
 // Workgroups are dispatched to MI355X's 8 XCDs in turn (block b to XCD
 // b mod 8) and each XCD has its own L2.  Renumbering the first 8 floor(nb / 8)
 // blocks so that XCD x gets the consecutive numbers [x nb8, (x + 1) nb8),

@@ -273,10 +273,9 @@ __device__ __forceinline__ void fam_consume_pair(uint32_t e, uint32_t o, uint64_
   dev::box_muller(e, o, z0, z1);
   const bool has0 = on && idx < n, has1 = on && idx + 1 < n;
   if constexpr (MOMENTS) {
-    if (has0) {  // one compensated update per sum and pair (has1 implies has0)
-      const float b = has1 ? z1 : 0.0f;
-      dev::kahan_add(m.s1, m.c1, z0 + b);
-      dev::kahan_add(m.s2, m.c2, __builtin_fmaf(b, b, z0 * z0));
+    if (has0) {  // a group of one pair per compensated update (has1 implies has0)
+      dev::group_add(m, z0, has1 ? z1 : 0.0f);
+      dev::group_close(m);
     }
   } else {
     if (pair_aligned && has1) {
@@ -328,7 +327,7 @@ __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict_
   const uint32_t m = L.j;
   float *o_s = MOMENTS ? nullptr : out + L.k * n;
   const bool pair_aligned = !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
-  dev::Moments mo{0.0f, 0.0f, 0.0f, 0.0f};
+  dev::Moments mo{0.0f, 0.0f, 0.0f, 0.0f, -0.0f, -0.0f};
   for (uint64_t b = 0; b != nblk; ++b) {
     const uint32_t oa = next();
     const uint32_t ob = next();

@@ -29,7 +29,8 @@ namespace xg {
 namespace {
 
 using dev::box_muller;
-using dev::kahan_add;
+using dev::group_add;
+using dev::group_close;
 using dev::lanes_rotate_up;
 using dev::Moments;
 using dev::wave_lds_sync;
@@ -332,14 +333,8 @@ __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t id
   box_muller(e, o, z0, z1);
   const bool has0 = !CHECKED || idx < n, has1 = !CHECKED || idx + 1 < n;
   if constexpr (MOMENTS) {
-    // One compensated update per sum and pair: z0 + z1 (one rounding) and
-    // z0^2 + z1^2 as one FMA over the rounded z0^2 (two roundings).  has1
-    // implies has0.
-    if (has0) {
-      const float b = has1 ? z1 : 0.0f;
-      kahan_add(m.s1, m.c1, z0 + b);
-      kahan_add(m.s2, m.c2, __builtin_fmaf(b, b, z0 * z0));
-    }
+    // Into the open group (the caller closes groups); has1 implies has0.
+    if (has0) group_add(m, z0, has1 ? z1 : 0.0f);
   } else {
     if (pair_aligned && has1) {
       const f32x2 pair = {z0, z1};
@@ -366,7 +361,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
   const uint64_t words = n + (n & 1u);
   const uint64_t nblk = words >> 7;     // 128-word blocks: 64 pairs, one per lane
   const uint32_t rw = (uint32_t)(words & 127u);
-  Moments m = {0.f, 0.f, 0.f, 0.f};
+  Moments m = {0.f, 0.f, 0.f, 0.f, -0.f, -0.f};
   const bool pair_aligned = (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
   const uint64_t nsafe = n >> 7;        // blocks whose 128 normals are all below n
   const uint64_t nouter = nsafe / UNROLL;
@@ -383,6 +378,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
       uint32_t e, o;
       gather_pair(oa, ob, lane, e, o);
       consume_pair<MOMENTS, false>(e, o, ((b + u) << 7) + 2u * lane, n, out, pair_aligned, m);
+      if (MOMENTS && ((u & 3) == 3 || u == UNROLL - 1)) group_close(m);
     }
   }
   for (; b != nsafe; ++b) {
@@ -395,6 +391,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     uint32_t e, o;
     gather_pair(oa, ob, lane, e, o);
     consume_pair<MOMENTS, false>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
+    if (MOMENTS) group_close(m);
   }
   for (; b != nblk; ++b) {
     const uint32_t xa = ring_step(g, lane0);
@@ -406,6 +403,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     uint32_t e, o;
     gather_pair(oa, ob, lane, e, o);
     consume_pair<MOMENTS, true>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
+    if (MOMENTS) group_close(m);
   }
   // Tail: rw (even, < 128) more words.
   uint32_t p0 = g.prev, c0 = g.cur, xl = 0u, rem = 0u;
@@ -431,6 +429,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     uint32_t e, o;
     gather_pair(oa, ob, lane, e, o);
     if (2u * lane < rw) consume_pair<MOMENTS, true>(e, o, (nblk << 7) + 2u * lane, n, out, pair_aligned, m);
+    if (MOMENTS) group_close(m);
   }
   write_state(dst, p0, c0, xl, rem, w_start + (uint32_t)words * kOmega, pos + words, lane);
   if constexpr (MOMENTS) {

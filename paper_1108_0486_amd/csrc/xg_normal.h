@@ -1,6 +1,6 @@
 // Normal variates of libxg's kernels (gfx950): the Box-Muller map on a pair
-// of generator outputs, with the angle reduced exactly, and the compensated
-// sum used by the fused moments.  Shared by every family member's kernels.
+// of generator outputs, with the angle reduced exactly, and the grouped
+// compensated sums used by the fused moments.  Shared by every family member's kernels.
 //
 // u1 = ((e >> 8) + 1) 2^-24 in (0, 1] and u2 = (o >> 8) 2^-24 in [0, 1) are
 // exact; z0 = rho cos(2 pi u2), z1 = rho sin(2 pi u2), rho = sqrt(-2 ln u1).
@@ -9,16 +9,23 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "xg_device.h"
+
 namespace xg {
 namespace dev {
 
-// sin(pi x) and cos(pi x) for x = 2 u2 in [0, 2), a multiple of 2^-23.  The
-// argument is reduced exactly: 2x = q + 2f with q = rint(2x), |f| <= 1/4, so
-// pi x = q pi / 2 + pi f.  sin(pi f) and cos(pi f) come from their Taylor
-// series in t = f^2 (the first omitted terms are below 2e-9 and 1.2e-10
-// relative at |f| = 1/4), the leading pi f of the sine formed with pi split
-// as pi_hi + pi_lo so that it is rounded once.  A quarter-turn rotation by q
-// finishes.  f = 0 gives exact zeros and ones.
+// sin and cos of the angle 2 pi u2, u2 = (o >> 8) 2^-24, with the angle
+// reduced exactly in integer arithmetic on the word o.  With m = o >> 8,
+// 4 u2 = m 2^-22 = q + 2f, where q = floor(4 u2 + 1/2) is the quadrant and
+// |f| <= 1/4, so 2 pi u2 = q pi/2 + pi f.  Adding 2^29 to o leaves q mod 4 in
+// bits 31:30 and (with o's low 8 bits cleared) 2^29 + f 2^31 in bits 29:0,
+// so f is exact.  sin(pi f) and cos(pi f) come from their Taylor series in
+// t = f^2 (the first omitted terms are below 2e-9 and 1.2e-10 relative at
+// |f| = 1/4), the leading pi f of the sine formed with pi split as
+// pi_hi + pi_lo so that it is rounded once.  A quarter-turn rotation by q
+// finishes: odd q swaps sin and cos, and the sign bits come straight from
+// the sum (sin is negated in quadrants 2 and 3, cos in quadrants 1 and 2).
+// f = 0 gives exact zeros and ones.
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kPiHi = (float)kPi;
 constexpr float kPiLo = (float)(kPi - (double)kPiHi);
@@ -32,10 +39,9 @@ constexpr float kC6 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 720.0);
 constexpr float kC8 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 40320.0);
 constexpr float kC10 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 3628800.0);
 
-__device__ __forceinline__ void sincospi_unit(float x, float &s, float &c) {
-  const float y = 2.0f * x;            // exact
-  const float q = rintf(y);            // exact integer 0 .. 4
-  const float f = (y - q) * 0.5f;      // exact, |f| <= 1/4
+__device__ __forceinline__ void sincos_turn(uint32_t o, float &s, float &c) {
+  const uint32_t qf = o + 0x20000000u;
+  const float f = fmaf((float)(qf & 0x3FFFFF00u), 0x1p-31f, -0.25f);  // exact (22-bit integer, dyadic result)
   const float t = f * f;
   float p = fmaf(kS9, t, kS7);
   p = fmaf(p, t, kS5);
@@ -47,26 +53,48 @@ __device__ __forceinline__ void sincospi_unit(float x, float &s, float &c) {
   r = fmaf(r, t, kC4);
   r = fmaf(r, t, kC2);
   const float cp = fmaf(r, t, 1.0f);             // cos(pi f)
-  const uint32_t qi = (uint32_t)(int)q;
-  const bool odd = (qi & 1u) != 0;
-  const float s0 = odd ? cp : sp, c0 = odd ? sp : cp;
-  // sin is negated in quadrants 2, 3; cos in quadrants 1, 2
-  s = __uint_as_float(__float_as_uint(s0) ^ ((qi & 2u) << 30));
-  c = __uint_as_float(__float_as_uint(c0) ^ (((qi + 1u) & 2u) << 30));
+  const uint32_t odd = (uint32_t)((int32_t)(qf << 1) >> 31);  // all ones for odd q
+  const uint32_t spb = __float_as_uint(sp), cpb = __float_as_uint(cp);
+  s = __uint_as_float(xor_and(select_bits(cpb, spb, odd), qf, 0x80000000u));
+  c = __uint_as_float(xor_and(select_bits(spb, cpb, odd), qf + 0x40000000u, 0x80000000u));
+}
+
+// rho = sqrt(-2 ln u1), u1 = ((e >> 8) + 1) 2^-24 in [2^-24, 1].  u1 is never
+// denormal, infinite or NaN, so no special-case guards: the hardware base-2
+// logarithm (within 1 ulp, relative, for every such u1), times -2 ln 2 held
+// as two floats (one rounding), gives x = -2 ln u1; the square root is the
+// hardware reciprocal square root refined by one Newton step on the residual
+// x - r0^2 (an FMA).  Over all 2^24 values of u1, rho is within 1.6 ulp of
+// sqrt(-2 ln u1).  u1 = 1 gives x = -0 and rho = -0 (the reciprocal square
+// root is taken of a tiny normal there instead of zero).
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr float kM2Ln2Hi = (float)(-2.0 * kLn2);
+constexpr float kM2Ln2Lo = (float)(-2.0 * kLn2 - (double)kM2Ln2Hi);
+
+__device__ __forceinline__ float rho_of(uint32_t e) {
+  const float u1 = fmaf((float)(e >> 8), 0x1p-24f, 0x1p-24f);  // exact
+  const float l2 = __builtin_amdgcn_logf(u1);
+  const float x = fmaf(l2, kM2Ln2Hi, l2 * kM2Ln2Lo);
+  const float y = __builtin_amdgcn_rsqf(x + 0x1p-126f);         // x + 2^-126 == x unless x == 0
+  const float r0 = x * y;
+  const float res = fmaf(-r0, r0, x);
+  return fmaf(res, 0.5f * y, r0);
 }
 
 __device__ __forceinline__ void box_muller(uint32_t e, uint32_t o, float &z0, float &z1) {
-  const float u1 = (float)((e >> 8) + 1u) * 0x1p-24f;  // (0, 1], exact
-  const float u2 = (float)(o >> 8) * 0x1p-24f;         // [0, 1), exact
-  const float rho = sqrtf(-2.0f * logf(u1));
+  const float rho = rho_of(e);
   float s, c;
-  sincospi_unit(2.0f * u2, s, c);                      // angle 2 pi u2 reduced exactly
+  sincos_turn(o, s, c);
   z0 = rho * c;
   z1 = rho * s;
 }
 
+// Sums of z and z^2 kept by one lane: each pair is added first (z0 + z1, and
+// z0^2 + z1^2 as one FMA over the rounded z0^2), pairs accumulate plainly in
+// a group of at most four, and each group enters a compensated (Kahan) sum.
 struct Moments {
   float s1, c1, s2, c2;  // compensated sums of z and z^2
+  float g1, g2;          // plain sums of the open group (-0 when empty)
 };
 
 __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
@@ -74,6 +102,18 @@ __device__ __forceinline__ void kahan_add(float &s, float &c, float v) {
   const float t = s + y;
   c = (t - s) - y;
   s = t;
+}
+
+__device__ __forceinline__ void group_add(Moments &m, float z0, float z1) {
+  m.g1 = m.g1 + (z0 + z1);
+  m.g2 = m.g2 + __builtin_fmaf(z1, z1, z0 * z0);
+}
+
+__device__ __forceinline__ void group_close(Moments &m) {
+  kahan_add(m.s1, m.c1, m.g1);
+  kahan_add(m.s2, m.c2, m.g2);
+  m.g1 = -0.0f;  // x + -0 == x, so the next group's first add is free
+  m.g2 = -0.0f;
 }
 
 }  // namespace dev
