@@ -483,7 +483,8 @@ def main() -> int:
             "outputs_per_stream_per_type": N,
             "rn_per_step": rn_per_step,
             "params": "(r,s,a,b,c,d)=(128,65,15,14,12,17), w=32, omega=0x9E3779B9, gamma=16",
-            "launch": {"waves_per_block": wpb, "unroll": un, "store_words": sw},
+            "launch": {"waves_per_block": wpb or "auto: 4 (one stream per SIMD)",
+                       "unroll": un or "auto: 4 for the uint32 fill, 8 for FP32", "store_words": sw},
         },
         "roofline": {
             "bound": "hbm",

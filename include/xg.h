@@ -147,7 +147,8 @@ uint32_t xg_family(const xg_ctx *ctx);
  * xg_autotune_batch picks the fastest for a batch. */
 typedef struct {
     uint32_t waves_per_block;  /* streams served at once by one workgroup: 1, 2, 4, 8, 16 */
-    uint32_t unroll;           /* 64-word chunks per thread per loop trip: 1, 2, 4, 8 */
+    uint32_t unroll;           /* 64-word chunks per thread per loop trip: 1, 2, 4, 8
+                                  (0: chosen per launch, plain tune only) */
     uint32_t blocks_per_cu;    /* persistent workgroups per compute unit: 1 .. 32 */
     uint32_t store_words;      /* words each lane writes per store instruction: 1, or 4
                                   (groups of four chunks staged through a 1 KB LDS slot
@@ -158,8 +159,10 @@ typedef struct {
  * (waves_per_block, unroll and store_words are used; blocks_per_cu is
  * ignored).  waves_per_block 0 chooses per launch: 4 when count >= 4 x the
  * compute units, else 2 when count >= 2 x, else 1, so one stream's wavefront
- * lands on each SIMD before any SIMD gets a second.  The default is
- * {0, 8, 1, 4}.  Output bits do not depend on it.
+ * lands on each SIMD before any SIMD gets a second.  unroll 0 chooses per
+ * launch: 4 for the bulk-fill uint32 launch of Section 2's member (faster
+ * and steadier there, measured), 8 for every other launch.  The default is
+ * {0, 0, 1, 4}.  Output bits do not depend on it.
  * Errors: XG_EINVAL (NULL pointer or a shape outside the ranges of xg_tune). */
 xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune);
 xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune);

@@ -19,12 +19,12 @@ enum Kind : uint32_t { kU32 = XG_U32, kF32 = XG_F32, kNormal = XG_NORMAL, kMomen
 
 struct Shape {
   uint32_t waves_per_block;  // 1, 2, 4, 8, 16; 0 (plain launches only): chosen per launch
-  uint32_t unroll;           // 1, 2, 4, 8
+  uint32_t unroll;           // 1, 2, 4, 8; 0 (plain launches only): chosen per launch
   uint32_t blocks_per_cu;    // persistent batch only
   uint32_t store_words;      // 1 or 4 (4 needs unroll >= 4)
 };
 
-constexpr Shape kDefaultPlain{0, 8, 1, 4};
+constexpr Shape kDefaultPlain{0, 0, 1, 4};  // waves_per_block and unroll chosen per launch
 
 // Waves per block for a plain launch of `count` streams on `num_cus` compute
 // units: one stream per wavefront, and at least as many blocks as compute

@@ -122,9 +122,30 @@ def test_wide_stores_with_unaligned_output(n):
 
 def test_default_plain_shape():
     gs = XorgensStreams(2, seed=1)
-    assert gs.plain_tune() == (0, 8, 4)
+    assert gs.plain_tune() == (0, 0, 4)
     gs.set_plain_tune(0, 4, 1)
     assert gs.plain_tune() == (0, 4, 1)
+    gs.set_plain_tune(2, 0, 0)                 # automatic unroll, default store width
+    assert gs.plain_tune() == (2, 0, 4)
+
+
+@pytest.mark.parametrize("kind", ["fill_u32", "fill_f32", "u32", "f32"])
+def test_automatic_unroll_matches_oracle(kind):
+    """The automatic unroll (4 for the uint32 bulk fill, 8 otherwise) gives
+    the oracle's bits, with a ragged length, like every explicit shape."""
+    count, n = 9, 64 * 13 + 5
+    gs = XorgensStreams(count, seed=77)
+    ref = O.OracleStreams(77, count)
+    want = ref.u32(n) if kind.endswith("u32") else ref.f32(n)
+    if kind.startswith("fill"):
+        got = getattr(gs, kind)(n)
+        idx = torch.as_tensor(xg.fill_index(count, n), device="cuda")
+        got = got[idx].view(count, n)
+    else:
+        got = getattr(gs, kind)(n)
+    got = as_u32(got) if kind.endswith("u32") else got.cpu().numpy()
+    assert (got == want).all()
+    _assert_state(gs, ref)
 
 
 @pytest.mark.parametrize("count", [1, 255, 256, 511, 512, 1023, 1024, 1025, 2049])
