@@ -359,7 +359,7 @@ def main() -> int:
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(streams are independent and would shard by stream id with no exchange)", file=sys.stderr)
         return 2
 
