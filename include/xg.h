@@ -407,7 +407,12 @@ xg_status xg_server_submit(xg_server *srv, uint64_t id, uint64_t stream, uint64_
 
 /* Makes progress without blocking: reaps finished batches, admits and
  * launches, and returns up to max_out completions (more wait for the next
- * poll).  Errors: XG_EINVAL, XG_EHIP. */
+ * poll).  Errors: XG_EINVAL (bad arguments; nothing changes), XG_EHIP,
+ * XG_ENOMEM.  A poll that fails with XG_EHIP or XG_ENOMEM (or with any other
+ * status once it has started moving requests) leaves the server failed: the
+ * streams of ctx may have been partly advanced, and every later submit, poll
+ * and release returns that status.  Only xg_server_destroy (and the counters)
+ * remain; outputs of requests already handed out stay valid. */
 xg_status xg_server_poll(xg_server *srv, xg_completion *out, uint32_t max_out, uint32_t *num_out);
 
 /* Returns a completed request's output to the pool.  Errors: XG_EINVAL

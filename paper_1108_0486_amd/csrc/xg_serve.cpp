@@ -26,7 +26,6 @@
 #include <cstdint>
 #include <cstring>
 #include <deque>
-#include <map>
 #include <new>
 #include <unordered_map>
 #include <unordered_set>
@@ -119,6 +118,10 @@ struct xg_server {
   std::deque<xg_completion> ready;    // completions not yet handed out
   xg_server_stats stats{};
   uint64_t outstanding = 0;
+  // Set when a poll fails part-way (a HIP error, or no memory while moving
+  // requests between queues): the host view of streams, pool and queues may
+  // then disagree with the device, so every later call but destroy refuses.
+  xg_status failed = XG_OK;
 };
 
 namespace {
@@ -363,6 +366,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
 
 xg_status xg_server_submit(xg_server *s, uint64_t id, uint64_t stream, uint64_t n, uint32_t dtype) {
   if (!s || n == 0 || dtype > XG_NORMAL) return XG_EINVAL;
+  if (s->failed != XG_OK) return s->failed;
   if (stream >= s->ctx->num_streams || xg::round_elems(n) > s->pool.capacity()) return XG_ERANGE;
   if (s->live.count(id)) return XG_EINVAL;
   try {
@@ -377,9 +381,9 @@ xg_status xg_server_submit(xg_server *s, uint64_t id, uint64_t stream, uint64_t 
   return XG_OK;
 }
 
-xg_status xg_server_poll(xg_server *s, xg_completion *out, uint32_t max_out, uint32_t *num_out) {
-  if (!s || !num_out || (max_out && !out)) return XG_EINVAL;
-  *num_out = 0;
+namespace {
+
+xg_status poll_body(xg_server *s, xg_completion *out, uint32_t max_out, uint32_t *num_out) {
   xg_status st = reap(s);
   if (st != XG_OK) return st;
   for (uint32_t li = 0; li < s->lanes.size() && !s->pending.empty(); ++li) {
@@ -398,8 +402,28 @@ xg_status xg_server_poll(xg_server *s, xg_completion *out, uint32_t max_out, uin
   return XG_OK;
 }
 
+}  // namespace
+
+xg_status xg_server_poll(xg_server *s, xg_completion *out, uint32_t max_out, uint32_t *num_out) {
+  if (!s || !num_out || (max_out && !out)) return XG_EINVAL;
+  *num_out = 0;
+  if (s->failed != XG_OK) return s->failed;
+  xg_status st;
+  try {
+    st = poll_body(s, out, max_out, num_out);
+  } catch (const std::bad_alloc &) {
+    st = XG_ENOMEM;
+  }
+  if (st != XG_OK) {
+    s->failed = st;
+    *num_out = 0;
+  }
+  return st;
+}
+
 xg_status xg_server_release(xg_server *s, uint64_t id) {
   if (!s) return XG_EINVAL;
+  if (s->failed != XG_OK) return s->failed;
   auto it = s->finished.find(id);
   if (it == s->finished.end()) return XG_EINVAL;
   s->pool.release(it->second.first, it->second.second);
