@@ -344,12 +344,14 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
+constexpr int kMaxReps = 100;  // timed repetitions per candidate shape
+
 xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
                             const uint32_t *d_groups, uint32_t num_groups, void *d_scratch_out,
                             uint64_t out_elems, void *d_scratch_state, void *d_work, int reps,
                             xg_tune *best, float *times_ms, uint32_t max_times,
                             uint32_t *num_times, void *stream) {
-  if (!ctx || !best || !d_scratch_state || reps < 1 || reps > 100) return XG_EINVAL;
+  if (!ctx || !best || !d_scratch_state || reps < 1 || reps > kMaxReps) return XG_EINVAL;
   if (!paper_member(ctx)) return XG_ENOTSUP;
   if (num_times) *num_times = 0;
   const hipStream_t s = static_cast<hipStream_t>(stream);
@@ -377,7 +379,8 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
           if (wpb * bpc > 32) continue;  // more waves than a compute unit holds
           if (sw == 4 && un < 4) continue;
           const xg_tune cand{wpb, un, bpc, sw};
-          std::vector<float> ms;
+          float ms[kMaxReps];
+          int nms = 0;
           for (int rep = 0; rep <= reps && result == XG_OK; ++rep) {
             if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) !=
                 hipSuccess) {
@@ -394,11 +397,11 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
             }
             float t = 0.f;
             if (hipEventElapsedTime(&t, t0, t1) != hipSuccess) { result = XG_EHIP; break; }
-            if (rep > 0) ms.push_back(t);  // rep 0 is the warm-up
+            if (rep > 0) ms[nms++] = t;  // rep 0 is the warm-up
           }
           if (result != XG_OK) break;
-          std::sort(ms.begin(), ms.end());
-          const float med = ms[ms.size() / 2];
+          std::sort(ms, ms + nms);
+          const float med = ms[nms / 2];
           if (times_ms && recorded < max_times) {
             float *rec = times_ms + 5 * recorded;
             rec[0] = (float)wpb; rec[1] = (float)un; rec[2] = (float)bpc; rec[3] = med; rec[4] = (float)sw;

@@ -12,6 +12,7 @@
 #include <cstdint>
 #include <cstring>
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "xg_host.h"
@@ -188,7 +189,11 @@ int member_degree(uint32_t family) { return family < 3 ? kMembers[family].n() : 
 
 bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g) {
   if (family >= 3) return false;
-  std::call_once(g_once[family], init_modulus, (int)family);
+  try {
+    std::call_once(g_once[family], init_modulus, (int)family);
+  } catch (const std::bad_alloc &) {  // the once-flag stays unset: a later call retries
+    return false;
+  }
   const Modulus &M = g_mod[family];
   if (!M.ok) return false;
   uint64_t base[kMaxW] = {0}, acc[kMaxW] = {0}, tmp[kMaxW];

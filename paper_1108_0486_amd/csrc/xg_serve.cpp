@@ -295,6 +295,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
     s->pool = xg::Pool(pool_elems);
     s->busy_stream.assign(ctx->num_streams, 0);
     s->pos.assign(ctx->num_streams, 0);
+    s->lanes.resize(cfg->num_lanes);
   } catch (const std::bad_alloc &) {
     delete s;
     return XG_ENOMEM;
@@ -322,13 +323,18 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
     }
   }
   const TableLayout tl = table_layout(cfg);
-  s->lanes.resize(cfg->num_lanes);
   char *base = static_cast<char *>(d_tables);
   if (cfg->segment_words) {
     // z^(k L) mod P for k = 1 .. kJumpEntries, computed on the host once.
     s->seg_words = cfg->segment_words;
     s->d_jump = reinterpret_cast<uint64_t *>(base + tl.per_lane * cfg->num_lanes);
-    std::vector<uint64_t> table((size_t)kJumpEntries * 64);
+    std::vector<uint64_t> table;
+    try {
+      table.resize((size_t)kJumpEntries * 64);
+    } catch (const std::bad_alloc &) {
+      delete s;
+      return XG_ENOMEM;
+    }
     for (uint32_t k = 1; k <= kJumpEntries; ++k) {
       if (!xg::jump_polynomial((uint64_t)k * cfg->segment_words, table.data() + (size_t)(k - 1) * 64)) {
         delete s;
