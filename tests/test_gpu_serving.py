@@ -238,3 +238,63 @@ def test_pool_not_a_multiple_of_64():
     assert len(done) == 3, [c.id for c in done]
     _check_against_oracle(done, outputs, 2)
     srv.close()
+
+
+def _oracle_at(stream: int, q: int, P: int):
+    """The oracle's stream `stream` (seed SEED + stream) moved to word q: by
+    stepping for short moves, else by its own polynomial jump (z^q mod P on
+    the x-part, q omega on the Weyl word)."""
+    ref = O.OracleStreams(SEED + stream, 1)
+    if q == 0:
+        return ref
+    if q < (1 << 16):
+        ref.skip(q)
+        return ref
+    g = O.poly_to_words(O.z_pow_mod(q, P), 64)
+    ring = O.xpart_jump_poly(O.PAPER, ref.ring[0], g)
+    weyl = (int(ref.weyl[0]) + q * O.PAPER.omega) % 2**32
+    return O.OracleStreams.from_state(ring[None, :], np.array([weyl], dtype=np.uint32), np.array([q], dtype=np.uint64))
+
+
+def test_serving_full_size_sampled():
+    """The serving workload at full size: 10^5 resident streams, the bench's
+    server (8 GiB pool, 4 lanes, batches of up to 8192 entries, requests over
+    2^16 words split into jumped segments) and the first 1500 requests of the
+    seed-11 trace (N up to 2^24, all three dtypes), submitted at once so the
+    batches mix.  Every request's first 64 values, and for the 60 longest and
+    90 random others also 64 values in the middle and at the end (inside
+    jumped segments), equal the oracle's at the request's start position."""
+    trace = W.serving_trace(1500)
+    gs = XorgensStreams(W.SERVE_STREAMS, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 31, num_lanes=4, max_batch=8192, segment_words=1 << 16)
+    by_n = sorted(trace, key=lambda r: -r.n)
+    rng = np.random.default_rng(5)
+    deep = {r.rid for r in by_n[:60]} | {int(i) for i in rng.choice(len(trace), size=90, replace=False)}
+    for r in trace:
+        srv.submit(r.rid, r.stream, r.n, r.dtype)
+    got = {}
+    deadline = time.monotonic() + 120.0
+    while len(got) < len(trace) and time.monotonic() < deadline:
+        for c in srv.poll():
+            out = srv.output(c)
+            offs = [0]
+            if c.id in deep and c.n > 128:
+                offs += [(c.n // 2) & ~1, (c.n - 64) & ~1]
+            got[c.id] = (c, {t: out[t:t + 64].cpu().numpy().copy() for t in offs})
+            srv.release(c.id)
+    srv.close()
+    assert len(got) == len(trace)
+    P = O.charpoly(O.PAPER)
+    splits = 0
+    for c, slices in got.values():
+        for t, v in slices.items():
+            ref = _oracle_at(c.stream, c.start_pos + t, P)
+            L = v.size
+            if c.dtype == xg.XG_U32:
+                assert (v.view(np.uint32) == ref.u32(L)[0]).all(), (c.id, t)
+            elif c.dtype == xg.XG_F32:
+                assert (v == ref.f32(L)[0]).all(), (c.id, t)
+            else:
+                assert ulp32_error(v, ref.normal(L)[0]).max() <= 4.0, (c.id, t)
+            splits += t >= (1 << 16)
+    assert splits >= 100          # many checked slices lie beyond the first segment
