@@ -77,17 +77,32 @@ bool paper_member(const xg_ctx *ctx) { return ctx && ctx->family == XG_FAMILY_R1
 // this launch (the further members run two streams per wavefront).  The
 // 64-bit member takes one wavefront per block: measured ~10 % faster than four
 // for its bulk fill and equal for stream-major, where the 32-bit kernels want
-// four.  The automatic unroll is 8 except for Section 2's member's uint32
-// bulk fill, which takes 4: at 8 that kernel ran 700-770 us per 4 GiB on some
-// boxes against 600-630 us at 4 (interleaved A/B runs), while the FP32 fill
-// is 4-5 % faster at 8 everywhere.
-xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count, xg::Kind kind = xg::kU32, bool fill_layout = false) {
+// four.  The automatic unroll (interleaved A/B runs over several boxes,
+// 1024 streams x 2^20 words) is, for Section 2's member:
+//  - uint32 bulk fill: 4 (at 8 it ran 700-770 us per 4 GiB on some boxes,
+//    at 4 600-640 us everywhere);
+//  - FP32 bulk fill: 8 (4-5 % faster than 4);
+//  - uint32 / FP32 stream-major: 2 with 4-byte stores (FP32 710-735 us
+//    against 780-815 us for unroll 8 with 16-byte stores; uint32 with its
+//    stores paced, see the kernels, 717-736 us);
+//  - normals and moments: 8.
+// The further members keep 8.
+xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count, xg::Kind kind, bool fill_layout) {
   xg::Shape s = ctx->plain;
   const uint64_t waves = ctx->family == XG_FAMILY_R128_W32 ? count : (count + 1) / 2;
   if (s.waves_per_block == 0)
     s.waves_per_block = ctx->family == XG_FAMILY_R64_W64 ? 1u : xg::auto_waves_per_block(waves, ctx->num_cus);
-  if (s.unroll == 0)
-    s.unroll = fill_layout && kind == xg::kU32 && ctx->family == XG_FAMILY_R128_W32 ? 4u : 8u;
+  if (s.unroll == 0) {
+    s.unroll = 8;
+    if (ctx->family == XG_FAMILY_R128_W32 && (kind == xg::kU32 || kind == xg::kF32)) {
+      if (fill_layout) {
+        s.unroll = kind == xg::kU32 ? 4u : 8u;
+      } else {
+        s.unroll = 2;
+        s.store_words = 1;
+      }
+    }
+  }
   return s;
 }
 
@@ -99,7 +114,7 @@ xg_status family_words(xg_ctx *ctx, xg::Kind kind, bool fill_layout, uint64_t fi
   if (ctx->family != (w64 ? XG_FAMILY_R64_W64 : XG_FAMILY_R64_W32)) return XG_ENOTSUP;
   xg_status st = check_range(ctx, first, count, n, out, n, w64 ? 8 : 4);
   if (st != XG_OK || n == 0) return st;
-  const hipError_t e = xg::launch_family_generate(ctx->family, kind, fill_layout, plain_shape(ctx, count),
+  const hipError_t e = xg::launch_family_generate(ctx->family, kind, fill_layout, plain_shape(ctx, count, kind, fill_layout),
                                                   reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
                                                   n, out, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? XG_OK : XG_EHIP;
@@ -112,7 +127,7 @@ xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint
     // normals and their fused moments (kNormal, kMoments)
     xg_status st = check_range(ctx, first, count, n, out, kind == xg::kMoments ? 2 : n);
     if (st != XG_OK || n == 0) return st;
-    const hipError_t e = xg::launch_family_generate(ctx->family, kind, false, plain_shape(ctx, count),
+    const hipError_t e = xg::launch_family_generate(ctx->family, kind, false, plain_shape(ctx, count, kind, false),
                                                     reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
                                                     n, out, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? XG_OK : XG_EHIP;
@@ -121,7 +136,7 @@ xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint
   const uint64_t per_stream = kind == xg::kMoments ? 2 : n;
   xg_status st = check_range(ctx, first, count, n, out, per_stream);
   if (st != XG_OK || n == 0) return st;
-  const hipError_t e = xg::launch_generate(kind, plain_shape(ctx, count), ctx->d_state, first, count,
+  const hipError_t e = xg::launch_generate(kind, plain_shape(ctx, count, kind, false), ctx->d_state, first, count,
                                            n, out, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }

@@ -128,9 +128,18 @@ __device__ __forceinline__ uint32_t map_word(uint32_t o) {
   }
 }
 
-template <uint32_t KIND>
+// PACED: the store is followed by an issue gap of three wait states
+// (s_nop 2).  Used only by the uint32 stream-major launch at unroll 2 with
+// 4-byte stores: there, with one wavefront per SIMD and 1024 fronts 4 MB
+// apart, spacing each wavefront's 256-byte stores this way took a 4 GiB
+// launch from 790-815 us to 717-736 us on three boxes (interleaved A/B), as
+// fast as the FP32 launch, whose three extra ALU operations per chunk space
+// its stores anyway.  Longer gaps, other unrolls and the other layouts
+// measured slower with it, so nothing else is paced.
+template <uint32_t KIND, bool PACED = false>
 __device__ __forceinline__ void emit_word(uint32_t *p, uint32_t o) {
   __builtin_nontemporal_store(map_word<KIND>(o), p);
+  if constexpr (PACED) asm volatile("s_nop 2");
 }
 
 // Dynamic LDS: one 256-word staging slot per wavefront of the block (wide stores).
@@ -227,7 +236,7 @@ __device__ __forceinline__ void close_stream(uint32_t *dst, WordStream &s, uint6
 // the wavefront's LDS slot and leave as one 16-byte store per lane (1 KB per
 // store instruction instead of 256 B); the rest uses one 4-byte store per lane.
 // ---------------------------------------------------------------------------
-template <uint32_t KIND, int UNROLL, bool WIDE>
+template <uint32_t KIND, int UNROLL, bool WIDE, bool PACED = false>
 __device__ __forceinline__ void serve_words_from(const StreamState &s0, uint64_t n, uint32_t *__restrict__ out,
                                                  uint32_t *dst) {
   WordStream s = open_from(s0);
@@ -261,20 +270,20 @@ __device__ __forceinline__ void serve_words_from(const StreamState &s0, uint64_t
   const uint64_t nouter = nrest / UNROLL;
   for (uint64_t it = 0; it != nouter; ++it) {
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) emit_word<KIND>(o + u * 64, next_chunk(s));
+    for (int u = 0; u < UNROLL; ++u) emit_word<KIND, PACED>(o + u * 64, next_chunk(s));
     o += UNROLL * 64;
   }
   const uint32_t nleft = (uint32_t)(nrest % UNROLL);
   for (uint32_t c = 0; c != nleft; ++c) {
-    emit_word<KIND>(o, next_chunk(s));
+    emit_word<KIND, PACED>(o, next_chunk(s));
     o += 64;
   }
   close_stream<KIND>(dst, s, n, rem, o);
 }
 
-template <uint32_t KIND, int UNROLL, bool WIDE>
+template <uint32_t KIND, int UNROLL, bool WIDE, bool PACED = false>
 __device__ __forceinline__ void serve_words(uint32_t *st, uint64_t n, uint32_t *__restrict__ out) {
-  serve_words_from<KIND, UNROLL, WIDE>(load_state(st), n, out, st);
+  serve_words_from<KIND, UNROLL, WIDE, PACED>(load_state(st), n, out, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +497,8 @@ __global__ __launch_bounds__(1024) void k_generate(uint32_t *__restrict__ state,
   if (wid >= count) return;
   uint32_t *st = state + (first + wid) * kStateWords;
   if constexpr (KIND == kU32 || KIND == kF32) {
-    serve_words<KIND, UNROLL, WIDE>(st, n, reinterpret_cast<uint32_t *>(out) + wid * n);
+    constexpr bool kPaced = KIND == kU32 && UNROLL == 2 && !WIDE;  // see emit_word
+    serve_words<KIND, UNROLL, WIDE, kPaced>(st, n, reinterpret_cast<uint32_t *>(out) + wid * n);
   } else if constexpr (KIND == kNormal) {
     serve_normals<false, UNROLL>(st, n, reinterpret_cast<float *>(out) + wid * n, nullptr);
   } else {
