@@ -124,6 +124,8 @@ def lib() -> ctypes.CDLL:
                                         ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int]
         L.xgo64_xpart_run.argtypes = [P64, u64p, ctypes.c_uint64, ctypes.c_uint32, u8p]
         L.xgo64_xpart_jump_poly.argtypes = [P64, u64p, u64p]
+        L.xgo64_box_muller.argtypes = [ctypes.c_uint64, ctypes.c_uint64, P(ctypes.c_double), P(ctypes.c_double)]
+        L.xgo64_box_muller.restype = None
         L.gf2_clmul64.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p, u64p]
         L.gf2_clmul64_portable.argtypes = [ctypes.c_uint64, ctypes.c_uint64, u64p, u64p]
         L.gf2_degree.argtypes = [u64p, ctypes.c_int]
@@ -272,6 +274,13 @@ class OracleStreams64:
         self._run(1, n, out, threads)
         return out
 
+    def normal(self, n: int, threads: int | None = None) -> np.ndarray:
+        """n FP64 Box-Muller normals per stream (long double, rounded once);
+        consumes 2 ceil(n / 2) words."""
+        out = np.empty((self.count, n), dtype=np.float64)
+        self._run(2, n, out, threads)
+        return out
+
     def skip(self, n: int, threads: int | None = None) -> None:
         self._run(SKIP, n, None, threads)
 
@@ -279,6 +288,13 @@ class OracleStreams64:
 def splitmix64_sequence(seed: int, k: int) -> list[int]:
     z = ctypes.c_uint64(seed & (2**64 - 1))
     return [int(lib().xgo_splitmix64(ctypes.byref(z))) for _ in range(k)]
+
+
+def box_muller_w64(o_even: int, o_odd: int) -> tuple[float, float]:
+    """The 64-bit member's pair map: 53-bit uniforms, long double, rounded once."""
+    z0, z1 = ctypes.c_double(), ctypes.c_double()
+    lib().xgo64_box_muller(o_even & (2**64 - 1), o_odd & (2**64 - 1), ctypes.byref(z0), ctypes.byref(z1))
+    return z0.value, z1.value
 
 
 def box_muller64(o_even: int, o_odd: int) -> tuple[float, float]:

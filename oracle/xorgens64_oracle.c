@@ -24,7 +24,14 @@
  * (all 64 bits of each: r ring words x_{-r} .. x_{-1}, then the Weyl start),
  * sets x_{-1} = 1 if the ring is all zero, and discards 4r steps.
  * f64 uniform: (out >> 11) * 2^-53, exact, in [0, 1 - 2^-53].
+ * f64 normal (the paper has none; the 32-bit member's Box-Muller pairing with
+ * 53-bit uniforms): for the pair (o_{2m}, o_{2m+1}) of a call's outputs,
+ *   u1 = ((o_{2m} >> 11) + 1) 2^-53 in (0, 1],  u2 = (o_{2m+1} >> 11) 2^-53,
+ *   rho = sqrt(-2 ln u1),  z_{2m} = rho cos(2 pi u2),  z_{2m+1} = rho sin(2 pi u2),
+ * evaluated in long double (64-bit significand) with the dyadic angle reduced
+ * exactly, and rounded once to double: a reference for FP64 results.
  */
+#include <math.h>
 #include <pthread.h>
 #include <stdint.h>
 #include <string.h>
@@ -122,8 +129,37 @@ static void save_state(const xgo64_params *p, const xgo64_state *st, uint64_t *r
     *pos = st->pos;
 }
 
-enum { XGO64_U64 = 0, XGO64_F64 = 1, XGO64_SKIP = 4 };
+static const long double PI_L = 3.14159265358979323846264338327950288L;
 
+/* Box-Muller on one pair of 64-bit outputs (see the header).  4 u2 is a
+   multiple of 2^-51 below 4; it splits exactly into q + 2f with q the nearest
+   integer and |f| <= 1/4, and the pair (cos, sin) of 2 pi u2 is that of pi f
+   turned by q quarter turns. */
+void xgo64_box_muller(uint64_t o_even, uint64_t o_odd, double *z0, double *z1)
+{
+    long double u1 = ldexpl((long double)((o_even >> 11) + 1u), -53);
+    long double u2 = ldexpl((long double)(o_odd >> 11), -53);
+    long double rho = sqrtl(-2.0L * logl(u1));
+    long double y = 4.0L * u2;                 /* exact */
+    long double q = nearbyintl(y);             /* exact integer 0 .. 4 */
+    long double f = 0.5L * (y - q);            /* exact */
+    long double sf = sinl(PI_L * f), cf = cosl(PI_L * f), s, c;
+    int qi = (int)q % 4;
+    if (f == 0.0L) { sf = 0.0L; cf = 1.0L; }
+    switch (qi) {
+    case 0: s = sf;  c = cf;  break;
+    case 1: s = cf;  c = -sf; break;
+    case 2: s = -sf; c = -cf; break;
+    default: s = -cf; c = sf; break;
+    }
+    *z0 = (double)(rho * c);
+    *z1 = (double)(rho * s);
+}
+
+enum { XGO64_U64 = 0, XGO64_F64 = 1, XGO64_NORMAL = 2, XGO64_SKIP = 4 };
+
+/* A normal request of n variates consumes 2 ceil(n / 2) words (odd n drops
+   the last sine value). */
 static void run_one(const xgo64_params *p, xgo64_state *st, int kind, uint64_t n, void *out)
 {
     uint64_t t;
@@ -133,6 +169,16 @@ static void run_one(const xgo64_params *p, xgo64_state *st, int kind, uint64_t n
     } else if (kind == XGO64_F64) {
         double *o = (double *)out;
         for (t = 0; t < n; t++) o[t] = (double)(step_out(p, st) >> 11) * 0x1p-53;
+    } else if (kind == XGO64_NORMAL) {
+        double *o = (double *)out;
+        for (t = 0; t < n; t += 2) {
+            uint64_t e = step_out(p, st);
+            uint64_t d = step_out(p, st);
+            double z0, z1;
+            xgo64_box_muller(e, d, &z0, &z1);
+            o[t] = z0;
+            if (t + 1 < n) o[t + 1] = z1;
+        }
     } else {
         for (t = 0; t < n; t++) (void)step_out(p, st);
     }
@@ -176,8 +222,9 @@ int xgo64_seed_streams(const xgo64_params *p, uint64_t seed, uint64_t first, uin
     return 0;
 }
 
-/* Advances every stream by n words of `kind` (U64: uint64_t out, F64: double
-   out, SKIP: none), stream i's values at out + i * out_stride_bytes, on up
+/* Advances every stream by n values of `kind` (U64: uint64_t out, F64: double
+   out, NORMAL: double out, 2 ceil(n / 2) words; SKIP: none), stream i's
+   values at out + i * out_stride_bytes, on up
    to `threads` POSIX threads over disjoint streams. */
 int xgo64_run_streams(const xgo64_params *p, uint64_t *ring, uint64_t *weyl, uint64_t *pos,
                       uint64_t count, int kind, uint64_t n, void *out, uint64_t out_stride_bytes,
@@ -187,7 +234,7 @@ int xgo64_run_streams(const xgo64_params *p, uint64_t *ring, uint64_t *weyl, uin
     job64_t jobs[256];
     int t, nt;
     if (!xgo64_params_valid(p)) return -1;
-    if (kind != XGO64_U64 && kind != XGO64_F64 && kind != XGO64_SKIP) return -1;
+    if (kind != XGO64_U64 && kind != XGO64_F64 && kind != XGO64_NORMAL && kind != XGO64_SKIP) return -1;
     if (kind != XGO64_SKIP && out == NULL && count > 0) return -1;
     nt = threads < 1 ? 1 : (threads > 256 ? 256 : threads);
     if ((uint64_t)nt > count) nt = count ? (int)count : 1;

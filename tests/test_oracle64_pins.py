@@ -191,3 +191,66 @@ def test_w64_split_call_and_threads():
     whole = a.u64(1001, threads=1)
     parts = np.concatenate([b.u64(500, threads=3), b.u64(1, threads=2), b.u64(500, threads=5)], axis=1)
     assert (whole == parts).all() and (a.ring == b.ring).all() and (a.weyl == b.weyl).all()
+
+
+# ---- FP64 normals of the 64-bit member (the 32-bit member's Box-Muller
+# pairing with 53-bit uniforms, evaluated in long double) ----
+
+def _u1(e):
+    return ((e >> 11) + 1) * 2.0**-53
+
+
+def test_w64_box_muller_special_values():
+    """u1 = 1 gives two zeros; u2 = 0, 1/4, 1/2, 3/4 put the whole radius on
+    one axis with the right sign and an exact zero on the other; the radius
+    is sqrt(-2 ln u1) (to double rounding)."""
+    top = (2**53 - 1) << 11                       # (e >> 11) + 1 = 2^53: u1 = 1
+    assert O.box_muller_w64(top, 12345 << 11) == (0.0, 0.0)
+    for e in (0, 1 << 11, 0x0123456789ABCDEF, (2**52) << 11, M64):
+        rho = math.sqrt(-2.0 * math.log(_u1(e)))
+        for k, (c, s) in enumerate([(1, 0), (0, 1), (-1, 0), (0, -1)]):
+            o = (k << 62) | 0x7FF                  # u2 = k / 4 (low 11 bits ignored)
+            z0, z1 = O.box_muller_w64(e, o)
+            for z, axis in ((z0, c), (z1, s)):
+                if axis == 0:
+                    assert z == 0.0, (e, k)
+                else:
+                    assert abs(z - axis * rho) <= 2e-16 * rho, (e, k)
+
+
+def test_w64_box_muller_invariants():
+    """For random pairs: z0^2 + z1^2 = -2 ln u1 and atan2(z1, z0) = 2 pi u2
+    (mod 2 pi), so a dropped factor, a swapped or mis-signed branch, or a
+    wrong shift of either word shows."""
+    rng = np.random.default_rng(64)
+    for e, o in rng.integers(0, 2**63, size=(400, 2), dtype=np.int64).tolist():
+        e, o = (e << 1) | (e & 1), (o << 1) | 1
+        z0, z1 = O.box_muller_w64(e, o)
+        r2 = -2.0 * math.log(_u1(e))
+        assert abs(z0 * z0 + z1 * z1 - r2) <= 1e-14 * max(r2, 1e-300) + 1e-300, (e, o)
+        u2 = (o >> 11) * 2.0**-53
+        d = (math.atan2(z1, z0) - 2 * math.pi * u2) % (2 * math.pi)
+        assert min(d, 2 * math.pi - d) <= 1e-12, (e, o)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 64, 129])
+def test_w64_normals_pair_consecutive_words(n):
+    """The stream method pairs consecutive outputs of the call and consumes
+    2 ceil(n / 2) words: it equals the pair map on a copy's u64 outputs, and
+    both copies end at the same state."""
+    a = O.OracleStreams64(9, 3, W64)
+    b = a.copy()
+    z = a.normal(n)
+    w = b.u64(2 * ((n + 1) // 2))
+    for i in range(3):
+        want = [v for m in range(0, n, 2) for v in O.box_muller_w64(int(w[i, m]), int(w[i, m + 1]))][:n]
+        assert np.array_equal(z[i], np.array(want)), i
+    assert (a.ring == b.ring).all() and (a.weyl == b.weyl).all() and (a.pos == b.pos).all()
+
+
+def test_w64_normals_moments():
+    z = O.OracleStreams64(42, 8, W64).normal(1 << 15).ravel()
+    n = z.size
+    assert abs(z.mean()) < 5 / math.sqrt(n)
+    assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / n)
+    assert abs((z**4).mean() - 3.0) < 5 * math.sqrt(96.0 / n)
