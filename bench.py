@@ -294,6 +294,23 @@ def extra_family_members(torch, dev):
     ms = a.elapsed_time(e) / 20
     res["r64_w32 (n=2048) fused moments 4096 x 2^18"] = {"kernel_ms": ms, "rn_per_s": S * n / (ms * 1e-3)}
     del gs, sums
+    # the 64-bit member's FP64 normals: 2048 streams x 2^18 doubles (4 GiB)
+    S, n = 2048, 1 << 18
+    gs = XorgensStreams(S, seed=SEED, device=dev, family=xg.XG_FAMILY_R64_W64)
+    z = torch.empty((S, n), dtype=torch.float64, device=dev)
+    for _ in range(10):
+        gs.normal_f64(n, out=z)
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(20):
+        gs.normal_f64(n, out=z)
+    e.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / 20
+    res["r64_w64 (n=4096) FP64 normals 2048 x 2^18"] = {"kernel_ms": ms, "rn_per_s": S * n / (ms * 1e-3),
+                                                        "GBs": 8 * S * n / (ms * 1e-3) / 1e9}
+    del gs, z
     return res
 
 

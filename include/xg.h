@@ -80,7 +80,8 @@ typedef int32_t xg_status;
  *                       state.  Plain and bulk-fill u32 / f32, normals and
  *                       fused moments (as for Section 2's member), and xg_skip.
  *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
- *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), and xg_skip.
+ *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), FP64
+ *                       normals (xg_generate_normal_f64), and xg_skip.
  * The paper gives shifts only for the first; those of the other two were
  * chosen by a search for primitive characteristic polynomials.  Calls a
  * member does not support return XG_ENOTSUP. */
@@ -219,6 +220,18 @@ xg_status xg_fill_u64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                       uint64_t *d_out, void *stream);
 xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                       double *d_out, void *stream);
+
+/* FP64 standard normals of XG_FAMILY_R64_W64 (the paper has no 64-bit
+ * member; this is xg_generate_normal's pairing with 53-bit uniforms): for
+ * consecutive outputs (o_{2m}, o_{2m+1}) of the call, u1 = ((o_{2m} >> 11)
+ * + 1) 2^-53 in (0, 1], u2 = (o_{2m+1} >> 11) 2^-53, rho = sqrt(-2 ln u1),
+ * z_{2m} = rho cos(2 pi u2), z_{2m+1} = rho sin(2 pi u2), in FP64 with the
+ * angle reduced exactly.  Stream-major d_out[(i - first) n + t] (8-byte
+ * aligned; pairs go out as 16-byte stores when it is 16-byte aligned and n
+ * even).  Consumes 2 ceil(n / 2) words (odd n drops the last sine value).
+ * Other families: XG_ENOTSUP.  Otherwise the errors of xg_generate_u64. */
+xg_status xg_generate_normal_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                                 double *d_out, void *stream);
 
 /* Standard normals by the Box-Muller transform on consecutive pairs of
  * outputs (o_{2m}, o_{2m+1}) of the call: u1 = ((o_{2m} >> 8) + 1) 2^-24 in

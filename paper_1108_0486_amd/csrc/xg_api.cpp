@@ -290,6 +290,19 @@ xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, d
   return family_words(ctx, xg::kF64, true, first, count, n, d_out, stream);
 }
 
+xg_status xg_generate_normal_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, double *d_out,
+                                 void *stream) {
+  if (!ctx) return XG_EINVAL;
+  if (ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
+  const xg_status st = check_range(ctx, first, count, n, d_out, n, 8);
+  if (st != XG_OK || n == 0) return st;
+  const hipError_t e = xg::launch_family_generate(ctx->family, xg::kNormal, false,
+                                                  plain_shape(ctx, count, xg::kNormal, false),
+                                                  reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
+                                                  n, d_out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
 xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream) {
   if (!ctx || count == 0) return XG_EINVAL;
   if (first > ctx->num_streams || count > ctx->num_streams - first) return XG_ERANGE;

@@ -23,6 +23,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "xg_device.h"
 #include "xg_normal.h"
 #include "xg_internal.h"
@@ -249,21 +251,39 @@ __device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, con
 }
 
 // ---------------------------------------------------------------------------
-// normals of the 32-bit member: Box-Muller on consecutive pairs (o_{2m},
-// o_{2m+1}) of each stream's outputs of the call, as for Section 2's member.
-// Two steps give 64 words of each stream, i.e. 32 pairs: lane 2m + h takes
-// pair m of stream h, whose words sit on lanes (4m + h) mod 64 and
-// (4m + 2 + h) mod 64 of the first step (m < 16) or of the second.  MOMENTS:
+// normals: Box-Muller on consecutive pairs (o_{2m}, o_{2m+1}) of each
+// stream's outputs of the call, as for Section 2's member; FP32 from the
+// 32-bit member, FP64 (53-bit uniforms) from the 64-bit member.  Two steps
+// give 64 words of each stream, i.e. 32 pairs: lane 2m + h takes pair m of
+// stream h, whose words sit on lanes (4m + h) mod 64 and (4m + 2 + h) mod 64
+// of the first step (m < 16) or of the second.  MOMENTS (32-bit member):
 // per-lane compensated sums of z and z^2, reduced over the lanes of each
 // stream (their lane parity), instead of storing the variates.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void fam_gather_pair(uint32_t a, uint32_t b, uint32_t m, uint32_t h, uint32_t &e,
-                                                uint32_t &o) {
+template <typename word>
+__device__ __forceinline__ void fam_gather_pair(word a, word b, uint32_t m, uint32_t h, word &e, word &o) {
   const int se = (int)((4u * m + h) & 63u), so = (int)((4u * m + 2u + h) & 63u);
-  const uint32_t ea = shfl_word(a, se), eb = shfl_word(b, se), oa = shfl_word(a, so), ob = shfl_word(b, so);
+  const word ea = shfl_word(a, se), eb = shfl_word(b, se), oa = shfl_word(a, so), ob = shfl_word(b, so);
   const bool upper = m >= 16u;
   e = upper ? eb : ea;
   o = upper ? ob : oa;
+}
+
+// Stores FP64 normals idx and idx + 1 of the call (those below n); a pair is
+// one 16-byte store when `pair_aligned` (wave-uniform).
+__device__ __forceinline__ void fam_consume_pair_f64(uint64_t e, uint64_t o, uint64_t idx, uint64_t n, bool on,
+                                                     double *__restrict__ out, bool pair_aligned) {
+  double z0, z1;
+  dev::box_muller_f64(e, o, z0, z1);
+  const bool has0 = on && idx < n, has1 = on && idx + 1 < n;
+  if (pair_aligned && has1) {
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const f64x2 pair = {z0, z1};
+    __builtin_nontemporal_store(pair, reinterpret_cast<f64x2 *>(out + idx));
+  } else {
+    if (has0) __builtin_nontemporal_store(z0, out + idx);
+    if (has1) __builtin_nontemporal_store(z1, out + idx + 1);
+  }
 }
 
 template <bool MOMENTS>
@@ -292,55 +312,65 @@ __device__ __forceinline__ void fam_consume_pair(uint32_t e, uint32_t o, uint64_
 // n normals of each of `count` streams (launch index k = stream first + k)
 // at out[k n + t], or their sums at sums[2k], sums[2k + 1].  Consumes
 // 2 ceil(n / 2) words per stream.
-template <bool MOMENTS>
+template <class M, bool MOMENTS>
 __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict__ state, uint64_t first,
-                                                      uint64_t count, uint64_t n, float *__restrict__ out,
+                                                      uint64_t count, uint64_t n, void *__restrict__ out_v,
                                                       float *__restrict__ sums) {
-  using M = MemberN2048;
+  using word = typename M::word;
+  constexpr bool kW64 = sizeof(word) == 8;
+  static_assert(!(kW64 && MOMENTS), "fused moments exist for the 32-bit member only");
+  using real = typename std::conditional<kW64, double, float>::type;
+  real *out = static_cast<real *>(out_v);
   const Lanes L = lanes_of(count, xcd_block());
   if (2 * (L.k >> 1) >= count) return;  // wave-uniform
   const bool on = L.active;
   unsigned char *st = state + (first + L.k) * M::state_bytes;
-  uint32_t prev = 0, cur = 0, w_start = 0;
+  word prev = 0, cur = 0, w_start = 0;
   uint64_t pos = 0;
   if (on) {
-    const uint32_t *ring = reinterpret_cast<const uint32_t *>(st);
+    const word *ring = reinterpret_cast<const word *>(st);
     prev = ring[L.j];
     cur = ring[32 + L.j];
-    w_start = *reinterpret_cast<const uint32_t *>(st + M::weyl_off);
+    w_start = *reinterpret_cast<const word *>(st + M::weyl_off);
     pos = *reinterpret_cast<const uint64_t *>(st + M::pos_off);
   }
   Ring2<M> g;
   g.open(prev, cur);
   const bool word0 = L.j == 0;
-  const uint32_t wlane = (L.j + 1u) * M::omega;
-  uint32_t wbase = w_start;
+  const word wlane = word(L.j + 1u) * M::omega;
+  word wbase = w_start;
   auto next = [&]() {
-    const uint32_t x = g.step(word0);
-    const uint32_t w = wbase + wlane;
-    wbase += kStep * M::omega;
-    return x + (w ^ (w >> M::gamma));
+    const word x = g.step(word0);
+    const word w = wbase + wlane;
+    wbase += word(kStep) * M::omega;
+    return word(x + (w ^ (w >> M::gamma)));
   };
   const uint64_t words = n + (n & 1u);
   const uint64_t nblk = words >> 6;  // 64-word blocks: 32 pairs of each stream
   const uint32_t rw = (uint32_t)(words & 63u);
   const uint32_t m = L.j;
-  float *o_s = MOMENTS ? nullptr : out + L.k * n;
-  const bool pair_aligned = !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
+  real *o_s = MOMENTS ? nullptr : out + L.k * n;
+  const bool pair_aligned =
+      !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(out) & (2 * sizeof(real) - 1)) == 0;
   dev::Moments mo{0.0f, 0.0f, 0.0f, 0.0f, -0.0f, -0.0f};
+  auto consume = [&](word e, word o, uint64_t idx) {
+    if constexpr (kW64) fam_consume_pair_f64(e, o, idx, n, on, o_s, pair_aligned);
+    else fam_consume_pair<MOMENTS>(e, o, idx, n, on, o_s, pair_aligned, mo);
+  };
   for (uint64_t b = 0; b != nblk; ++b) {
-    const uint32_t oa = next();
-    const uint32_t ob = next();
-    uint32_t e, o;
+    const word oa = next();
+    const word ob = next();
+    word e, o;
     fam_gather_pair(oa, ob, m, L.h, e, o);
-    fam_consume_pair<MOMENTS>(e, o, (b << 6) + 2u * m, n, on, o_s, pair_aligned, mo);
+    consume(e, o, (b << 6) + 2u * m);
   }
   // Tail: rw (even, < 64) more words.
-  uint32_t p0 = g.prev, c0 = g.cur, xl = 0u, rem = 0u;
+  word p0 = g.prev, c0 = g.cur, xl = 0;
+  uint32_t rem = 0u;
   if (rw) {  // wave-uniform
-    uint32_t oa, ob = 0u;
+    word oa, ob = 0;
     if (rw <= 32u) {
-      const uint32_t w = wbase + wlane;
+      const word w = wbase + wlane;
       xl = g.step(word0);
       oa = xl + (w ^ (w >> M::gamma));
       rem = rw & 31u;  // rw == 32 completes the step
@@ -352,16 +382,16 @@ __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict_
       oa = next();
       p0 = g.prev;
       c0 = g.cur;
-      const uint32_t w = wbase + wlane;
+      const word w = wbase + wlane;
       xl = g.step(word0);
       ob = xl + (w ^ (w >> M::gamma));
       rem = rw - 32u;
     }
-    uint32_t e, o;
+    word e, o;
     fam_gather_pair(oa, ob, m, L.h, e, o);
-    if (2u * m < rw) fam_consume_pair<MOMENTS>(e, o, (nblk << 6) + 2u * m, n, on, o_s, pair_aligned, mo);
+    if (2u * m < rw) consume(e, o, (nblk << 6) + 2u * m);
   }
-  store_state<M>(st, L, p0, c0, xl, rem, w_start + (uint32_t)words * M::omega, pos + words);
+  store_state<M>(st, L, p0, c0, xl, rem, w_start + (word)words * M::omega, pos + words);
   if constexpr (MOMENTS) {
     float v1 = mo.s1 - mo.c1, v2 = mo.s2 - mo.c2;
 #pragma unroll
@@ -537,9 +567,16 @@ hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const S
   if (family == XG_FAMILY_R64_W32 && (kind == kNormal || kind == kMoments)) {
     float *o = static_cast<float *>(out);
     if (kind == kNormal)
-      hipLaunchKernelGGL((k_fam_normals<false>), grid, block, 0, stream, state, first, count, n, o, nullptr);
+      hipLaunchKernelGGL((k_fam_normals<MemberN2048, false>), grid, block, 0, stream, state, first, count, n, out,
+                         nullptr);
     else
-      hipLaunchKernelGGL((k_fam_normals<true>), grid, block, 0, stream, state, first, count, n, nullptr, o);
+      hipLaunchKernelGGL((k_fam_normals<MemberN2048, true>), grid, block, 0, stream, state, first, count, n, nullptr,
+                         o);
+    return hipGetLastError();
+  }
+  if (family == XG_FAMILY_R64_W64 && kind == kNormal) {
+    hipLaunchKernelGGL((k_fam_normals<MemberW64, false>), grid, block, 0, stream, state, first, count, n, out,
+                       nullptr);
     return hipGetLastError();
   }
   if (family == XG_FAMILY_R64_W32 && kind == kU32)

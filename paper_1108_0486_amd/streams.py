@@ -132,6 +132,14 @@ class XorgensStreams:
         xg.xg_fill_f64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
         return out
 
+    def normal_f64(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                   stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """FP64 Box-Muller normals (64-bit member only); consumes 2 ceil(n / 2) words."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count, n), torch.float64)
+        xg.xg_generate_normal_f64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
     def normal(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
                stream: torch.cuda.Stream | None = None) -> torch.Tensor:
         first, count = self._range(first, count)

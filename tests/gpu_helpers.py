@@ -25,3 +25,18 @@ def ulp32_error(z32: np.ndarray, z64: np.ndarray) -> np.ndarray:
     zero = a == 0
     err[zero] = np.where(z32[zero] == 0, 0.0, np.inf)
     return err
+
+
+def ulp64_error(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
+    """|got - ref| in units of the FP64 ulp of ref: 2^(max(e, -1022) - 52) with
+    e = floor(log2 |ref|); where ref == 0 exactly the error is 0 if got == 0
+    and infinite otherwise."""
+    got = np.asarray(got, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    a = np.abs(ref)
+    _, e2 = np.frexp(np.where(a > 0, a, 1.0))
+    e = np.maximum(e2 - 1, -1022)
+    err = np.abs(got - ref) / np.exp2(e - 52.0)
+    zero = a == 0
+    err[zero] = np.where(got[zero] == 0, 0.0, np.inf)
+    return err

@@ -9,7 +9,7 @@ the oracle, and so is the state left behind.
 import numpy as np
 import pytest
 
-from gpu_helpers import needs_gpu, ulp32_error
+from gpu_helpers import needs_gpu, ulp32_error, ulp64_error
 from oracle import oracle as O
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -146,7 +146,8 @@ def test_family_unsupported_calls_are_rejected(fam):
         calls = [lambda: xg.xg_generate_normal(gs.ctx, 0, 4, 8, p), lambda: xg.xg_normal_moments(gs.ctx, 0, 4, 8, p),
                  lambda: xg.xg_generate_u32(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f32(gs.ctx, 0, 4, 8, p)]
     else:
-        calls = [lambda: xg.xg_generate_u64(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f64(gs.ctx, 0, 4, 8, p)]
+        calls = [lambda: xg.xg_generate_u64(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f64(gs.ctx, 0, 4, 8, p),
+                 lambda: xg.xg_generate_normal_f64(gs.ctx, 0, 4, 8, p)]
     for c in calls:
         with pytest.raises(xg.XgError) as e:
             c()
@@ -160,9 +161,10 @@ def test_family_unsupported_calls_are_rejected(fam):
         Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4)
     assert e.value.status == xg.XG_ENOTSUP
     paper = XorgensStreams(4, seed=1)
-    with pytest.raises(xg.XgError) as e:
-        xg.xg_generate_u64(paper.ctx, 0, 4, 8, p)
-    assert e.value.status == xg.XG_ENOTSUP
+    for c in (xg.xg_generate_u64, xg.xg_generate_normal_f64):
+        with pytest.raises(xg.XgError) as e:
+            c(paper.ctx, 0, 4, 8, p)
+        assert e.value.status == xg.XG_ENOTSUP
     torch.cuda.synchronize()
     _assert_state(gs, _oracle(fam, 1, 4))                      # nothing ran
 
@@ -261,3 +263,46 @@ def test_r64w32_moments_within_bound(n):
     assert (np.abs(m[:, 1] - mr[:, 1]) <= tau * mr[:, 1]).all()
     torch.cuda.synchronize()
     _assert_state(gs, ref)
+
+
+@pytest.mark.parametrize("n", [1, 2, 31, 32, 33, 63, 64, 65, 127, 128, 1000, 4133])
+def test_w64_normals_f64_match_oracle(n):
+    """FP64 Box-Muller normals of the 64-bit member (53-bit uniforms):
+    within 4 FP64 ulp of the oracle's long-double values rounded to double;
+    odd n consumes 2 ceil(n / 2) words.  Streams 3 .. 35 of 37 (the last
+    wavefront holds one stream)."""
+    gs = XorgensStreams(37, seed=13, family=R64W64)
+    ref = _sub(_oracle(R64W64, 13, 37), 3, 36)
+    z = gs.normal_f64(n, first=3, count=33).cpu().numpy()
+    zr = ref.normal(n)
+    err = ulp64_error(z, zr)
+    assert err.max() <= 4.0, err.max()
+    torch.cuda.synchronize()
+    _assert_state(gs, ref, idx=list(range(3, 36)))
+    assert (_bits(gs.u64(100, first=3, count=33)) == ref.u64(100)).all()
+
+
+@pytest.mark.parametrize("misalign", [False, True])
+def test_w64_normals_f64_output_alignment(misalign):
+    """Pairs go out as 16-byte stores only from a 16-byte-aligned buffer; an
+    8-byte-aligned one takes single stores with the same values."""
+    count, n = 5, 258
+    gs = XorgensStreams(count, seed=2, family=R64W64)
+    buf = torch.full((count * n + 1,), -7.0, dtype=torch.float64, device="cuda")
+    out = (buf[1:] if misalign else buf[:-1]).view(count, n)
+    gs.normal_f64(n, out=out)
+    zr = _oracle(R64W64, 2, count).normal(n)
+    assert ulp64_error(out.cpu().numpy(), zr).max() <= 4.0
+    assert buf[0 if misalign else -1].item() == -7.0
+
+
+def test_w64_normals_f64_large_sample():
+    """2048 streams x 2^13 normals (the launch shape of a full wave of pairs
+    per SIMD): every value within 4 FP64 ulp; the worst is printed."""
+    count, n = 2048, 1 << 13
+    gs = XorgensStreams(count, seed=42, family=R64W64)
+    z = gs.normal_f64(n).cpu().numpy()
+    zr = _oracle(R64W64, 42, count).normal(n)
+    err = ulp64_error(z, zr)
+    print("FP64 normals: max error %.3f ulp over %d values" % (err.max(), err.size))
+    assert err.max() <= 4.0
