@@ -260,6 +260,27 @@ __device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, con
 // per-lane compensated sums of z and z^2, reduced over the lanes of each
 // stream (their lane parity), instead of storing the variates.
 // ---------------------------------------------------------------------------
+// FP64 normals of the 64-bit member: u1 = ((e >> 11) + 1) 2^-53 in (0, 1]
+// and u2 = (o >> 11) 2^-53 in [0, 1), both exact; z0 = rho cos(2 pi u2),
+// z1 = rho sin(2 pi u2), rho = sqrt(-2 ln u1).  The angle is reduced exactly
+// on the word as in dev::sincos_turn: adding 2^61 to o leaves the quadrant in bits
+// 63:62 and (o's low 11 bits cleared) 2^61 + f 2^63 in bits 61:0, |f| <= 1/4.
+// sin(pi f), cos(pi f), ln and the square root are the device library's FP64
+// functions.
+__device__ __forceinline__ void box_muller_f64(uint64_t e, uint64_t o, double &z0, double &z1) {
+  const double u1 = fma((double)(e >> 11), 0x1p-53, 0x1p-53);  // exact
+  const double rho = sqrt(-2.0 * log(u1));
+  const uint64_t qf = o + (1ull << 61);
+  const double f = fma((double)(qf & 0x3FFFFFFFFFFFF800ull), 0x1p-63, -0.25);  // exact
+  double sp, cp;
+  sincospi(f, &sp, &cp);
+  const bool odd = ((qf >> 62) & 1u) != 0u;
+  const double s0 = odd ? cp : sp, c0 = odd ? sp : cp;
+  const uint64_t sign_s = qf & 0x8000000000000000ull, sign_c = (qf + (1ull << 62)) & 0x8000000000000000ull;
+  z0 = rho * __longlong_as_double((long long)((uint64_t)__double_as_longlong(c0) ^ sign_c));
+  z1 = rho * __longlong_as_double((long long)((uint64_t)__double_as_longlong(s0) ^ sign_s));
+}
+
 template <typename word>
 __device__ __forceinline__ void fam_gather_pair(word a, word b, uint32_t m, uint32_t h, word &e, word &o) {
   const int se = (int)((4u * m + h) & 63u), so = (int)((4u * m + 2u + h) & 63u);
@@ -274,7 +295,7 @@ __device__ __forceinline__ void fam_gather_pair(word a, word b, uint32_t m, uint
 __device__ __forceinline__ void fam_consume_pair_f64(uint64_t e, uint64_t o, uint64_t idx, uint64_t n, bool on,
                                                      double *__restrict__ out, bool pair_aligned) {
   double z0, z1;
-  dev::box_muller_f64(e, o, z0, z1);
+  box_muller_f64(e, o, z0, z1);
   const bool has0 = on && idx < n, has1 = on && idx + 1 < n;
   if (pair_aligned && has1) {
     typedef double f64x2 __attribute__((ext_vector_type(2)));

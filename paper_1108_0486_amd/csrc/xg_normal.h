@@ -89,27 +89,6 @@ __device__ __forceinline__ void box_muller(uint32_t e, uint32_t o, float &z0, fl
   z1 = rho * s;
 }
 
-// FP64 normals of the 64-bit member: u1 = ((e >> 11) + 1) 2^-53 in (0, 1]
-// and u2 = (o >> 11) 2^-53 in [0, 1), both exact; z0 = rho cos(2 pi u2),
-// z1 = rho sin(2 pi u2), rho = sqrt(-2 ln u1).  The angle is reduced exactly
-// on the word as in sincos_turn: adding 2^61 to o leaves the quadrant in bits
-// 63:62 and (o's low 11 bits cleared) 2^61 + f 2^63 in bits 61:0, |f| <= 1/4.
-// sin(pi f), cos(pi f), ln and the square root are the device library's FP64
-// functions.
-__device__ __forceinline__ void box_muller_f64(uint64_t e, uint64_t o, double &z0, double &z1) {
-  const double u1 = fma((double)(e >> 11), 0x1p-53, 0x1p-53);  // exact
-  const double rho = sqrt(-2.0 * log(u1));
-  const uint64_t qf = o + (1ull << 61);
-  const double f = fma((double)(qf & 0x3FFFFFFFFFFFF800ull), 0x1p-63, -0.25);  // exact
-  double sp, cp;
-  sincospi(f, &sp, &cp);
-  const bool odd = ((qf >> 62) & 1u) != 0u;
-  const double s0 = odd ? cp : sp, c0 = odd ? sp : cp;
-  const uint64_t sign_s = qf & 0x8000000000000000ull, sign_c = (qf + (1ull << 62)) & 0x8000000000000000ull;
-  z0 = rho * __longlong_as_double((long long)((uint64_t)__double_as_longlong(c0) ^ sign_c));
-  z1 = rho * __longlong_as_double((long long)((uint64_t)__double_as_longlong(s0) ^ sign_s));
-}
-
 // Sums of z and z^2 kept by one lane: each pair is added first (z0 + z1, and
 // z0^2 + z1^2 as one FMA over the rounded z0^2), pairs accumulate plainly in
 // a group of at most four, and each group enters a compensated (Kahan) sum.
