@@ -161,11 +161,11 @@ typedef struct {
  * ignored).  waves_per_block 0 chooses per launch: 4 when count >= 4 x the
  * compute units, else 2 when count >= 2 x, else 1, so one stream's wavefront
  * lands on each SIMD before any SIMD gets a second.  unroll 0 chooses per
- * launch (measured fastest for each): for Section 2's member 4 for the
- * bulk-fill uint32 launch, 8 for the bulk-fill FP32 launch, and 2 with
- * 4-byte stores for the stream-major uint32 and FP32 launches; 8 for every
- * other launch.  The default is {0, 0, 1, 4}.  Output bits do not depend on
- * it.
+ * launch (measured fastest for each): for Section 2's member, when count is
+ * at least 4 x the compute units, 4 for the bulk-fill uint32 launch, 8 for
+ * the bulk-fill FP32 launch, and 2 with 4-byte stores for the stream-major
+ * uint32 and FP32 launches; 8 for every other launch.  The default is
+ * {0, 0, 1, 4}.  Output bits do not depend on it.
  * Errors: XG_EINVAL (NULL pointer or a shape outside the ranges of xg_tune). */
 xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune);
 xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune);

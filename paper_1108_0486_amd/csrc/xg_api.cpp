@@ -86,7 +86,9 @@ bool paper_member(const xg_ctx *ctx) { return ctx && ctx->family == XG_FAMILY_R1
 //    against 780-815 us for unroll 8 with 16-byte stores; uint32 with its
 //    stores paced, see the kernels, 717-736 us);
 //  - normals and moments: 8.
-// The further members keep 8.
+// Those were measured with a wavefront on every SIMD; smaller launches (fewer
+// than 4 x CUs streams, e.g. one stream per launch) keep unroll 8, as do the
+// further members.
 xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count, xg::Kind kind, bool fill_layout) {
   xg::Shape s = ctx->plain;
   const uint64_t waves = ctx->family == XG_FAMILY_R128_W32 ? count : (count + 1) / 2;
@@ -94,7 +96,8 @@ xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count, xg::Kind kind, bool fil
     s.waves_per_block = ctx->family == XG_FAMILY_R64_W64 ? 1u : xg::auto_waves_per_block(waves, ctx->num_cus);
   if (s.unroll == 0) {
     s.unroll = 8;
-    if (ctx->family == XG_FAMILY_R128_W32 && (kind == xg::kU32 || kind == xg::kF32)) {
+    const bool every_simd = waves >= 4 * (uint64_t)(ctx->num_cus > 0 ? ctx->num_cus : 1);
+    if (ctx->family == XG_FAMILY_R128_W32 && every_simd && (kind == xg::kU32 || kind == xg::kF32)) {
       if (fill_layout) {
         s.unroll = kind == xg::kU32 ? 4u : 8u;
       } else {

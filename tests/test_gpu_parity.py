@@ -129,11 +129,16 @@ def test_default_plain_shape():
     assert gs.plain_tune() == (2, 0, 4)
 
 
+@pytest.mark.parametrize("full", [False, True])
 @pytest.mark.parametrize("kind", ["fill_u32", "fill_f32", "u32", "f32"])
-def test_automatic_unroll_matches_oracle(kind):
-    """The automatic unroll (4 for the uint32 bulk fill, 8 otherwise) gives
-    the oracle's bits, with a ragged length, like every explicit shape."""
-    count, n = 9, 64 * 13 + 5
+def test_automatic_unroll_matches_oracle(kind, full):
+    """The automatic shape gives the oracle's bits, with a ragged length
+    (13 chunks and 5 words: an odd chunk count leaves a remainder for every
+    unroll), like every explicit shape.  `full`: a wavefront on every SIMD,
+    where the uint32 fill takes unroll 4 and stream-major unroll 2 with
+    4-byte stores (the uint32 one paced); otherwise unroll 8."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    count, n = (4 * cus + 5 if full else 9), 64 * 13 + 5
     gs = XorgensStreams(count, seed=77)
     ref = O.OracleStreams(77, count)
     want = ref.u32(n) if kind.endswith("u32") else ref.f32(n)
