@@ -28,6 +28,11 @@
  *     HIP stream, or events).  Calls on disjoint stream ranges may overlap.
  *   - All sizes count elements (4-byte words), not bytes, unless named *_bytes.
  *   - No C++ exception crosses this interface.
+ *   - Host threads: calls on different handles may come from different host
+ *     threads.  A handle's launch shape is read at each launch, so
+ *     xg_set_plain_tune must not race with launches on the same handle.  The
+ *     jump polynomials' modulus is built once per member and process,
+ *     thread-safely.  A request server is driven by one host thread.
  *
  * Stream state (device memory, XG_STATE_WORDS 32-bit words per stream, 528 B):
  *   words [0, 128)   ring[t] = x_{pos-128+t}, the last 128 words of the x-part
