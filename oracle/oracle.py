@@ -35,7 +35,9 @@ U32, F32, NORMAL, MOMENTS, SKIP = 0, 1, 2, 3, 4
 def build(force: bool = True) -> str:
     """Compiles liboracle.so with gcc (plain -O2, no hand SIMD in the generator)."""
     if not force and os.path.exists(_LIB_PATH):
-        return _LIB_PATH
+        built = os.path.getmtime(_LIB_PATH)
+        if all(os.path.getmtime(os.path.join(_HERE, s)) <= built for s in _SOURCES):
+            return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-std=gnu11", "-O2", "-fPIC", "-shared", "-mpclmul", "-msse4.1",
            *[os.path.join(_HERE, s) for s in _SOURCES], "-o", tmp, "-lpthread", "-lm"]
@@ -97,8 +99,7 @@ _lib = None
 def lib() -> ctypes.CDLL:
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB_PATH):
-            build()
+        build(force=False)  # builds when missing or older than its sources
         L = ctypes.CDLL(_LIB_PATH)
         P = ctypes.POINTER
         u32p, u64p, u8p = P(ctypes.c_uint32), P(ctypes.c_uint64), P(ctypes.c_uint8)
@@ -279,6 +280,13 @@ class OracleStreams64:
         consumes 2 ceil(n / 2) words."""
         out = np.empty((self.count, n), dtype=np.float64)
         self._run(2, n, out, threads)
+        return out
+
+    def moments(self, n: int, threads: int | None = None) -> np.ndarray:
+        """[count, 3]: sums of z, z^2 and |z| over the n normals normal(n)
+        would give, accumulated in long double; the same words consumed."""
+        out = np.empty((self.count, 3), dtype=np.float64)
+        self._run(3, n, out, threads)
         return out
 
     def skip(self, n: int, threads: int | None = None) -> None:

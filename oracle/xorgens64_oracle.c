@@ -156,10 +156,11 @@ void xgo64_box_muller(uint64_t o_even, uint64_t o_odd, double *z0, double *z1)
     *z1 = (double)(rho * s);
 }
 
-enum { XGO64_U64 = 0, XGO64_F64 = 1, XGO64_NORMAL = 2, XGO64_SKIP = 4 };
+enum { XGO64_U64 = 0, XGO64_F64 = 1, XGO64_NORMAL = 2, XGO64_MOMENTS = 3, XGO64_SKIP = 4 };
 
-/* A normal request of n variates consumes 2 ceil(n / 2) words (odd n drops
-   the last sine value). */
+/* A normal (or moments) request of n variates consumes 2 ceil(n / 2) words
+   (odd n drops the last sine value).  MOMENTS writes 3 doubles: the sums of
+   z, z^2 and |z| over the n normals, accumulated in long double. */
 static void run_one(const xgo64_params *p, xgo64_state *st, int kind, uint64_t n, void *out)
 {
     uint64_t t;
@@ -169,16 +170,23 @@ static void run_one(const xgo64_params *p, xgo64_state *st, int kind, uint64_t n
     } else if (kind == XGO64_F64) {
         double *o = (double *)out;
         for (t = 0; t < n; t++) o[t] = (double)(step_out(p, st) >> 11) * 0x1p-53;
-    } else if (kind == XGO64_NORMAL) {
+    } else if (kind == XGO64_NORMAL || kind == XGO64_MOMENTS) {
         double *o = (double *)out;
+        long double s1 = 0.0L, s2 = 0.0L, sa = 0.0L;
         for (t = 0; t < n; t += 2) {
             uint64_t e = step_out(p, st);
             uint64_t d = step_out(p, st);
             double z0, z1;
             xgo64_box_muller(e, d, &z0, &z1);
-            o[t] = z0;
-            if (t + 1 < n) o[t + 1] = z1;
+            if (kind == XGO64_NORMAL) {
+                o[t] = z0;
+                if (t + 1 < n) o[t + 1] = z1;
+            } else {
+                s1 += z0; s2 += (long double)z0 * z0; sa += fabsl(z0);
+                if (t + 1 < n) { s1 += z1; s2 += (long double)z1 * z1; sa += fabsl(z1); }
+            }
         }
+        if (kind == XGO64_MOMENTS) { o[0] = (double)s1; o[1] = (double)s2; o[2] = (double)sa; }
     } else {
         for (t = 0; t < n; t++) (void)step_out(p, st);
     }
@@ -223,7 +231,8 @@ int xgo64_seed_streams(const xgo64_params *p, uint64_t seed, uint64_t first, uin
 }
 
 /* Advances every stream by n values of `kind` (U64: uint64_t out, F64: double
-   out, NORMAL: double out, 2 ceil(n / 2) words; SKIP: none), stream i's
+   out, NORMAL: double out, 2 ceil(n / 2) words; MOMENTS: 3 doubles per stream,
+   the same words; SKIP: none), stream i's
    values at out + i * out_stride_bytes, on up
    to `threads` POSIX threads over disjoint streams. */
 int xgo64_run_streams(const xgo64_params *p, uint64_t *ring, uint64_t *weyl, uint64_t *pos,
@@ -234,7 +243,7 @@ int xgo64_run_streams(const xgo64_params *p, uint64_t *ring, uint64_t *weyl, uin
     job64_t jobs[256];
     int t, nt;
     if (!xgo64_params_valid(p)) return -1;
-    if (kind != XGO64_U64 && kind != XGO64_F64 && kind != XGO64_NORMAL && kind != XGO64_SKIP) return -1;
+    if (kind < XGO64_U64 || kind > XGO64_SKIP) return -1;
     if (kind != XGO64_SKIP && out == NULL && count > 0) return -1;
     nt = threads < 1 ? 1 : (threads > 256 ? 256 : threads);
     if ((uint64_t)nt > count) nt = count ? (int)count : 1;

@@ -254,3 +254,17 @@ def test_w64_normals_moments():
     assert abs(z.mean()) < 5 / math.sqrt(n)
     assert abs(z.var() - 1.0) < 5 * math.sqrt(2.0 / n)
     assert abs((z**4).mean() - 3.0) < 5 * math.sqrt(96.0 / n)
+
+
+@pytest.mark.parametrize("n", [1, 2, 7, 1000])
+def test_w64_moments_are_the_sums_of_the_normals(n):
+    """The moments kind sums exactly the normals the normal kind returns (and
+    consumes the same words): against numpy sums of normal(n) to a few ulp."""
+    a = O.OracleStreams64(17, 4, W64)
+    b = a.copy()
+    m = a.moments(n)
+    z = b.normal(n)
+    assert np.allclose(m[:, 0], z.sum(axis=1), rtol=0, atol=1e-12 * np.abs(z).sum(axis=1).max())
+    assert np.allclose(m[:, 1], (z * z).sum(axis=1), rtol=1e-13)
+    assert np.allclose(m[:, 2], np.abs(z).sum(axis=1), rtol=1e-13)
+    assert (a.ring == b.ring).all() and (a.pos == b.pos).all() and (a.weyl == b.weyl).all()
