@@ -86,7 +86,9 @@ typedef int32_t xg_status;
  *                       fused moments (as for Section 2's member), and xg_skip.
  *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
  *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), FP64
- *                       normals (xg_generate_normal_f64), and xg_skip.
+ *                       normals and their fused moments
+ *                       (xg_generate_normal_f64, xg_normal_moments_f64), and
+ *                       xg_skip.
  * The paper gives shifts only for the first; those of the other two were
  * chosen by a search for primitive characteristic polynomials.  Calls a
  * member does not support return XG_ENOTSUP. */
@@ -238,6 +240,16 @@ xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
 xg_status xg_generate_normal_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                                  double *d_out, void *stream);
 
+/* Fused FP64 generate-and-consume for XG_FAMILY_R64_W64: each stream draws n
+ * normals exactly as xg_generate_normal_f64 would (never written to memory)
+ * and reduces them in-kernel to d_sums[2 (i - first)] = sum of z and
+ * d_sums[2 (i - first) + 1] = sum of z^2, in FP64 with compensated per-lane
+ * sums and a pairwise reduction across the stream's lanes.  The streams
+ * advance by 2 ceil(n / 2) words.  Other families: XG_ENOTSUP.  Otherwise
+ * the errors of xg_generate_u64 (d_sums holds 2 * count doubles). */
+xg_status xg_normal_moments_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
+                                double *d_sums, void *stream);
+
 /* Standard normals by the Box-Muller transform on consecutive pairs of
  * outputs (o_{2m}, o_{2m+1}) of the call: u1 = ((o_{2m} >> 8) + 1) 2^-24 in
  * (0, 1], u2 = (o_{2m+1} >> 8) 2^-24 in [0, 1), rho = sqrt(-2 ln u1),
@@ -260,8 +272,8 @@ xg_status xg_box_muller(const uint32_t *d_words, uint64_t pairs, float *d_out, v
  * reduces them in-kernel to
  *     d_sums[2 (i - first)]     = sum of z      (FP32)
  *     d_sums[2 (i - first) + 1] = sum of z^2    (FP32)
- * with compensated per-lane sums and a pairwise reduction across the
- * wavefront.  The streams advance by 2 * ceil(n / 2) words.
+ * with compensated FP32 per-lane sums, reduced across the wavefront in FP64
+ * and rounded once to FP32.  The streams advance by 2 * ceil(n / 2) words.
  * Same errors as xg_generate_u32 (d_sums holds 2 * count floats). */
 xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n,
                             float *d_sums, void *stream);

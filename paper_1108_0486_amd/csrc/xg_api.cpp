@@ -155,6 +155,20 @@ xg_status fill(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint6
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
+// FP64 normals (kNormal: n doubles per stream) or their fused sums
+// (kMoments: 2 doubles per stream) of the 64-bit member.
+xg_status normals_f64(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint64_t n, double *d_out,
+                      void *stream) {
+  if (!ctx) return XG_EINVAL;
+  if (ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
+  const xg_status st = check_range(ctx, first, count, n, d_out, kind == xg::kMoments ? 2 : n, 8);
+  if (st != XG_OK || n == 0) return st;
+  const hipError_t e = xg::launch_family_generate(ctx->family, kind, false, plain_shape(ctx, count, kind, false),
+                                                  reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
+                                                  n, d_out, static_cast<hipStream_t>(stream));
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
 bool tune_to_shape(const xg_tune *t, uint32_t blocks_per_cu, xg::Shape *s) {
   if (!t) return false;
   const uint32_t sw = t->store_words ? t->store_words : (t->unroll >= 4 ? 4u : 1u);
@@ -295,15 +309,12 @@ xg_status xg_fill_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, d
 
 xg_status xg_generate_normal_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, double *d_out,
                                  void *stream) {
-  if (!ctx) return XG_EINVAL;
-  if (ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
-  const xg_status st = check_range(ctx, first, count, n, d_out, n, 8);
-  if (st != XG_OK || n == 0) return st;
-  const hipError_t e = xg::launch_family_generate(ctx->family, xg::kNormal, false,
-                                                  plain_shape(ctx, count, xg::kNormal, false),
-                                                  reinterpret_cast<unsigned char *>(ctx->d_state), first, count,
-                                                  n, d_out, static_cast<hipStream_t>(stream));
-  return e == hipSuccess ? XG_OK : XG_EHIP;
+  return normals_f64(ctx, xg::kNormal, first, count, n, d_out, stream);
+}
+
+xg_status xg_normal_moments_f64(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t n, double *d_sums,
+                                void *stream) {
+  return normals_f64(ctx, xg::kMoments, first, count, n, d_sums, stream);
 }
 
 xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void *stream) {

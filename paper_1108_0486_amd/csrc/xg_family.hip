@@ -290,14 +290,35 @@ __device__ __forceinline__ void fam_gather_pair(word a, word b, uint32_t m, uint
   o = upper ? ob : oa;
 }
 
-// Stores FP64 normals idx and idx + 1 of the call (those below n); a pair is
-// one 16-byte store when `pair_aligned` (wave-uniform).
+// Compensated FP64 sums of z and z^2 kept by one lane (one update per pair).
+struct MomentsF64 {
+  double s1, c1, s2, c2;
+};
+
+__device__ __forceinline__ void kahan_add_f64(double &s, double &c, double v) {
+  const double y = v - c;
+  const double t = s + y;
+  c = (t - s) - y;
+  s = t;
+}
+
+// FP64 normals idx and idx + 1 of the call (those below n): stored (a pair is
+// one 16-byte store when `pair_aligned`, wave-uniform) or, MOMENTS, added to
+// the lane's sums as z0 + z1 and fma(z1, z1, z0 z0).
+template <bool MOMENTS>
 __device__ __forceinline__ void fam_consume_pair_f64(uint64_t e, uint64_t o, uint64_t idx, uint64_t n, bool on,
-                                                     double *__restrict__ out, bool pair_aligned) {
+                                                     double *__restrict__ out, bool pair_aligned,
+                                                     MomentsF64 &m) {
   double z0, z1;
   box_muller_f64(e, o, z0, z1);
   const bool has0 = on && idx < n, has1 = on && idx + 1 < n;
-  if (pair_aligned && has1) {
+  if constexpr (MOMENTS) {
+    if (has0) {  // has1 implies has0
+      const double b = has1 ? z1 : 0.0;
+      kahan_add_f64(m.s1, m.c1, z0 + b);
+      kahan_add_f64(m.s2, m.c2, fma(b, b, z0 * z0));
+    }
+  } else if (pair_aligned && has1) {
     typedef double f64x2 __attribute__((ext_vector_type(2)));
     const f64x2 pair = {z0, z1};
     __builtin_nontemporal_store(pair, reinterpret_cast<f64x2 *>(out + idx));
@@ -336,12 +357,12 @@ __device__ __forceinline__ void fam_consume_pair(uint32_t e, uint32_t o, uint64_
 template <class M, bool MOMENTS>
 __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict__ state, uint64_t first,
                                                       uint64_t count, uint64_t n, void *__restrict__ out_v,
-                                                      float *__restrict__ sums) {
+                                                      void *__restrict__ sums_v) {
   using word = typename M::word;
   constexpr bool kW64 = sizeof(word) == 8;
-  static_assert(!(kW64 && MOMENTS), "fused moments exist for the 32-bit member only");
   using real = typename std::conditional<kW64, double, float>::type;
   real *out = static_cast<real *>(out_v);
+  real *sums = static_cast<real *>(sums_v);
   const Lanes L = lanes_of(count, xcd_block());
   if (2 * (L.k >> 1) >= count) return;  // wave-uniform
   const bool on = L.active;
@@ -374,8 +395,9 @@ __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict_
   const bool pair_aligned =
       !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(out) & (2 * sizeof(real) - 1)) == 0;
   dev::Moments mo{0.0f, 0.0f, 0.0f, 0.0f, -0.0f, -0.0f};
+  MomentsF64 md{0.0, 0.0, 0.0, 0.0};
   auto consume = [&](word e, word o, uint64_t idx) {
-    if constexpr (kW64) fam_consume_pair_f64(e, o, idx, n, on, o_s, pair_aligned);
+    if constexpr (kW64) fam_consume_pair_f64<MOMENTS>(e, o, idx, n, on, o_s, pair_aligned, md);
     else fam_consume_pair<MOMENTS>(e, o, idx, n, on, o_s, pair_aligned, mo);
   };
   for (uint64_t b = 0; b != nblk; ++b) {
@@ -414,15 +436,24 @@ __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict_
   }
   store_state<M>(st, L, p0, c0, xl, rem, w_start + (word)words * M::omega, pos + words);
   if constexpr (MOMENTS) {
-    float v1 = mo.s1 - mo.c1, v2 = mo.s2 - mo.c2;
+    // Folded and reduced across the stream's lanes in FP64 (for the FP32
+    // sums: rounded once to FP32 at the end).
+    double v1, v2;
+    if constexpr (kW64) {
+      v1 = md.s1 - md.c1;
+      v2 = md.s2 - md.c2;
+    } else {
+      v1 = (double)mo.s1 - (double)mo.c1;
+      v2 = (double)mo.s2 - (double)mo.c2;
+    }
 #pragma unroll
     for (int off = 32; off >= 2; off >>= 1) {  // even offsets keep each stream's lanes apart
       v1 += __shfl_xor(v1, off);
       v2 += __shfl_xor(v2, off);
     }
     if (on && L.j == 0) {
-      sums[2 * L.k] = v1;
-      sums[2 * L.k + 1] = v2;
+      sums[2 * L.k] = (real)v1;
+      sums[2 * L.k + 1] = (real)v2;
     }
   }
 }
@@ -595,9 +626,13 @@ hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const S
                          o);
     return hipGetLastError();
   }
-  if (family == XG_FAMILY_R64_W64 && kind == kNormal) {
-    hipLaunchKernelGGL((k_fam_normals<MemberW64, false>), grid, block, 0, stream, state, first, count, n, out,
-                       nullptr);
+  if (family == XG_FAMILY_R64_W64 && (kind == kNormal || kind == kMoments)) {
+    if (kind == kNormal)
+      hipLaunchKernelGGL((k_fam_normals<MemberW64, false>), grid, block, 0, stream, state, first, count, n, out,
+                         nullptr);
+    else
+      hipLaunchKernelGGL((k_fam_normals<MemberW64, true>), grid, block, 0, stream, state, first, count, n, nullptr,
+                         out);
     return hipGetLastError();
   }
   if (family == XG_FAMILY_R64_W32 && kind == kU32)

@@ -442,15 +442,18 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
   }
   write_state(dst, p0, c0, xl, rem, w_start + (uint32_t)words * kOmega, pos + words, lane);
   if constexpr (MOMENTS) {
-    float v1 = m.s1 - m.c1, v2 = m.s2 - m.c2;
+    // The lanes' compensated sums are folded and reduced across the
+    // wavefront in FP64, then rounded once to FP32: the reduction then adds
+    // well under one FP32 rounding to the error of the sums.
+    double v1 = (double)m.s1 - (double)m.c1, v2 = (double)m.s2 - (double)m.c2;
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
       v1 += __shfl_xor(v1, off);
       v2 += __shfl_xor(v2, off);
     }
     if (lane == 0) {
-      sums[0] = v1;
-      sums[1] = v2;
+      sums[0] = (float)v1;
+      sums[1] = (float)v2;
     }
   }
 }

@@ -140,6 +140,14 @@ class XorgensStreams:
         xg.xg_generate_normal_f64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
         return out
 
+    def moments_f64(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
+                    stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """[count, 2] FP64 sums of z and z^2 over n fused normals (64-bit member)."""
+        first, count = self._range(first, count)
+        out = self._out(out, (count, 2), torch.float64)
+        xg.xg_normal_moments_f64(self.ctx, first, count, n, out.data_ptr(), _stream_handle(stream))
+        return out
+
     def normal(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,
                stream: torch.cuda.Stream | None = None) -> torch.Tensor:
         first, count = self._range(first, count)

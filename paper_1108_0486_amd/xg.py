@@ -118,6 +118,7 @@ def lib() -> ctypes.CDLL:
         "xg_fill_u64": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_fill_f64": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_generate_normal_f64": (st, [vp, u64, u64, u64, vp, vp]),
+        "xg_normal_moments_f64": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
         "xg_plan_batch": (st, [P(xg_request), u32, u64, u64, P(xg_request), P(u32), P(u32)]),
         "xg_generate_batch": (st, [vp, vp, u32, vp, u32, vp, u64, P(xg_tune), vp, vp]),
@@ -273,6 +274,10 @@ def xg_fill_f64(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0
 
 def xg_generate_normal_f64(ctx, first: int, count: int, n: int, d_out: int, stream: int = 0) -> None:
     _check(lib().xg_generate_normal_f64(ctx, first, count, n, d_out, stream), "xg_generate_normal_f64")
+
+
+def xg_normal_moments_f64(ctx, first: int, count: int, n: int, d_sums: int, stream: int = 0) -> None:
+    _check(lib().xg_normal_moments_f64(ctx, first, count, n, d_sums, stream), "xg_normal_moments_f64")
 
 
 def xg_box_muller(d_words: int, pairs: int, d_out: int, stream: int = 0) -> None:

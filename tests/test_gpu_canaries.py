@@ -43,12 +43,13 @@ CASES = []
 for n in (1, 31, 33, 63, 65, 129, 1001):
     CASES += [(xg.XG_FAMILY_R128_W32, name, n) for name in ("u32", "f32", "normal", "moments", "fill_u32", "fill_f32")]
     CASES += [(xg.XG_FAMILY_R64_W32, name, n) for name in ("u32", "f32", "normal", "moments", "fill_u32", "fill_f32")]
-    CASES += [(xg.XG_FAMILY_R64_W64, name, n) for name in ("u64", "f64", "fill_u64", "fill_f64", "normal_f64")]
+    CASES += [(xg.XG_FAMILY_R64_W64, name, n) for name in ("u64", "f64", "fill_u64", "fill_f64", "normal_f64",
+                                                           "moments_f64")]
 
 
 def _words_of(name, n, count):
-    per = 2 if name == "moments" else n
-    wide = name in ("u64", "f64", "fill_u64", "fill_f64", "normal_f64")
+    per = 2 if name.startswith("moments") else n
+    wide = name in ("u64", "f64", "fill_u64", "fill_f64", "normal_f64", "moments_f64")
     return count * per * (2 if wide else 1)
 
 
@@ -59,7 +60,7 @@ def _run(family, name, n, first, count, out_words):
     for _ in range(2):
         gs.restore(saved)
         buf, view = _guarded(out_words)
-        if name in ("u64", "f64", "fill_u64", "fill_f64", "normal_f64"):
+        if name in ("u64", "f64", "fill_u64", "fill_f64", "normal_f64", "moments_f64"):
             dt = torch.int64 if "u64" in name else torch.float64
             target = view.view(dt)
         elif name in ("f32", "normal", "moments", "fill_f32"):
@@ -68,8 +69,8 @@ def _run(family, name, n, first, count, out_words):
             target = view
         if name.startswith("fill"):
             getattr(gs, name)(n, first=first, count=count, out=target)
-        elif name == "moments":
-            gs.moments(n, first=first, count=count, out=target.view(count, 2))
+        elif name.startswith("moments"):
+            getattr(gs, name)(n, first=first, count=count, out=target.view(count, 2))
         else:
             getattr(gs, name)(n, first=first, count=count, out=target.view(count, -1))
         torch.cuda.synchronize()

@@ -147,7 +147,8 @@ def test_family_unsupported_calls_are_rejected(fam):
                  lambda: xg.xg_generate_u32(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f32(gs.ctx, 0, 4, 8, p)]
     else:
         calls = [lambda: xg.xg_generate_u64(gs.ctx, 0, 4, 8, p), lambda: xg.xg_fill_f64(gs.ctx, 0, 4, 8, p),
-                 lambda: xg.xg_generate_normal_f64(gs.ctx, 0, 4, 8, p)]
+                 lambda: xg.xg_generate_normal_f64(gs.ctx, 0, 4, 8, p),
+                 lambda: xg.xg_normal_moments_f64(gs.ctx, 0, 4, 8, p)]
     for c in calls:
         with pytest.raises(xg.XgError) as e:
             c()
@@ -161,7 +162,7 @@ def test_family_unsupported_calls_are_rejected(fam):
         Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4)
     assert e.value.status == xg.XG_ENOTSUP
     paper = XorgensStreams(4, seed=1)
-    for c in (xg.xg_generate_u64, xg.xg_generate_normal_f64):
+    for c in (xg.xg_generate_u64, xg.xg_generate_normal_f64, xg.xg_normal_moments_f64):
         with pytest.raises(xg.XgError) as e:
             c(paper.ctx, 0, 4, 8, p)
         assert e.value.status == xg.XG_ENOTSUP
@@ -306,3 +307,25 @@ def test_w64_normals_f64_large_sample():
     err = ulp64_error(z, zr)
     print("FP64 normals: max error %.3f ulp over %d values" % (err.max(), err.size))
     assert err.max() <= 4.0
+
+
+@pytest.mark.parametrize("n", [1, 2, 64, 65, 1000, 4133, 1 << 16])
+def test_w64_moments_f64_within_bound(n):
+    """Fused FP64 sums of z and z^2 of the 64-bit member within tau = 27 u
+    (u = 2^-53) of the oracle's long-double sums, relative to sum |z| and
+    sum z^2: variates within 4 ulp (8 u), the pair add or square-and-FMA
+    (1 u / 2 u), the lane's compensated sum (2 u), its fold (1 u) and a
+    5-level tree over the stream's 32 lanes (5 u) give at most 17 u and
+    26 u.  The streams then continue as the oracle's."""
+    gs = XorgensStreams(21, seed=5, family=R64W64)
+    ref = _oracle(R64W64, 5, 21)
+    m = gs.moments_f64(n).cpu().numpy()
+    mr = ref.moments(n)
+    tau = 27 * 2.0**-53
+    e1 = np.abs(m[:, 0] - mr[:, 0]) / mr[:, 2]
+    e2 = np.abs(m[:, 1] - mr[:, 1]) / mr[:, 1]
+    print("FP64 moments n=%d: max rel err %.3g, %.3g (bound %.3g)" % (n, e1.max(), e2.max(), tau))
+    assert (e1 <= tau).all() and (e2 <= tau).all()
+    torch.cuda.synchronize()
+    _assert_state(gs, ref)
+    assert (_bits(gs.u64(70)) == ref.u64(70)).all()
