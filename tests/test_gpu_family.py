@@ -329,3 +329,37 @@ def test_w64_moments_f64_within_bound(n):
     torch.cuda.synchronize()
     _assert_state(gs, ref)
     assert (_bits(gs.u64(70)) == ref.u64(70)).all()
+
+
+def test_w64_normals_f64_exact_special_values():
+    """The FP64 map's exact cases, forced through attached states.  With an
+    all-zero x-part ring the outputs are the tempered Weyl values alone,
+    out = W xor (W >> 32) (Section 1.5, Eq. (1)), so a chosen W_0 fixes the
+    words: out = 0xFFFFFFFF_FFFFF800 gives u1 = 1 (both normals exactly 0);
+    out = k 2^62 gives u2 = k / 4 (a quarter turn: one normal exactly 0, the
+    other +-rho).  Each stream's W_{-1} = W_0 - omega; the GPU must equal the
+    oracle from the same states, with the exact zeros and signs."""
+    omega = O.W64.omega
+    m64 = (1 << 64) - 1
+    # stream 0: word 0 gives u1 = 1; streams 1..4: word 1 gives u2 = k / 4
+    w0s = [0xFFFFFFFF000007FF]
+    for k in range(4):
+        w1 = (k << 62) | (k << 30)                       # out_1 = W ^ (W >> 32) = k 2^62
+        w0s.append((w1 - omega) & m64)
+    S = len(w0s)
+    words = np.zeros((S, 66), dtype=np.uint64)             # ring u64[64] | W | pos
+    words[:, 64] = [(w - omega) & m64 for w in w0s]
+    state = torch.from_numpy(words.view(np.int64).ravel().copy()).cuda()
+    gs = XorgensStreams.attach(state, S, family=R64W64)
+    ref = O.OracleStreams64.from_state(np.zeros((S, 64), dtype=np.uint64), words[:, 64].copy(),
+                                       np.zeros(S, dtype=np.uint64), O.W64)
+    z = gs.normal_f64(4).cpu().numpy()
+    zr = ref.normal(4)
+    assert z[0, 0] == 0.0 and z[0, 1] == 0.0 and zr[0, 0] == 0.0 and zr[0, 1] == 0.0
+    for k in range(4):
+        c, s = [(1, 0), (0, 1), (-1, 0), (0, -1)][k]
+        z0, z1 = z[1 + k, 0], z[1 + k, 1]
+        assert (z0 == 0.0) == (c == 0) and (z1 == 0.0) == (s == 0), (k, z0, z1)
+        assert np.sign(z0) == c or c == 0, k
+        assert np.sign(z1) == s or s == 0, k
+    assert ulp64_error(z, zr).max() <= 4.0
