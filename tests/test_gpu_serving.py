@@ -298,3 +298,27 @@ def test_serving_full_size_sampled():
                 assert ulp32_error(v, ref.normal(L)[0]).max() <= 4.0, (c.id, t)
             splits += t >= (1 << 16)
     assert splits >= 100          # many checked slices lie beyond the first segment
+
+
+@pytest.mark.parametrize("seed,seg,pool,lanes,max_batch", [
+    (21, None, 1 << 16, 2, 8),          # small pool: admission waits; small tables
+    (22, 4096, 1 << 17, 3, 6),          # segments; some requests too long to split into 6
+    (23, 4096, 1 << 20, 4, 64),         # segments, roomy
+    (24, None, 1 << 20, 1, 1),          # one request per batch
+])
+def test_serving_random_traces_match_oracle(seed, seg, pool, lanes, max_batch):
+    """Randomised traces (few streams, so requests chain on a stream; N from 1
+    to 2^15; all three dtypes) through servers configured to hit the
+    admission paths: a pool far smaller than the trace, tables that hold
+    fewer entries than a split request has segments, a single lane.  Every
+    value of every request equals the oracle's from its start position, and
+    each stream's requests chain without gaps."""
+    S = 12
+    gs = XorgensStreams(S, seed=SEED)
+    kw = {} if seg is None else {"segment_words": seg}
+    srv = Server(gs, pool_elems=pool, num_lanes=lanes, max_batch=max_batch, **kw)
+    trace = W.serving_trace(250, num_streams=S, rate=200_000.0, seed=seed, lo_exp=0, hi_exp=15)
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True, timeout_s=60)
+    assert summary["server"]["completed"] == len(trace)
+    _check_against_oracle(done, outputs, S)
+    srv.close()
