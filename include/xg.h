@@ -171,8 +171,10 @@ typedef struct {
  * launch (measured fastest for each): for Section 2's member, when count is
  * at least 4 x the compute units, 4 for the bulk-fill uint32 launch, 8 for
  * the bulk-fill FP32 launch, and 2 with 4-byte stores for the stream-major
- * uint32 and FP32 launches; 8 for every other launch.  The default is
- * {0, 0, 1, 4}.  Output bits do not depend on it.
+ * uint32 and FP32 launches; for XG_FAMILY_R64_W32 (count at least 8 x the
+ * compute units: two streams per wavefront) 2 for its stream-major launches;
+ * 8 for every other launch.  The default is {0, 0, 1, 4}.  Output bits do not
+ * depend on it.
  * Errors: XG_EINVAL (NULL pointer or a shape outside the ranges of xg_tune). */
 xg_status xg_set_plain_tune(xg_ctx *ctx, const xg_tune *tune);
 xg_status xg_get_plain_tune(const xg_ctx *ctx, xg_tune *tune);

@@ -86,9 +86,12 @@ bool paper_member(const xg_ctx *ctx) { return ctx && ctx->family == XG_FAMILY_R1
 //    against 780-815 us for unroll 8 with 16-byte stores; uint32 with its
 //    stores paced, see the kernels, 717-736 us);
 //  - normals and moments: 8.
+// For the 32-bit r = 64 member (2048 streams, 1024 wavefronts) stream-major
+// uint32 / FP32 take 2 as well (u32 764-779 us against 828 us, f32 740-754
+// against 789-812 us, three boxes); its fills keep 8.
 // Those were measured with a wavefront on every SIMD; smaller launches (fewer
-// than 4 x CUs streams, e.g. one stream per launch) keep unroll 8, as do the
-// further members.
+// than 4 x CUs wavefronts, e.g. one stream per launch) keep unroll 8, as does
+// the 64-bit member.
 xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count, xg::Kind kind, bool fill_layout) {
   xg::Shape s = ctx->plain;
   const uint64_t waves = ctx->family == XG_FAMILY_R128_W32 ? count : (count + 1) / 2;
@@ -104,6 +107,9 @@ xg::Shape plain_shape(const xg_ctx *ctx, uint64_t count, xg::Kind kind, bool fil
         s.unroll = 2;
         s.store_words = 1;
       }
+    } else if (ctx->family == XG_FAMILY_R64_W32 && every_simd && !fill_layout &&
+               (kind == xg::kU32 || kind == xg::kF32)) {
+      s.unroll = 2;
     }
   }
   return s;

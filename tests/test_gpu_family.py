@@ -363,3 +363,24 @@ def test_w64_normals_f64_exact_special_values():
         assert np.sign(z0) == c or c == 0, k
         assert np.sign(z1) == s or s == 0, k
     assert ulp64_error(z, zr).max() <= 4.0
+
+
+@pytest.mark.parametrize("fp", [False, True])
+def test_r64w32_automatic_shape_every_simd(fp):
+    """With a wavefront on every SIMD (8 x CUs + 3 streams of the 32-bit r = 64
+    member; the last wavefront holds one stream) the automatic shape takes
+    unroll 2 for stream-major and 8 for the fill: both layouts equal the
+    oracle at a ragged length (13 steps and 5 words), and so do the states."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    count, n = 8 * cus + 3, 32 * 13 + 5
+    gs = XorgensStreams(count, seed=19, family=R64W32)
+    ref = _oracle(R64W32, 19, count)
+    sm = _bits(gs.f32(n)) if fp else _bits(gs.u32(n))
+    want = _ref_words(ref, R64W32, n, fp=fp)
+    assert (sm == (want.view(np.uint32) if fp else want)).all()
+    fill = _bits(gs.fill_f32(n) if fp else gs.fill_u32(n))
+    want = _ref_words(ref, R64W32, n, fp=fp)
+    idx = xg.fill_index(count, n, chunk=32)
+    assert (fill[idx] == (want.view(np.uint32) if fp else want)).all()
+    torch.cuda.synchronize()
+    _assert_state(gs, ref)
