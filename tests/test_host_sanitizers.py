@@ -7,7 +7,8 @@ undefined (any report aborts the program):
   * libxg's host-only sources (the batch planner and the jump polynomials,
     which include no HIP header), whose jump polynomials must also equal the
     oracle's z^J mod P;
-  * the request server's output pool, fuzzed against a brute-force model.
+  * the request server's output pool, fuzzed against a brute-force model;
+  * the jump polynomials' lazy initialisation under ThreadSanitizer.
 """
 import os
 import shutil
@@ -67,3 +68,18 @@ def test_server_pool_under_sanitizers(tmp_path):
     _need("g++")
     cmd = ["g++", "-std=c++17", *SAN, "-I", CSRC, os.path.join(HERE, "sanitize", "pool_driver.cpp")]
     _run(cmd, tmp_path)
+
+
+def test_jump_polynomials_under_thread_sanitizer(tmp_path):
+    """Eight threads make the first calls for every member at once (the moduli
+    are built lazily, once per process); ThreadSanitizer must stay silent and
+    every thread's z^J mod P must equal a later single-threaded one."""
+    _need("g++")
+    exe = str(tmp_path / "jt")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-I", os.path.join(ROOT, "include"),
+                    "-I", CSRC, os.path.join(HERE, "sanitize", "jump_threads.cpp"), os.path.join(CSRC, "xg_jump.cpp"),
+                    "-o", exe, "-lpthread"], check=True, cwd=ROOT)
+    p = subprocess.run([exe], capture_output=True, text=True, timeout=120,
+                       env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert p.returncode == 0 and p.stdout.strip().endswith("OK"), p.stdout + p.stderr
+    assert "ThreadSanitizer" not in p.stderr, p.stderr
