@@ -107,6 +107,18 @@ def test_ragged_batch_full_size_graph():
         got = as_u32(b.out[int(off[i]):int(off[i]) + n])
         one = ref.subset([j])
         assert (got == one.u32(n)[0]).all(), i
+    # End states of 512 more streams: each depends on every word the stream
+    # generated.  The oracle reaches them by its own polynomial jump
+    # (z^n mod P on the x-part, n omega on the Weyl word).
+    P = O.charpoly(O.PAPER)
+    more = sorted(rng.choice(S, size=512, replace=False).tolist())
+    ring, weyl, _ = gs.host_state(more)
+    for j, i in enumerate(more):
+        n = int(lengths[i])
+        start = O.OracleStreams(W.SEED + i, 1)
+        g = O.poly_to_words(O.z_pow_mod(n, P), 64)
+        assert (ring[j] == O.xpart_jump_poly(O.PAPER, start.ring[0], g)).all(), i
+        assert int(weyl[j]) == (int(start.weyl[0]) + n * O.PAPER.omega) % 2**32, i
     del recs
 
 
