@@ -263,7 +263,9 @@ def test_serving_full_size_sampled():
     seed-11 trace (N up to 2^24, all three dtypes), submitted at once so the
     batches mix.  Every request's first 64 values, and for the 60 longest and
     90 random others also 64 values in the middle and at the end (inside
-    jumped segments), equal the oracle's at the request's start position."""
+    jumped segments), equal the oracle's at the request's start position; and
+    every touched stream ends in the oracle's state after the words its
+    requests consumed."""
     trace = W.serving_trace(1500)
     gs = XorgensStreams(W.SERVE_STREAMS, seed=SEED)
     srv = Server(gs, pool_elems=1 << 31, num_lanes=4, max_batch=8192, segment_words=1 << 16)
@@ -285,6 +287,17 @@ def test_serving_full_size_sampled():
     srv.close()
     assert len(got) == len(trace)
     P = O.charpoly(O.PAPER)
+    # End state of every stream the trace touched: it depends on every word
+    # its requests (and their jumped segments) generated.
+    used = {}
+    for c, _ in got.values():
+        used[c.stream] = used.get(c.stream, 0) + c.n + (c.n & 1 if c.dtype == xg.XG_NORMAL else 0)
+    touched = sorted(used)
+    ring, weyl, pos = gs.host_state(touched)
+    for j, st in enumerate(touched):
+        ref = _oracle_at(st, used[st], P)
+        assert int(pos[j]) == used[st], st
+        assert (ring[j] == ref.ring[0]).all() and int(weyl[j]) == int(ref.weyl[0]), st
     splits = 0
     for c, slices in got.values():
         for t, v in slices.items():
