@@ -29,6 +29,9 @@ class Batch:
         dev = streams.device
         self.d_reqs = torch.from_numpy(raw).to(dev)
         self.d_groups = torch.from_numpy(np.array(groups, dtype=np.uint32).view(np.int32)).to(dev)
+        if out is not None and (not out.is_cuda or not out.is_contiguous() or out.element_size() != 4
+                                or out.numel() < self.out_elems):
+            raise ValueError("out must be a contiguous GPU tensor of at least out_elems 4-byte elements")
         self.out = out if out is not None else torch.empty(max(1, self.out_elems), dtype=torch.int32, device=dev)
         self.work = torch.zeros(xg.xg_batch_workspace_bytes() // 4, dtype=torch.int32, device=dev)
 

@@ -68,8 +68,23 @@ class XorgensStreams:
         return first, (self.num_streams - first if count is None else count)
 
     def _out(self, out, shape, dtype):
+        """A new output tensor, or the caller's after checks that keep every
+        kernel write inside it: on a GPU, contiguous, elements of the dtype's
+        width, and at least as many as the call writes."""
         if out is None:
             return torch.empty(shape, dtype=dtype, device=self.device)
+        need = 1
+        for d in shape:
+            need *= int(d)
+        width = torch.empty((), dtype=dtype).element_size()
+        if not out.is_cuda:
+            raise ValueError("out must be a GPU tensor")
+        if not out.is_contiguous():
+            raise ValueError("out must be contiguous")
+        if out.element_size() != width:
+            raise ValueError("out has %d-byte elements; this call writes %d-byte values" % (out.element_size(), width))
+        if out.numel() < need:
+            raise ValueError("out holds %d elements; this call writes %d" % (out.numel(), need))
         return out
 
     def u32(self, n: int, first: int = 0, count: int | None = None, out: torch.Tensor | None = None,

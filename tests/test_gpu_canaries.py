@@ -99,3 +99,24 @@ def test_batch_guard_bands_and_determinism():
         assert b.error_flag() == 0
         hashes.append(_check_guards(buf, words))
     assert hashes[0] == hashes[1]
+
+
+@pytest.mark.gpu
+def test_caller_output_checked_before_launch():
+    # A caller's output tensor that the call would overrun, or that the
+    # kernels cannot address linearly, is refused before anything is launched.
+    gs = XorgensStreams(8, seed=5)
+    dev = gs.device
+    with pytest.raises(ValueError, match="holds"):
+        gs.u32(64, first=0, count=4, out=torch.empty(4 * 64 - 1, dtype=torch.int32, device=dev))
+    with pytest.raises(ValueError, match="contiguous"):
+        gs.f32(64, first=0, count=4, out=torch.empty(64, 8, dtype=torch.float32, device=dev).t())
+    with pytest.raises(ValueError, match="byte"):
+        gs.normal(64, first=0, count=4, out=torch.empty(4, 64, dtype=torch.float64, device=dev))
+    with pytest.raises(ValueError, match="GPU"):
+        gs.fill_u32(64, first=0, count=4, out=torch.empty(4 * 64, dtype=torch.int32))
+    with pytest.raises(ValueError, match="out_elems"):
+        Batch(gs, [(0, 100, 0, 0)], 100, out=torch.empty(99, dtype=torch.int32, device=dev))
+    # Nothing ran: the states are those of a fresh generator.
+    ref = XorgensStreams(8, seed=5)
+    assert torch.equal(gs.u32(64), ref.u32(64))
