@@ -354,7 +354,18 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
     l.d_work = reinterpret_cast<uint32_t *>(lb + tl.reqs + tl.groups);
     l.d_stage = tl.stage ? reinterpret_cast<uint32_t *>(lb + tl.reqs + tl.groups + tl.work) : nullptr;
     l.h_scratch = new (std::nothrow) xg_request[cfg->max_batch];
-    if (!l.h_scratch || hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
+    bool reserved = l.h_scratch != nullptr;
+    try {
+      if (reserved) l.reqs.reserve(cfg->max_batch);
+    } catch (const std::bad_alloc &) {
+      reserved = false;
+    }
+    if (!reserved) {
+      destroy_lanes(s);
+      delete s;
+      return XG_ENOMEM;
+    }
+    if (hipStreamCreateWithFlags(&l.stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&l.done, hipEventDisableTiming) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void **>(&l.h_reqs), (size_t)cfg->max_batch * sizeof(xg_request),
                       hipHostMallocDefault) != hipSuccess ||
@@ -364,7 +375,6 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
       delete s;
       return XG_EHIP;
     }
-    l.reqs.reserve(cfg->max_batch);
   }
   *out = s;
   return XG_OK;
