@@ -29,10 +29,14 @@ class Batch:
         dev = streams.device
         self.d_reqs = torch.from_numpy(raw).to(dev)
         self.d_groups = torch.from_numpy(np.array(groups, dtype=np.uint32).view(np.int32)).to(dev)
-        if out is not None and (not out.is_cuda or not out.is_contiguous() or out.element_size() != 4
+        # Elements are the member's word width: 8 bytes for the 64-bit member, else 4.
+        width = 8 if streams.family == xg.XG_FAMILY_R64_W64 else 4
+        if out is not None and (not out.is_cuda or not out.is_contiguous() or out.element_size() != width
                                 or out.numel() < self.out_elems):
-            raise ValueError("out must be a contiguous GPU tensor of at least out_elems 4-byte elements")
-        self.out = out if out is not None else torch.empty(max(1, self.out_elems), dtype=torch.int32, device=dev)
+            raise ValueError("out must be a contiguous GPU tensor of at least out_elems %d-byte elements" % width)
+        if out is None:
+            out = torch.empty(max(1, self.out_elems), dtype=torch.int64 if width == 8 else torch.int32, device=dev)
+        self.out = out
         self.work = torch.zeros(xg.xg_batch_workspace_bytes() // 4, dtype=torch.int32, device=dev)
 
     def requests_in_order(self):

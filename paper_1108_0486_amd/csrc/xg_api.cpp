@@ -12,6 +12,7 @@
 
 #include "xg.h"
 #include "xg_internal.h"
+#include "xg_fam_batch.h"
 
 namespace {
 
@@ -374,16 +375,25 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
                             const uint32_t *d_groups, uint32_t num_groups, void *d_out,
                             uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream) {
   if (!ctx || !d_reqs || !d_groups || !d_out || !d_work) return XG_EINVAL;
-  if (!paper_member(ctx)) return XG_ENOTSUP;
+  const bool member = !paper_member(ctx);
+  if (member && ctx->family != XG_FAMILY_R64_W32 && ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
   if (num_groups > num_reqs) return XG_ERANGE;
+  const uintptr_t out_align = ctx->family == XG_FAMILY_R64_W64 ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_groups) % 4 ||
-      reinterpret_cast<uintptr_t>(d_out) % 4 || reinterpret_cast<uintptr_t>(d_work) % 4)
+      reinterpret_cast<uintptr_t>(d_out) % out_align || reinterpret_cast<uintptr_t>(d_work) % 4)
     return XG_EALIGN;
   xg::Shape shape = xg::kDefaultBatch;
   if (tune && !tune_to_shape(tune, tune->blocks_per_cu, &shape)) return XG_EINVAL;
   xg_status st = check_ctx_device(ctx);
   if (st != XG_OK) return st;
   if (num_groups == 0) return XG_OK;
+  if (member) {
+    const hipError_t e = xg::launch_family_batch(ctx->family, shape, ctx->num_cus,
+                                                 reinterpret_cast<unsigned char *>(ctx->d_state), ctx->num_streams,
+                                                 d_reqs, num_reqs, d_groups, num_groups, d_out, out_elems,
+                                                 static_cast<uint32_t *>(d_work), static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? XG_OK : XG_EHIP;
+  }
   const hipError_t e = xg::launch_batch(shape, ctx->num_cus, ctx->d_state, ctx->num_streams, d_reqs,
                                         num_reqs, d_groups, num_groups,
                                         static_cast<uint32_t *>(d_out), out_elems,
@@ -400,10 +410,11 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
                             xg_tune *best, float *times_ms, uint32_t max_times,
                             uint32_t *num_times, void *stream) {
   if (!ctx || !best || !d_scratch_state || reps < 1 || reps > kMaxReps) return XG_EINVAL;
-  if (!paper_member(ctx)) return XG_ENOTSUP;
+  const bool member = !paper_member(ctx);
+  if (member && ctx->family != XG_FAMILY_R64_W32 && ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
   if (num_times) *num_times = 0;
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  const size_t state_bytes = xg_state_bytes(ctx->num_streams);
+  const size_t state_bytes = xg_family_state_bytes(ctx->family, ctx->num_streams);
   xg_ctx scratch = *ctx;
   scratch.d_state = static_cast<uint32_t *>(d_scratch_state);
   if (reinterpret_cast<uintptr_t>(d_scratch_state) % 16) return XG_EALIGN;
@@ -425,7 +436,7 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
       for (uint32_t bpc : kBpc) {
         for (uint32_t sw : kStoreWords) {
           if (wpb * bpc > 32) continue;  // more waves than a compute unit holds
-          if (sw == 4 && un < 4) continue;
+          if (sw == 4 && (un < 4 || member)) continue;  // the members' batch kernel has no wide stores
           const xg_tune cand{wpb, un, bpc, sw};
           float ms[kMaxReps];
           int nms = 0;

@@ -1,0 +1,22 @@
+// Launcher of the batched kernel for the further family members
+// (xg_family.hip), used by xg_generate_batch.  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "xg.h"
+#include "xg_internal.h"
+
+namespace xg {
+
+// Clears the 256-byte workspace, then serves the planned table (num_groups
+// groups of reqs) with blocks_per_cu x CUs persistent workgroups of
+// waves_per_block wavefronts, two groups per wavefront; shape.store_words is
+// not used.  out holds out_elems elements of the member's word width.
+hipError_t launch_family_batch(uint32_t family, const Shape &shape, int num_cus, unsigned char *state,
+                               uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
+                               const uint32_t *groups, uint32_t num_groups, void *out, uint64_t out_elems,
+                               uint32_t *work, hipStream_t stream);
+
+}  // namespace xg

@@ -28,6 +28,7 @@
 #include "xg_device.h"
 #include "xg_normal.h"
 #include "xg_internal.h"
+#include "xg_fam_batch.h"
 
 namespace xg {
 namespace {
@@ -190,19 +191,17 @@ __global__ __launch_bounds__(256) void k_fam_init(unsigned char *__restrict__ st
   store_state<M>(state + L.k * M::state_bytes, L, g.prev, g.cur, word(0), 0u, w0 + word(256) * M::omega, 0ull);
 }
 
-// n words of each of `count` streams (launch index k = stream first + k).
-// FILL = false: stream-major, out[k n + t].  FILL = true: chunk c (words
-// 32c .. 32c + 31) of stream k at out[(c count + k) 32 ..], the ragged last
-// chunks (rem = n mod 32 words each) packed after them at
-// out[32 (n / 32) count + k rem ..]; a wavefront's step then writes 64
-// adjacent words.  CHECK: the wavefront's second stream is absent (odd count,
-// last pair), so that half's loads and stores are masked.
-template <class M, uint32_t KIND, int UNROLL, bool FILL, bool CHECK>
-__device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, const Lanes &L, uint64_t first,
-                                          uint64_t count, uint64_t n, typename M::word *__restrict__ out) {
+// n words of one stream per half-wavefront from its state at st: the full
+// steps go to o, o + stride, ... (o already offset to word j of the step),
+// the ragged last step (rem = n mod 32 words) to tail + j, or after the full
+// steps when tail is NULL.  on = false masks this lane's loads and stores
+// (that half's stream is absent); n is wave-uniform.
+template <class M, uint32_t KIND, int UNROLL>
+__device__ __forceinline__ void fam_run(unsigned char *__restrict__ st, bool on, Lanes L, uint64_t n,
+                                        typename M::word *__restrict__ o, uint64_t stride,
+                                        typename M::word *__restrict__ tail) {
   using word = typename M::word;
-  const bool on = !CHECK || L.active;
-  unsigned char *st = state + (first + L.k) * M::state_bytes;
+  L.active = on;
   const word *ring = reinterpret_cast<const word *>(st);
   word prev = 0, cur = 0, w_start = 0;
   uint64_t pos = 0;
@@ -219,8 +218,6 @@ __device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, con
   word wbase = w_start;
   const uint64_t nfull = n / kStep;
   const uint32_t rem = (uint32_t)(n % kStep);
-  const uint64_t stride = FILL ? count * kStep : kStep;
-  word *o = FILL ? out + L.k * kStep + L.j : out + L.k * n + L.j;
   const uint64_t nouter = nfull / UNROLL;
   for (uint64_t it = 0; it != nouter; ++it) {
 #pragma unroll
@@ -244,10 +241,31 @@ __device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, con
   if (rem) {  // wave-uniform
     x = g.step(word0);
     const word w = wbase + wlane;
-    word *tail = FILL ? out + nfull * count * kStep + L.k * rem + L.j : o;
-    if (on && L.j < rem) __builtin_nontemporal_store(map_out<M, KIND>(x + (word)(w ^ (w >> M::gamma))), tail);
+    word *t = tail ? tail : o;
+    if (on && L.j < rem) __builtin_nontemporal_store(map_out<M, KIND>(x + (word)(w ^ (w >> M::gamma))), t);
   }
   store_state<M>(st, L, p0, c0, x, rem, w_start + (word)n * M::omega, pos + n);
+}
+
+// n words of each of `count` streams (launch index k = stream first + k).
+// FILL = false: stream-major, out[k n + t].  FILL = true: chunk c (words
+// 32c .. 32c + 31) of stream k at out[(c count + k) 32 ..], the ragged last
+// chunks (rem = n mod 32 words each) packed after them at
+// out[32 (n / 32) count + k rem ..]; a wavefront's step then writes 64
+// adjacent words.  CHECK: the wavefront's second stream is absent (odd count,
+// last pair), so that half's loads and stores are masked.
+template <class M, uint32_t KIND, int UNROLL, bool FILL, bool CHECK>
+__device__ __forceinline__ void fam_serve(unsigned char *__restrict__ state, const Lanes &L, uint64_t first,
+                                          uint64_t count, uint64_t n, typename M::word *__restrict__ out) {
+  using word = typename M::word;
+  const bool on = !CHECK || L.active;
+  unsigned char *st = state + (first + L.k) * M::state_bytes;
+  if constexpr (FILL) {
+    word *tail = out + (n / kStep) * count * kStep + L.k * (n % kStep) + L.j;
+    fam_run<M, KIND, UNROLL>(st, on, L, n, out + L.k * kStep + L.j, count * kStep, tail);
+  } else {
+    fam_run<M, KIND, UNROLL>(st, on, L, n, out + L.k * n + L.j, kStep, nullptr);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -475,6 +493,117 @@ __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict
 }
 
 // ---------------------------------------------------------------------------
+// Batched requests (the persistent launch of xg_generate_batch) for these
+// members.  A wavefront serves two request groups at once, one per
+// half-wavefront (lanes 2j + h serve group 2p + h of pair p, taken from the
+// atomic queue work[0]).  Each loop trip runs min(words left in the two
+// current requests) through fam_run, with the state written back between
+// trips, so both halves step together; a half whose group is done, or whose
+// current request has the other output type, is masked for that trip (half
+// 0 goes first).  Requests are uint32 / uint64 (XG_U32) or FP32 / FP64
+// (XG_F32) of the member's word width, in elements of that width; a request
+// or group that fails the bounds check (stream, dtype, flags 0, output range,
+// group offsets) is skipped and sets work[1].  Every wavefront exits once the
+// queue passes num_groups.
+// ---------------------------------------------------------------------------
+__global__ void k_fam_clear_work(uint32_t *work) {
+  if (threadIdx.x < 64) work[threadIdx.x] = 0u;
+}
+
+// Lane src's value of v, held in scalar registers.
+__device__ __forceinline__ uint64_t lane_value(uint64_t v, int src) {
+  const uint64_t x = shfl_word(v, src);
+  return ((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(x >> 32)) << 32) |
+         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+}
+
+template <class M, int UNROLL>
+__global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ state, uint64_t num_streams,
+                                                    const xg_request *__restrict__ reqs, uint32_t num_reqs,
+                                                    const uint32_t *__restrict__ groups, uint32_t num_groups,
+                                                    void *__restrict__ out_v, uint64_t out_elems,
+                                                    uint32_t *__restrict__ work) {
+  using word = typename M::word;
+  constexpr uint32_t kInt = sizeof(word) == 4 ? kU32 : kU64;
+  constexpr uint32_t kReal = sizeof(word) == 4 ? kF32 : kF64;
+  word *out = reinterpret_cast<word *>(out_v);
+  Lanes L;
+  L.lane = threadIdx.x & 63u;
+  L.h = L.lane & 1u;
+  L.j = L.lane >> 1;
+  L.k = 0;
+  L.active = true;
+  for (;;) {
+    uint32_t p = 0;
+    if (L.lane == 0) p = atomicAdd(&work[0], 1u);
+    p = (uint32_t)__builtin_amdgcn_readfirstlane((int)p);
+    if (2ull * p >= num_groups) break;
+    const uint64_t g = 2ull * p + L.h;
+    uint32_t r = 0, r_end = 0;
+    if (g < num_groups) {
+      r = groups[g];
+      r_end = groups[g + 1];
+      if (r > r_end || r_end > num_reqs) {
+        if (L.j == 0) atomicOr(&work[1], 1u);
+        r = r_end = 0;
+      }
+    }
+    uint64_t done = 0;  // words of the half's current request already written
+    for (;;) {
+      // Each half moves past bad and empty requests (no cross-lane work here).
+      xg_request q{};
+      bool have = false;
+      while (r < r_end) {
+        q = reqs[r];
+        const bool ok = q.stream < num_streams && q.dtype <= XG_F32 && q.flags == 0u &&
+                        q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
+        if (ok && q.n > done) {
+          have = true;
+          break;
+        }
+        if (!ok && L.j == 0) atomicOr(&work[1], 1u);
+        ++r;
+        done = 0;
+      }
+      const uint64_t left = have ? q.n - done : 0;
+      const uint64_t left0 = lane_value(left, 0), left1 = lane_value(left, 1);
+      if (left0 == 0 && left1 == 0) break;
+      const uint32_t dt0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 0));
+      const uint32_t dt1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 1));
+      const bool run0 = left0 != 0;
+      const bool run1 = left1 != 0 && (!run0 || dt0 == dt1);
+      const uint64_t n = run0 ? (run1 && left1 < left0 ? left1 : left0) : left1;
+      const bool mine = L.h ? run1 : run0;
+      unsigned char *st = state + (mine ? q.stream : 0) * M::state_bytes;
+      word *o = out + (mine ? q.out_offset + done : 0) + L.j;
+      if ((run0 ? dt0 : dt1) == XG_F32)
+        fam_run<M, kReal, UNROLL>(st, mine, L, n, o, kStep, nullptr);
+      else
+        fam_run<M, kInt, UNROLL>(st, mine, L, n, o, kStep, nullptr);
+      if (mine) {
+        done += n;
+        if (done == q.n) {
+          ++r;
+          done = 0;
+        }
+      }
+    }
+  }
+}
+
+template <class M>
+void launch_fam_batch_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t num_streams,
+                        const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups, uint32_t num_groups,
+                        void *out, uint64_t out_elems, uint32_t *work, hipStream_t stream) {
+  switch (unroll) {
+    case 1: hipLaunchKernelGGL((k_fam_batch<M, 1>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 2: hipLaunchKernelGGL((k_fam_batch<M, 2>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 4: hipLaunchKernelGGL((k_fam_batch<M, 4>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    default: hipLaunchKernelGGL((k_fam_batch<M, 8>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // skip: advance each stream by J words without producing them.
 //
 // JUMP = false: the x-part steps through the J words (J small).
@@ -645,6 +774,28 @@ hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const S
     launch_fam_layout<MemberW64, kF64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
   else
     return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_family_batch(uint32_t family, const Shape &shape, int num_cus, unsigned char *state,
+                               uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
+                               const uint32_t *groups, uint32_t num_groups, void *out, uint64_t out_elems,
+                               uint32_t *work, hipStream_t stream) {
+  if (family != XG_FAMILY_R64_W32 && family != XG_FAMILY_R64_W64) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_fam_clear_work, dim3(1), dim3(64), 0, stream, work);
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const uint64_t pairs = ((uint64_t)num_groups + 1) / 2;
+  uint64_t blocks = (uint64_t)(num_cus > 0 ? num_cus : 1) * shape.blocks_per_cu;
+  const uint64_t need = (pairs + shape.waves_per_block - 1) / shape.waves_per_block;
+  if (need < blocks) blocks = need ? need : 1;
+  const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  if (family == XG_FAMILY_R64_W32)
+    launch_fam_batch_k<MemberN2048>(shape.unroll, grid, block, state, num_streams, reqs, num_reqs, groups,
+                                    num_groups, out, out_elems, work, stream);
+  else
+    launch_fam_batch_k<MemberW64>(shape.unroll, grid, block, state, num_streams, reqs, num_reqs, groups,
+                                  num_groups, out, out_elems, work, stream);
   return hipGetLastError();
 }
 

@@ -76,7 +76,7 @@ class XorgensStreams:
         need = 1
         for d in shape:
             need *= int(d)
-        width = torch.empty((), dtype=dtype).element_size()
+        width = dtype.itemsize
         if not out.is_cuda:
             raise ValueError("out must be a GPU tensor")
         if not out.is_contiguous():

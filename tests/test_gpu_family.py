@@ -153,10 +153,6 @@ def test_family_unsupported_calls_are_rejected(fam):
         with pytest.raises(xg.XgError) as e:
             c()
         assert e.value.status == xg.XG_ENOTSUP
-    work = torch.zeros(64, dtype=torch.int32, device="cuda")
-    with pytest.raises(xg.XgError) as e:
-        xg.xg_generate_batch(gs.ctx, p, 1, p, 1, p, 8, None, work.data_ptr())
-    assert e.value.status == xg.XG_ENOTSUP
     from paper_1108_0486_amd.serve import Server
     with pytest.raises(xg.XgError) as e:
         Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4)

@@ -1,0 +1,164 @@
+"""The persistent batched launch for the two further members: two request
+groups per wavefront (one per half), identical bits to the oracle, after
+graph replays and under every launch shape, with bad and empty requests
+skipped."""
+import numpy as np
+import pytest
+
+from gpu_helpers import needs_gpu
+from oracle import oracle as O
+
+pytestmark = [pytest.mark.gpu, needs_gpu]
+
+torch = pytest.importorskip("torch")
+
+from paper_1108_0486_amd import xg  # noqa: E402
+from paper_1108_0486_amd.batch import Batch  # noqa: E402
+from paper_1108_0486_amd.streams import XorgensStreams  # noqa: E402
+
+R64W32, R64W64 = xg.XG_FAMILY_R64_W32, xg.XG_FAMILY_R64_W64
+FAMILIES = [R64W32, R64W64]
+PARAMS = {R64W32: O.R64, R64W64: O.W64}
+
+
+def _oracle(fam, seed, count):
+    p = PARAMS[fam]
+    if fam == R64W64:
+        return O.OracleStreams64(seed, count, p)
+    return O.OracleStreams(seed, count, params=p)
+
+
+def _one(fam, ref, s):
+    if fam == R64W64:
+        return O.OracleStreams64.from_state(ref.ring[[s]], ref.weyl[[s]], ref.pos[[s]], ref.params)
+    return ref.subset([s])
+
+
+def _oracle_serve(fam, ref, reqs):
+    """Serves the requests in the given order on the oracle (each stream's
+    requests in that order); returns the expected words of each."""
+    want = []
+    for s, n, off, dt in reqs:
+        one = _one(fam, ref, s)
+        if fam == R64W64:
+            v = one.u64(n)[0] if dt == 0 else one.f64(n)[0].view(np.uint64)
+        else:
+            v = one.u32(n)[0] if dt == 0 else one.f32(n)[0].view(np.uint32)
+        ref.ring[s], ref.weyl[s], ref.pos[s] = one.ring[0], one.weyl[0], one.pos[0]
+        want.append(np.asarray(v))
+    return want
+
+
+def _requests(rng, num_streams, num_reqs, max_n, mixed=True):
+    reqs, off = [], 0
+    for i in range(num_reqs):
+        s = int(rng.integers(0, num_streams)) if i % 4 else 3
+        n = int(rng.integers(0, max_n))
+        dt = int(rng.integers(0, 2)) if mixed else 0
+        reqs.append((s, n, off, dt))
+        off += n + int(rng.integers(0, 3))
+    return reqs, off
+
+
+def _check(fam, out, reqs, want):
+    words = out.cpu().numpy().view(np.uint64 if fam == R64W64 else np.uint32)
+    for (s, n, off, dt), w in zip(reqs, want):
+        if n:
+            assert (words[off:off + n] == w).all(), (s, n, off, dt)
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+@pytest.mark.parametrize("tune", [None, (1, 1, 1), (2, 2, 4), (4, 4, 8), (16, 8, 2), (1, 8, 32)])
+def test_member_batch_matches_oracle(fam, tune):
+    rng = np.random.default_rng(17)
+    S = 37
+    reqs, out_elems = _requests(rng, S, 120, 3000)
+    gs = XorgensStreams(S, seed=9, family=fam)
+    b = Batch(gs, reqs, out_elems)
+    b.run(tune=None if tune is None else (tune[0], tune[1], tune[2], 1))
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    # Served order: the planner's (groups by stream, arrival order inside).
+    ref = _oracle(fam, 9, S)
+    want = _oracle_serve(fam, ref, b.requests_in_order())
+    _check(fam, b.out, b.requests_in_order(), want)
+    # End states equal the oracle's after every request.
+    ring, weyl, pos = gs.host_state()
+    assert (ring == ref.ring).all() and (weyl == ref.weyl).all() and (pos == ref.pos).all()
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+def test_member_batch_equals_plain_launches(fam):
+    # One request per stream of equal length: the same words as one plain
+    # stream-major launch over all streams.
+    S, n = 64, 4133
+    reqs = [(i, n, i * n, 0) for i in range(S)]
+    a = XorgensStreams(S, seed=4, family=fam)
+    b = XorgensStreams(S, seed=4, family=fam)
+    bt = Batch(a, reqs, S * n)
+    bt.run()
+    plain = b.u64(n) if fam == R64W64 else b.u32(n)
+    torch.cuda.synchronize()
+    assert bt.error_flag() == 0
+    assert torch.equal(bt.out.view(plain.dtype).view(S, n), plain)
+    assert torch.equal(a.state, b.state)
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+def test_member_batch_graph_replay(fam):
+    rng = np.random.default_rng(5)
+    S = 21
+    reqs, out_elems = _requests(rng, S, 40, 2000)
+    gs = XorgensStreams(S, seed=13, family=fam)
+    b = Batch(gs, reqs, out_elems)
+    g = b.capture_graph()
+    ref = _oracle(fam, 13, S)
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        assert b.error_flag() == 0
+        want = _oracle_serve(fam, ref, b.requests_in_order())
+        _check(fam, b.out, b.requests_in_order(), want)
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+def test_member_batch_skips_bad_requests(fam):
+    # A normal request and a stream out of range are flagged and skipped; an
+    # empty request is skipped without a flag; the rest are served.
+    S = 6
+    gs = XorgensStreams(S, seed=2, family=fam)
+    good = [(0, 100, 0, 0), (1, 33, 100, 1), (2, 0, 133, 0), (0, 31, 133, 1)]
+    b = Batch(gs, good, 200)
+    raw = b.d_reqs.cpu().numpy().copy().view(np.uint64).reshape(-1, 4)
+    ref = _oracle(fam, 2, S)
+    want = _oracle_serve(fam, ref, b.requests_in_order())
+    b.run()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    _check(fam, b.out, b.requests_in_order(), want)
+    # Now corrupt one request on the device: dtype NORMAL.
+    bad = raw.copy()
+    bad[0, 3] = (bad[0, 3] & ~np.uint64(0xFFFFFFFF)) | np.uint64(xg.XG_NORMAL)
+    b.d_reqs.copy_(torch.from_numpy(bad.view(np.int32).reshape(-1)))
+    b.run()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 1
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+def test_member_batch_autotune_keeps_state(fam):
+    rng = np.random.default_rng(8)
+    S = 40
+    reqs, out_elems = _requests(rng, S, 80, 4000, mixed=False)
+    gs = XorgensStreams(S, seed=21, family=fam)
+    before = gs.state.clone()
+    b = Batch(gs, reqs, out_elems)
+    best, times = b.autotune(reps=1)
+    torch.cuda.synchronize()
+    assert torch.equal(gs.state, before)
+    assert all(t[3] == 1 for t in times)  # store_words: no wide stores for these members
+    b.run(tune=best)
+    torch.cuda.synchronize()
+    ref = _oracle(fam, 21, S)
+    want = _oracle_serve(fam, ref, b.requests_in_order())
+    _check(fam, b.out, b.requests_in_order(), want)
