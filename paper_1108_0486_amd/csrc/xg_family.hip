@@ -500,12 +500,52 @@ __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict
 // current requests) through fam_run, with the state written back between
 // trips, so both halves step together; a half whose group is done, or whose
 // current request has the other output type, is masked for that trip (half
-// 0 goes first).  Requests are uint32 / uint64 (XG_U32) or FP32 / FP64
+// 0 goes first).  While a half's next word falls inside a 32-word line of the
+// output, a one-step head trip (fam_head) first brings each such half to its
+// line's end, so that full steps store whole aligned lines.  Requests are uint32 / uint64 (XG_U32) or FP32 / FP64
 // (XG_F32) of the member's word width, in elements of that width; a request
 // or group that fails the bounds check (stream, dtype, flags 0, output range,
 // group offsets) is skipped and sets work[1].  Every wavefront exits once the
 // queue passes num_groups.
 // ---------------------------------------------------------------------------
+// One generator step of the stream at st, of which this half writes the
+// first `head` words (head < 32, per half; 0 writes nothing and leaves the
+// state as it was) as integers or, if real, as uniform reals; the state then
+// stands `head` words further on.  Branch-free in head, so every lane takes
+// part in the shuffles.
+template <class M, uint32_t KINT, uint32_t KREAL>
+__device__ __forceinline__ void fam_head(unsigned char *__restrict__ st, bool on, const Lanes &L, uint32_t head,
+                                         bool real, typename M::word *__restrict__ o) {
+  using word = typename M::word;
+  word *ring = reinterpret_cast<word *>(st);
+  word prev = 0, cur = 0, w_start = 0;
+  uint64_t pos = 0;
+  if (on) {
+    prev = ring[L.j];
+    cur = ring[32 + L.j];
+    w_start = *reinterpret_cast<const word *>(st + M::weyl_off);
+    pos = *reinterpret_cast<const uint64_t *>(st + M::pos_off);
+  }
+  Ring2<M> g;
+  g.open(prev, cur);
+  const word x = g.step(L.j == 0);
+  const word w = w_start + word(L.j + 1u) * M::omega;
+  const word v = x + (word)(w ^ (w >> M::gamma));
+  if (on && L.j < head) __builtin_nontemporal_store(real ? map_out<M, KREAL>(v) : map_out<M, KINT>(v), o);
+  // The new ring: the 64-word window ending `head` words into x.
+  const uint32_t js = (head + L.j) & 31u;
+  const int src = (int)(2 * js + L.h);
+  const word a = shfl_word(prev, src), b = shfl_word(cur, src), c = shfl_word(x, src);
+  const bool wrap = head + L.j >= 32u;
+  if (!on) return;
+  ring[L.j] = wrap ? b : a;
+  ring[32 + L.j] = wrap ? c : b;
+  if (L.j == 0) {
+    *reinterpret_cast<word *>(st + M::weyl_off) = w_start + (word)head * M::omega;
+    *reinterpret_cast<uint64_t *>(st + M::pos_off) = pos + head;
+  }
+}
+
 __global__ void k_fam_clear_work(uint32_t *work) {
   if (threadIdx.x < 64) work[threadIdx.x] = 0u;
 }
@@ -568,6 +608,30 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
       const uint64_t left = have ? q.n - done : 0;
       const uint64_t left0 = lane_value(left, 0), left1 = lane_value(left, 1);
       if (left0 == 0 && left1 == 0) break;
+      // Position of the half's next word within a 32-word line of the output.
+      const uint32_t mis =
+          have ? (uint32_t)((reinterpret_cast<uintptr_t>(out) / sizeof(word) + q.out_offset + done) % kStep) : 0u;
+      const uint32_t mis0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 0));
+      const uint32_t mis1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 1));
+      if (mis0 != 0u || mis1 != 0u) {
+        // Head trip: one step, in which each half that starts inside a line
+        // writes only up to that line's end, so its later full steps store
+        // whole aligned lines (dense request offsets start most requests
+        // inside a line, which measured twice as slow).
+        const uint32_t head = mis != 0u ? (uint32_t)(left < kStep - mis ? left : kStep - mis) : 0u;
+        const bool mine = head != 0u;
+        unsigned char *st = state + (mine ? q.stream : 0) * M::state_bytes;
+        word *o = out + (mine ? q.out_offset + done : 0) + L.j;
+        fam_head<M, kInt, kReal>(st, mine, L, head, q.dtype == XG_F32, o);
+        if (mine) {
+          done += head;
+          if (done == q.n) {
+            ++r;
+            done = 0;
+          }
+        }
+        continue;
+      }
       const uint32_t dt0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 0));
       const uint32_t dt1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 1));
       const bool run0 = left0 != 0;
