@@ -239,6 +239,41 @@ def extra_fused_moments(torch, dev):
             "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3)}
 
 
+def _member_ragged_batch(torch, dev, fam):
+    """The ragged workload (65536 streams, uint32, CSR offsets) served by one
+    persistent launch of a further member's batch kernel, autotuned, replayed
+    in a HIP graph."""
+    from paper_1108_0486_amd import workloads as W
+    from paper_1108_0486_amd.batch import Batch
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    lengths = W.ragged_lengths()
+    off = W.csr_offsets(lengths)
+    total = int(off[-1])
+    S = len(lengths)
+    gs = XorgensStreams(S, seed=SEED, device=dev, family=fam)
+    b = Batch(gs, [(i, int(lengths[i]), int(off[i]), 0) for i in range(S)], total)
+    best, recs = b.autotune(reps=1)
+    g = b.capture_graph(tune=best)
+    g.replay()
+    torch.cuda.synchronize()
+    reps = 5
+    a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        g.replay()
+    e.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(e) / reps
+    res = {"total_rn": total, "batched_graph_ms": ms, "batched_rn_per_s": total / (ms * 1e-3),
+           "batched_frac_of_hbm_peak": 4 * total / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+           "autotuned_shape": {"waves_per_block": best[0], "unroll": best[1], "blocks_per_cu": best[2]},
+           "error_flag": b.error_flag()}
+    del b, g, gs
+    torch.cuda.empty_cache()
+    return res
+
+
 def extra_family_members(torch, dev):
     """The two further members (r = 64, s = 33; two streams per wavefront):
     4 GiB per launch in the bulk-fill layout and stream-major, per output
@@ -281,6 +316,7 @@ def extra_family_members(torch, dev):
             del out, gs
             torch.cuda.empty_cache()
         res[name] = rec
+    res["r64_w32 (n=2048) ragged batch"] = _member_ragged_batch(torch, dev, xg.XG_FAMILY_R64_W32)
     # the 32-bit member's fused normal moments on the fused workload's shape
     S, n = 4096, 1 << 18
     gs = XorgensStreams(S, seed=SEED, device=dev, family=xg.XG_FAMILY_R64_W32)
