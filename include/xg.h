@@ -84,12 +84,12 @@ typedef int32_t xg_status;
  *   XG_FAMILY_R64_W32   w = 32, (64,33,19,19,9,18); n = 2048, a 272-byte
  *                       state.  Plain and bulk-fill u32 / f32, normals and
  *                       fused moments (as for Section 2's member), xg_skip,
- *                       and batches of u32 / f32 requests.
+ *                       and batches.
  *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
  *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), FP64
  *                       normals and their fused moments
  *                       (xg_generate_normal_f64, xg_normal_moments_f64),
- *                       xg_skip, and batches of u64 / f64 requests.
+ *                       xg_skip, and batches (u64 / f64 / FP64 normals).
  * The paper gives shifts only for the first; those of the other two were
  * chosen by a search for primitive characteristic polynomials.  Calls a
  * member does not support return XG_ENOTSUP. */
@@ -349,12 +349,13 @@ xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t nu
  * output range, group offsets) is skipped and sets the error word
  * (((uint32_t *)d_work)[1]) to 1; every wavefront still reaches the exit.
  * The further members (XG_FAMILY_R64_W32, XG_FAMILY_R64_W64) take the same
- * table: dtype XG_U32 gives the member's unsigned words (uint32 / uint64) and
- * XG_F32 its uniform reals (FP32 / FP64, as xg_generate_f32 / xg_generate_f64);
- * XG_NORMAL requests are skipped and set the error word.  One wavefront serves
- * two groups, one per half, stepping through both current requests together
- * (a half waits while its request has the other dtype); store_words of tune is
- * not used, and d_out must be 8-byte aligned for the 64-bit member.
+ * table: dtype XG_U32 gives the member's unsigned words (uint32 / uint64),
+ * XG_F32 its uniform reals (FP32 / FP64, as xg_generate_f32 / xg_generate_f64)
+ * and XG_NORMAL its normals (FP32 as xg_generate_normal / FP64 as
+ * xg_generate_normal_f64), each in elements of the word width.  One wavefront
+ * serves two groups, one per half, stepping through both current requests
+ * together (a half waits while its request has another dtype); store_words of
+ * tune is not used, and d_out must be 8-byte aligned for the 64-bit member.
  * Errors: XG_EINVAL, XG_ERANGE, XG_EALIGN, XG_EHIP. */
 xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
                             const uint32_t *d_groups, uint32_t num_groups, void *d_out,

@@ -372,19 +372,21 @@ __device__ __forceinline__ void fam_consume_pair(uint32_t e, uint32_t o, uint64_
 // n normals of each of `count` streams (launch index k = stream first + k)
 // at out[k n + t], or their sums at sums[2k], sums[2k + 1].  Consumes
 // 2 ceil(n / 2) words per stream.
+// n normals of the stream at st per half-wavefront (n wave-uniform), from
+// 2 ceil(n / 2) words: Box-Muller on consecutive pairs, written from o_s
+// (the stream's first output) unless MOMENTS, which instead reduces the
+// half's sums of z and z^2 and stores them at sums (two reals).  on = false
+// masks this lane's loads and stores.
 template <class M, bool MOMENTS>
-__global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict__ state, uint64_t first,
-                                                      uint64_t count, uint64_t n, void *__restrict__ out_v,
-                                                      void *__restrict__ sums_v) {
+__device__ __forceinline__ void fam_normals_run(unsigned char *__restrict__ st, bool on, Lanes L, uint64_t n,
+                                                typename std::conditional<sizeof(typename M::word) == 8, double,
+                                                                          float>::type *__restrict__ o_s,
+                                                typename std::conditional<sizeof(typename M::word) == 8, double,
+                                                                          float>::type *__restrict__ sums) {
   using word = typename M::word;
   constexpr bool kW64 = sizeof(word) == 8;
   using real = typename std::conditional<kW64, double, float>::type;
-  real *out = static_cast<real *>(out_v);
-  real *sums = static_cast<real *>(sums_v);
-  const Lanes L = lanes_of(count, xcd_block());
-  if (2 * (L.k >> 1) >= count) return;  // wave-uniform
-  const bool on = L.active;
-  unsigned char *st = state + (first + L.k) * M::state_bytes;
+  L.active = on;
   word prev = 0, cur = 0, w_start = 0;
   uint64_t pos = 0;
   if (on) {
@@ -409,9 +411,8 @@ __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict_
   const uint64_t nblk = words >> 6;  // 64-word blocks: 32 pairs of each stream
   const uint32_t rw = (uint32_t)(words & 63u);
   const uint32_t m = L.j;
-  real *o_s = MOMENTS ? nullptr : out + L.k * n;
   const bool pair_aligned =
-      !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(out) & (2 * sizeof(real) - 1)) == 0;
+      !MOMENTS && (n & 1u) == 0 && (reinterpret_cast<uintptr_t>(o_s) & (2 * sizeof(real) - 1)) == 0;
   dev::Moments mo{0.0f, 0.0f, 0.0f, 0.0f, -0.0f, -0.0f};
   MomentsF64 md{0.0, 0.0, 0.0, 0.0};
   auto consume = [&](word e, word o, uint64_t idx) {
@@ -470,10 +471,24 @@ __global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict_
       v2 += __shfl_xor(v2, off);
     }
     if (on && L.j == 0) {
-      sums[2 * L.k] = (real)v1;
-      sums[2 * L.k + 1] = (real)v2;
+      sums[0] = (real)v1;
+      sums[1] = (real)v2;
     }
   }
+}
+
+template <class M, bool MOMENTS>
+__global__ __launch_bounds__(1024) void k_fam_normals(unsigned char *__restrict__ state, uint64_t first,
+                                                      uint64_t count, uint64_t n, void *__restrict__ out_v,
+                                                      void *__restrict__ sums_v) {
+  using word = typename M::word;
+  using real = typename std::conditional<sizeof(word) == 8, double, float>::type;
+  real *out = static_cast<real *>(out_v);
+  real *sums = static_cast<real *>(sums_v);
+  const Lanes L = lanes_of(count, xcd_block());
+  if (2 * (L.k >> 1) >= count) return;  // wave-uniform
+  fam_normals_run<M, MOMENTS>(state + (first + L.k) * M::state_bytes, L.active, L, n,
+                              MOMENTS ? nullptr : out + L.k * n, MOMENTS ? sums + 2 * L.k : nullptr);
 }
 
 template <class M, uint32_t KIND, int UNROLL, bool FILL>
@@ -502,11 +517,12 @@ __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict
 // current request has the other output type, is masked for that trip (half
 // 0 goes first).  While a half's next word falls inside a 32-word line of the
 // output, a one-step head trip (fam_head) first brings each such half to its
-// line's end, so that full steps store whole aligned lines.  Requests are uint32 / uint64 (XG_U32) or FP32 / FP64
-// (XG_F32) of the member's word width, in elements of that width; a request
-// or group that fails the bounds check (stream, dtype, flags 0, output range,
-// group offsets) is skipped and sets work[1].  Every wavefront exits once the
-// queue passes num_groups.
+// line's end, so that full steps store whole aligned lines.  Requests are
+// uint32 / uint64 (XG_U32), FP32 / FP64 (XG_F32) or normals of that precision
+// (XG_NORMAL), in elements of the member's word width; a request or group
+// that fails the bounds check (stream, dtype, flags 0, output range, group
+// offsets) is skipped and sets work[1].  Every wavefront exits once the queue
+// passes num_groups.
 // ---------------------------------------------------------------------------
 // One generator step of the stream at st, of which this half writes the
 // first `head` words (head < 32, per half; 0 writes nothing and leaves the
@@ -566,6 +582,7 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
   using word = typename M::word;
   constexpr uint32_t kInt = sizeof(word) == 4 ? kU32 : kU64;
   constexpr uint32_t kReal = sizeof(word) == 4 ? kF32 : kF64;
+  using real = typename std::conditional<sizeof(word) == 8, double, float>::type;
   word *out = reinterpret_cast<word *>(out_v);
   Lanes L;
   L.lane = threadIdx.x & 63u;
@@ -595,7 +612,7 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
       bool have = false;
       while (r < r_end) {
         q = reqs[r];
-        const bool ok = q.stream < num_streams && q.dtype <= XG_F32 && q.flags == 0u &&
+        const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u &&
                         q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
         if (ok && q.n > done) {
           have = true;
@@ -609,8 +626,10 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
       const uint64_t left0 = lane_value(left, 0), left1 = lane_value(left, 1);
       if (left0 == 0 && left1 == 0) break;
       // Position of the half's next word within a 32-word line of the output.
-      const uint32_t mis =
-          have ? (uint32_t)((reinterpret_cast<uintptr_t>(out) / sizeof(word) + q.out_offset + done) % kStep) : 0u;
+      // (Normals are written pair by pair and are not realigned.)
+      const uint32_t mis = have && q.dtype != XG_NORMAL
+                               ? (uint32_t)((reinterpret_cast<uintptr_t>(out) / sizeof(word) + q.out_offset + done) % kStep)
+                               : 0u;
       const uint32_t mis0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 0));
       const uint32_t mis1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 1));
       if (mis0 != 0u || mis1 != 0u) {
@@ -634,16 +653,32 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
       }
       const uint32_t dt0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 0));
       const uint32_t dt1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 1));
-      const bool run0 = left0 != 0;
-      const bool run1 = left1 != 0 && (!run0 || dt0 == dt1);
-      const uint64_t n = run0 ? (run1 && left1 < left0 ? left1 : left0) : left1;
+      bool run0 = left0 != 0;
+      bool run1 = left1 != 0 && (!run0 || dt0 == dt1);
+      uint64_t n = run0 ? (run1 && left1 < left0 ? left1 : left0) : left1;
+      const uint32_t kind = run0 ? dt0 : dt1;
+      if (kind == XG_NORMAL && (n & 1u)) {
+        // An odd count drops the second variate of its last pair, so only a
+        // half that finishes its request with this trip may take one.
+        const bool fin0 = run0 && left0 == n, fin1 = run1 && left1 == n;
+        if ((run0 && !fin0) || (run1 && !fin1)) {
+          if (n > 1) {
+            n -= 1;
+          } else {
+            run0 = fin0;
+            run1 = fin1;
+          }
+        }
+      }
       const bool mine = L.h ? run1 : run0;
       unsigned char *st = state + (mine ? q.stream : 0) * M::state_bytes;
-      word *o = out + (mine ? q.out_offset + done : 0) + L.j;
-      if ((run0 ? dt0 : dt1) == XG_F32)
-        fam_run<M, kReal, UNROLL>(st, mine, L, n, o, kStep, nullptr);
+      const uint64_t at = mine ? q.out_offset + done : 0;
+      if (kind == XG_NORMAL)
+        fam_normals_run<M, false>(st, mine, L, n, reinterpret_cast<real *>(out) + at, nullptr);
+      else if (kind == XG_F32)
+        fam_run<M, kReal, UNROLL>(st, mine, L, n, out + at + L.j, kStep, nullptr);
       else
-        fam_run<M, kInt, UNROLL>(st, mine, L, n, o, kStep, nullptr);
+        fam_run<M, kInt, UNROLL>(st, mine, L, n, out + at + L.j, kStep, nullptr);
       if (mine) {
         done += n;
         if (done == q.n) {

@@ -1,11 +1,11 @@
 """The persistent batched launch for the two further members: two request
-groups per wavefront (one per half), identical bits to the oracle, after
-graph replays and under every launch shape, with bad and empty requests
-skipped."""
+groups per wavefront (one per half), identical bits to the oracle for words
+and reals and normals within 4 ulp, after graph replays and under every
+launch shape, with bad and empty requests skipped."""
 import numpy as np
 import pytest
 
-from gpu_helpers import needs_gpu
+from gpu_helpers import needs_gpu, ulp32_error, ulp64_error
 from oracle import oracle as O
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -40,7 +40,9 @@ def _oracle_serve(fam, ref, reqs):
     want = []
     for s, n, off, dt in reqs:
         one = _one(fam, ref, s)
-        if fam == R64W64:
+        if dt == 2:
+            v = one.normal(n)[0]
+        elif fam == R64W64:
             v = one.u64(n)[0] if dt == 0 else one.f64(n)[0].view(np.uint64)
         else:
             v = one.u32(n)[0] if dt == 0 else one.f32(n)[0].view(np.uint32)
@@ -54,7 +56,7 @@ def _requests(rng, num_streams, num_reqs, max_n, mixed=True):
     for i in range(num_reqs):
         s = int(rng.integers(0, num_streams)) if i % 4 else 3
         n = int(rng.integers(0, max_n))
-        dt = int(rng.integers(0, 2)) if mixed else 0
+        dt = int(rng.integers(0, 3)) if mixed else 0
         reqs.append((s, n, off, dt))
         off += n + int(rng.integers(0, 3))
     return reqs, off
@@ -63,8 +65,14 @@ def _requests(rng, num_streams, num_reqs, max_n, mixed=True):
 def _check(fam, out, reqs, want):
     words = out.cpu().numpy().view(np.uint64 if fam == R64W64 else np.uint32)
     for (s, n, off, dt), w in zip(reqs, want):
-        if n:
-            assert (words[off:off + n] == w).all(), (s, n, off, dt)
+        if n == 0:
+            continue
+        got = words[off:off + n]
+        if dt == 2:  # normals: FP32 / FP64 against the oracle's higher precision
+            err = ulp64_error(got.view(np.float64), w) if fam == R64W64 else ulp32_error(got.view(np.float32), w)
+            assert err.max() <= 4.0, (s, n, off, dt)
+        else:
+            assert (got == w).all(), (s, n, off, dt)
 
 
 @pytest.mark.parametrize("fam", FAMILIES)
@@ -123,11 +131,11 @@ def test_member_batch_graph_replay(fam):
 
 @pytest.mark.parametrize("fam", FAMILIES)
 def test_member_batch_skips_bad_requests(fam):
-    # A normal request and a stream out of range are flagged and skipped; an
-    # empty request is skipped without a flag; the rest are served.
+    # An empty request is skipped without a flag; a request with an unknown
+    # dtype is flagged and skipped.
     S = 6
     gs = XorgensStreams(S, seed=2, family=fam)
-    good = [(0, 100, 0, 0), (1, 33, 100, 1), (2, 0, 133, 0), (0, 31, 133, 1)]
+    good = [(0, 100, 0, 0), (1, 33, 100, 1), (2, 0, 133, 0), (0, 31, 133, 2)]
     b = Batch(gs, good, 200)
     raw = b.d_reqs.cpu().numpy().copy().view(np.uint64).reshape(-1, 4)
     ref = _oracle(fam, 2, S)
@@ -136,9 +144,9 @@ def test_member_batch_skips_bad_requests(fam):
     torch.cuda.synchronize()
     assert b.error_flag() == 0
     _check(fam, b.out, b.requests_in_order(), want)
-    # Now corrupt one request on the device: dtype NORMAL.
+    # Now corrupt one request on the device: dtype 3 (no such type).
     bad = raw.copy()
-    bad[0, 3] = (bad[0, 3] & ~np.uint64(0xFFFFFFFF)) | np.uint64(xg.XG_NORMAL)
+    bad[0, 3] = (bad[0, 3] & ~np.uint64(0xFFFFFFFF)) | np.uint64(3)
     b.d_reqs.copy_(torch.from_numpy(bad.view(np.int32).reshape(-1)))
     b.run()
     torch.cuda.synchronize()
@@ -162,3 +170,23 @@ def test_member_batch_autotune_keeps_state(fam):
     ref = _oracle(fam, 21, S)
     want = _oracle_serve(fam, ref, b.requests_in_order())
     _check(fam, b.out, b.requests_in_order(), want)
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+def test_member_batch_odd_normal_pieces(fam):
+    # Two groups in one wavefront, both normals, with odd lengths that end
+    # inside the partner's request: the trips shorten to even counts, and a
+    # count of one runs only the half that finishes (the pair is kept whole).
+    S = 2
+    reqs = [(0, 5, 0, 2), (1, 10, 5, 2), (0, 3, 15, 2), (1, 7, 18, 0), (0, 1, 25, 2)]
+    gs = XorgensStreams(S, seed=77, family=fam)
+    b = Batch(gs, reqs, 26)
+    assert b.num_groups == 2
+    b.run()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    ref = _oracle(fam, 77, S)
+    want = _oracle_serve(fam, ref, b.requests_in_order())
+    _check(fam, b.out, b.requests_in_order(), want)
+    ring, weyl, pos = gs.host_state()
+    assert (ring == ref.ring).all() and (weyl == ref.weyl).all() and (pos == ref.pos).all()
