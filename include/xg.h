@@ -84,12 +84,13 @@ typedef int32_t xg_status;
  *   XG_FAMILY_R64_W32   w = 32, (64,33,19,19,9,18); n = 2048, a 272-byte
  *                       state.  Plain and bulk-fill u32 / f32, normals and
  *                       fused moments (as for Section 2's member), xg_skip,
- *                       and batches.
+ *                       batches, and a server without segments.
  *   XG_FAMILY_R64_W64   w = 64, (64,33,24,22,37,45); n = 4096, 64-bit outputs
  *                       (xg_generate_u64 / f64, xg_fill_u64 / f64), FP64
  *                       normals and their fused moments
  *                       (xg_generate_normal_f64, xg_normal_moments_f64),
- *                       xg_skip, and batches (u64 / f64 / FP64 normals).
+ *                       xg_skip, batches (u64 / f64 / FP64 normals), and a
+ *                       server without segments.
  * The paper gives shifts only for the first; those of the other two were
  * chosen by a search for primitive characteristic polynomials.  Calls a
  * member does not support return XG_ENOTSUP. */
@@ -429,15 +430,17 @@ typedef struct {
 /* Device bytes of request tables and workspaces a server needs. */
 size_t xg_server_device_bytes(const xg_server_config *cfg);
 
-/* Creates a server.  d_pool (pool_elems >= 64 4-byte elements, 256-byte
- * aligned) holds request outputs: the server hands out 64-element-aligned
+/* Creates a server.  d_pool (pool_elems >= 64 elements of the handle's word
+ * width, 4 or 8 bytes; 256-byte aligned) holds request outputs: the server
+ * hands out 64-element-aligned
  * ranges of its first floor(pool_elems / 64) * 64 elements.  d_tables
  * (xg_server_device_bytes(cfg) bytes, 256-byte aligned) holds request tables.
  * Both stay owned by the caller.  Creates num_lanes HIP streams (default
  * priority) and pinned host staging; synchronises the device once and reads
  * the streams' positions.  The server keeps those positions on the host, so
- * while it exists no other call may advance the streams of ctx.  Section 2's
- * member only (others: XG_ENOTSUP).
+ * while it exists no other call may advance the streams of ctx.  The further
+ * members (XG_FAMILY_R64_W32, XG_FAMILY_R64_W64) are served through their
+ * batch kernel and only with segment_words 0 (otherwise XG_ENOTSUP).
  * Errors: XG_EINVAL (among others pool_elems < 64), XG_ERANGE (a buffer too
  * small), XG_EALIGN, XG_ENOMEM, XG_ENOTSUP, XG_EHIP. */
 xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config *cfg,

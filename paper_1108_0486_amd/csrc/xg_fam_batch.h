@@ -1,5 +1,6 @@
 // Launcher of the batched kernel for the further family members
-// (xg_family.hip), used by xg_generate_batch.  Not installed.
+// (xg_family.hip), used by xg_generate_batch and the request server, and the
+// byte offset of pos in a member's stream state.  Not installed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -18,5 +19,8 @@ hipError_t launch_family_batch(uint32_t family, const Shape &shape, int num_cus,
                                uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
                                const uint32_t *groups, uint32_t num_groups, void *out, uint64_t out_elems,
                                uint32_t *work, hipStream_t stream);
+
+// Byte offset of the 64-bit position in one stream's state of a family.
+uint32_t family_pos_offset(uint32_t family);
 
 }  // namespace xg

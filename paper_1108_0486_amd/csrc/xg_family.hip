@@ -808,6 +808,15 @@ uint32_t family_state_bytes(uint32_t family) {
   }
 }
 
+uint32_t family_pos_offset(uint32_t family) {
+  switch (family) {
+    case XG_FAMILY_R128_W32: return 130 * 4;
+    case XG_FAMILY_R64_W32: return MemberN2048::pos_off;
+    case XG_FAMILY_R64_W64: return MemberW64::pos_off;
+    default: return 0;
+  }
+}
+
 hipError_t launch_family_init(uint32_t family, unsigned char *state, uint64_t num_streams, uint64_t seed,
                               hipStream_t stream) {
   const uint64_t pairs = (num_streams + 1) / 2;

@@ -34,6 +34,7 @@
 #include "xg.h"
 #include "xg_internal.h"
 #include "xg_pool.h"
+#include "xg_fam_batch.h"
 
 namespace {
 
@@ -235,13 +236,20 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
   if (!s->default_tune)
     shape = xg::Shape{s->tune.waves_per_block, s->tune.unroll, s->tune.blocks_per_cu,
                       s->tune.store_words ? s->tune.store_words : (s->tune.unroll >= 4 ? 4u : 1u)};
-  xg::SegmentArgs seg{s->d_jump, s->seg_words, s->d_jump ? kJumpEntries : 0u, l.d_stage, s->max_batch};
-  if (xg::launch_batch(shape, s->ctx->num_cus, s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_groups,
-                       num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream,
-                       s->seg_words ? &seg : nullptr) != hipSuccess)
-    return XG_EHIP;
-  if (slots && xg::launch_commit(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, seg, l.stream) != hipSuccess)
-    return XG_EHIP;
+  if (s->ctx->family != XG_FAMILY_R128_W32) {  // a further member (no segments)
+    if (xg::launch_family_batch(s->ctx->family, shape, s->ctx->num_cus,
+                                reinterpret_cast<unsigned char *>(s->ctx->d_state), s->ctx->num_streams, l.d_reqs, k,
+                                l.d_groups, num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream) != hipSuccess)
+      return XG_EHIP;
+  } else {
+    xg::SegmentArgs seg{s->d_jump, s->seg_words, s->d_jump ? kJumpEntries : 0u, l.d_stage, s->max_batch};
+    if (xg::launch_batch(shape, s->ctx->num_cus, s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_groups,
+                         num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream,
+                         s->seg_words ? &seg : nullptr) != hipSuccess)
+      return XG_EHIP;
+    if (slots && xg::launch_commit(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, seg, l.stream) != hipSuccess)
+      return XG_EHIP;
+  }
   if (hipEventRecord(l.done, l.stream) != hipSuccess) return XG_EHIP;
   l.t_launch = now_ns();
   for (xg_completion &c : l.reqs) c.t_launch_ns = l.t_launch;
@@ -272,7 +280,10 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
   if (!out) return XG_EINVAL;
   *out = nullptr;
   if (!ctx || !config_valid(cfg) || !d_pool || !d_tables || pool_elems < xg::kPoolAlignElems) return XG_EINVAL;
-  if (ctx->family != XG_FAMILY_R128_W32) return XG_ENOTSUP;
+  // The further members are served without jump-ahead segments.
+  if (ctx->family != XG_FAMILY_R128_W32 &&
+      ((ctx->family != XG_FAMILY_R64_W32 && ctx->family != XG_FAMILY_R64_W64) || cfg->segment_words != 0))
+    return XG_ENOTSUP;
   if (tables_bytes < xg_server_device_bytes(cfg)) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_pool) % kAlignBytes || reinterpret_cast<uintptr_t>(d_tables) % kAlignBytes)
     return XG_EALIGN;
@@ -306,21 +317,20 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
     return XG_EHIP;
   }
   {
-    std::vector<uint32_t> state;
+    const size_t per = xg::family_state_bytes(ctx->family);
+    const size_t pos_off = xg::family_pos_offset(ctx->family);
+    std::vector<unsigned char> state;
     try {
-      state.resize((size_t)ctx->num_streams * XG_STATE_WORDS);
+      state.resize((size_t)ctx->num_streams * per);
     } catch (const std::bad_alloc &) {
       delete s;
       return XG_ENOMEM;
     }
-    if (hipMemcpy(state.data(), ctx->d_state, state.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+    if (hipMemcpy(state.data(), ctx->d_state, state.size(), hipMemcpyDeviceToHost) != hipSuccess) {
       delete s;
       return XG_EHIP;
     }
-    for (uint64_t i = 0; i < ctx->num_streams; ++i) {
-      const uint32_t *w = state.data() + i * XG_STATE_WORDS;
-      s->pos[i] = (uint64_t)w[130] | ((uint64_t)w[131] << 32);
-    }
+    for (uint64_t i = 0; i < ctx->num_streams; ++i) std::memcpy(&s->pos[i], state.data() + i * per + pos_off, 8);
   }
   const TableLayout tl = table_layout(cfg);
   char *base = static_cast<char *>(d_tables);

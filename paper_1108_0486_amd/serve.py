@@ -38,7 +38,9 @@ class Server:
     def __init__(self, streams: XorgensStreams, pool_elems: int, num_lanes: int = 4, max_batch: int = 1024,
                  tune=None, segment_words: int = 0):
         self.streams = streams
-        self.pool = torch.empty(pool_elems, dtype=torch.int32, device=streams.device)
+        # Pool elements are the member's word width: 8 bytes for the 64-bit member.
+        wide = streams.family == xg.XG_FAMILY_R64_W64
+        self.pool = torch.empty(pool_elems, dtype=torch.int64 if wide else torch.int32, device=streams.device)
         nbytes = xg.xg_server_device_bytes(num_lanes, max_batch, segment_words)
         if nbytes == 0:
             raise ValueError("invalid server configuration")
@@ -64,7 +66,9 @@ class Server:
 
     def output(self, c: Completion) -> torch.Tensor:
         v = self.pool[c.out_offset:c.out_offset + c.n]
-        return v if c.dtype == xg.XG_U32 else v.view(torch.float32)
+        if c.dtype == xg.XG_U32:
+            return v
+        return v.view(torch.float64 if v.element_size() == 8 else torch.float32)
 
     def release(self, rid: int) -> None:
         xg.xg_server_release(self.srv, rid)

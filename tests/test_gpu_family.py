@@ -154,8 +154,8 @@ def test_family_unsupported_calls_are_rejected(fam):
             c()
         assert e.value.status == xg.XG_ENOTSUP
     from paper_1108_0486_amd.serve import Server
-    with pytest.raises(xg.XgError) as e:
-        Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4)
+    with pytest.raises(xg.XgError) as e:  # served, but without jump-ahead segments
+        Server(gs, pool_elems=1 << 12, num_lanes=1, max_batch=4, segment_words=1 << 12)
     assert e.value.status == xg.XG_ENOTSUP
     paper = XorgensStreams(4, seed=1)
     for c in (xg.xg_generate_u64, xg.xg_generate_normal_f64, xg.xg_normal_moments_f64):

@@ -190,3 +190,29 @@ def test_member_batch_odd_normal_pieces(fam):
     _check(fam, b.out, b.requests_in_order(), want)
     ring, weyl, pos = gs.host_state()
     assert (ring == ref.ring).all() and (weyl == ref.weyl).all() and (pos == ref.pos).all()
+
+
+@pytest.mark.parametrize("fam", FAMILIES)
+@pytest.mark.parametrize("pool,lanes,max_batch", [(1 << 20, 4, 64), (1 << 14, 2, 8), (1 << 20, 1, 1)])
+def test_member_serving_matches_oracle(fam, pool, lanes, max_batch):
+    """A randomised trace (few streams, so requests chain on a stream; N from 1
+    to 2^13; all three dtypes) through a member's server: every request reads
+    from where the stream's previous request ended, and every value equals
+    the oracle's."""
+    from paper_1108_0486_amd import workloads as W
+    from paper_1108_0486_amd.serve import Server, run_trace
+
+    S = 10
+    gs = XorgensStreams(S, seed=31, family=fam)
+    srv = Server(gs, pool_elems=pool, num_lanes=lanes, max_batch=max_batch)
+    trace = W.serving_trace(200, num_streams=S, rate=200_000.0, seed=5, lo_exp=0, hi_exp=13)
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True, timeout_s=60)
+    assert summary["server"]["completed"] == len(trace)
+    ref = _oracle(fam, 31, S)
+    pos = [0] * S
+    for c in sorted(done, key=lambda c: (c.stream, c.start_pos)):
+        assert c.start_pos == pos[c.stream], (c.id, c.stream)
+        w = _oracle_serve(fam, ref, [(c.stream, c.n, 0, c.dtype)])[0]
+        _check(fam, outputs[c.id], [(c.stream, c.n, 0, c.dtype)], [w])
+        pos[c.stream] += c.n + (c.n & 1 if c.dtype == xg.XG_NORMAL else 0)
+    srv.close()
