@@ -216,3 +216,43 @@ def test_member_serving_matches_oracle(fam, pool, lanes, max_batch):
         _check(fam, outputs[c.id], [(c.stream, c.n, 0, c.dtype)], [w])
         pos[c.stream] += c.n + (c.n & 1 if c.dtype == xg.XG_NORMAL else 0)
     srv.close()
+
+
+def test_member_batch_full_size_ragged():
+    """The 65536-stream ragged workload (uint32, dense CSR offsets) on the
+    n = 2048 member, with the autotuned shape in a replayed graph, as the
+    bench times it: every word of 48 sampled streams (the longest and the
+    shortest among them) against the oracle, every end position, and the end
+    states of 256 more streams against the oracle's polynomial jump."""
+    from paper_1108_0486_amd import workloads as W
+
+    lengths = W.ragged_lengths()
+    off = W.csr_offsets(lengths)
+    total = int(off[-1])
+    S = len(lengths)
+    gs = XorgensStreams(S, seed=W.SEED, family=R64W32)
+    b = Batch(gs, [(i, int(lengths[i]), int(off[i]), 0) for i in range(S)], total)
+    best, _ = b.autotune(reps=1)
+    g = b.capture_graph(tune=best)
+    g.replay()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    _, _, pos = gs.host_state()
+    assert (pos == lengths).all()
+    rng = np.random.default_rng(1)
+    sample = sorted(set(rng.choice(S, size=44, replace=False).tolist()
+                        + [int(np.argmax(lengths)), int(np.argmin(lengths)), 0, S - 1]))
+    for i in sample:
+        n = int(lengths[i])
+        got = b.out[int(off[i]):int(off[i]) + n].cpu().numpy().view(np.uint32)
+        one = O.OracleStreams(W.SEED + i, 1, params=O.R64)
+        assert (got == one.u32(n)[0]).all(), i
+    P = O.charpoly(O.R64)
+    more = sorted(rng.choice(S, size=256, replace=False).tolist())
+    ring, weyl, _ = gs.host_state(more)
+    for j, i in enumerate(more):
+        n = int(lengths[i])
+        start = O.OracleStreams(W.SEED + i, 1, params=O.R64)
+        gp = O.poly_to_words(O.z_pow_mod(n, P), O.R64.n // 64)
+        assert (ring[j] == O.xpart_jump_poly(O.R64, start.ring[0], gp)).all(), i
+        assert int(weyl[j]) == (int(start.weyl[0]) + n * O.R64.omega) % 2**32, i
