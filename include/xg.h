@@ -301,6 +301,14 @@ xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void 
  * z^(64 k + i)).  Errors: XG_EINVAL (NULL h_g), XG_ENOTSUP. */
 xg_status xg_jump_polynomial(uint64_t J, uint64_t *h_g);
 
+/* The same for a family member (XG_FAMILY_*): z^J mod P of that member's
+ * x-part, P of degree n = r w, written as n / 64 little-endian words to h_g
+ * (host memory of at least n / 64 words).  The library derives each P once
+ * per process from its own stepping of the member's recurrence, as the first
+ * linear dependency among the states S, T S, ..., T^n S.
+ * Errors: XG_EINVAL (NULL h_g, unknown family), XG_ENOTSUP. */
+xg_status xg_family_jump_polynomial(uint32_t family, uint64_t J, uint64_t *h_g);
+
 /* ---- batched requests ------------------------------------------------------ */
 
 /* One request: n values of type dtype from stream `stream`'s current

@@ -379,3 +379,37 @@ int gf2_mat_pow_apply(const uint64_t *M, int n, const uint8_t *jbits, int nbits,
     free(Mp); free(T); free(nv);
     return 0;
 }
+
+/* v_j <- M^(J_j) v_j for k column vectors at once: the binary powers M^(2^b)
+   are formed once and applied to every v_j whose exponent has bit b set.
+   jbits holds k little-endian bit arrays of nbits bits each (row j for J_j);
+   vs holds the k vectors, rw = nwords(n - 1) words each. */
+int gf2_mat_pow_apply_many(const uint64_t *M, int n, const uint8_t *jbits, int nbits, int k, uint64_t *vs)
+{
+    int rw = nwords(n - 1), i, q, b, j;
+    size_t msz = (size_t)n * (size_t)rw;
+    uint64_t *Mp = (uint64_t *)malloc(msz * sizeof(uint64_t));
+    uint64_t *T = (uint64_t *)malloc(msz * sizeof(uint64_t));
+    uint64_t *nv = (uint64_t *)calloc((size_t)rw, sizeof(uint64_t));
+    if (!Mp || !T || !nv) { free(Mp); free(T); free(nv); return -2; }
+    memcpy(Mp, M, msz * sizeof(uint64_t));
+    for (b = 0; b < nbits; b++) {
+        for (j = 0; j < k; j++) {
+            uint64_t *v = vs + (size_t)j * rw;
+            if (!jbits[(size_t)j * nbits + b]) continue;
+            memset(nv, 0, (size_t)rw * sizeof(uint64_t));
+            for (i = 0; i < n; i++) {
+                uint64_t acc = 0;
+                for (q = 0; q < rw; q++) acc ^= Mp[(size_t)i * rw + q] & v[q];
+                if (__builtin_parityll(acc)) nv[i >> 6] |= 1ull << (i & 63);
+            }
+            memcpy(v, nv, (size_t)rw * sizeof(uint64_t));
+        }
+        if (b + 1 < nbits) {
+            matmul(Mp, Mp, T, n, rw);
+            memcpy(Mp, T, msz * sizeof(uint64_t));
+        }
+    }
+    free(Mp); free(T); free(nv);
+    return 0;
+}

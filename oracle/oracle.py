@@ -137,6 +137,8 @@ def lib() -> ctypes.CDLL:
                                        ctypes.c_int, ctypes.c_int]
         L.gf2_z_pow_mod.argtypes = [u64p, ctypes.c_int, u8p, ctypes.c_int, u64p]
         L.gf2_mat_pow_apply.argtypes = [u64p, ctypes.c_int, u8p, ctypes.c_int, u64p]
+        L.gf2_mat_pow_apply_many.argtypes = [u64p, ctypes.c_int, u8p, ctypes.c_int, ctypes.c_int, u64p]
+        L.xgo64_xpart_matrix.argtypes = [P64, u64p]
         _lib = L
     return _lib
 
@@ -348,20 +350,25 @@ def full_period(params: Params, ring, weyl: int, max_steps: int) -> int:
 
 
 def xpart_matrix(params: Params) -> np.ndarray:
+    """The x-part's one-step matrix (n rows of bits; next = M state)."""
     n = params.n
     rw = (n - 1) // 64 + 1
     rows = np.zeros((n, rw), dtype=np.uint64)
-    rc = lib().xgo_xpart_matrix(ctypes.byref(params.c_struct()), _ptr(rows, ctypes.c_uint64))
+    if params.w == 64:
+        rc = lib().xgo64_xpart_matrix(ctypes.byref(params.c_struct()), _ptr(rows, ctypes.c_uint64))
+    else:
+        rc = lib().xgo_xpart_matrix(ctypes.byref(params.c_struct()), _ptr(rows, ctypes.c_uint64))
     if rc != 0:
         raise ValueError("bad params")
     return rows
 
 
 def ring_to_bits(params: Params, ring) -> np.ndarray:
-    """Packs a linear ring into the column bit vector used by xpart_matrix."""
+    """Packs a linear ring into the column bit vector used by xpart_matrix
+    (state bit w t + b is bit b of ring word t)."""
     n = params.n
     v = np.zeros((n - 1) // 64 + 1, dtype=np.uint64)
-    for t, word in enumerate(np.asarray(ring, dtype=np.uint32)):
+    for t, word in enumerate(np.asarray(ring, dtype=np.uint64 if params.w == 64 else np.uint32)):
         for b in range(params.w):
             if (int(word) >> b) & 1:
                 i = t * params.w + b
@@ -370,10 +377,11 @@ def ring_to_bits(params: Params, ring) -> np.ndarray:
 
 
 def bits_to_ring(params: Params, v: np.ndarray) -> np.ndarray:
-    ring = np.zeros(params.r, dtype=np.uint32)
+    wt = np.uint64 if params.w == 64 else np.uint32
+    ring = np.zeros(params.r, dtype=wt)
     for i in range(params.n):
         if (int(v[i // 64]) >> (i % 64)) & 1:
-            ring[i // params.w] |= np.uint32(1 << (i % params.w))
+            ring[i // params.w] |= wt(1 << (i % params.w))
     return ring
 
 
@@ -385,6 +393,20 @@ def mat_pow_apply(M: np.ndarray, n: int, J: int, v: np.ndarray) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("mat_pow_apply failed")
     return v
+
+
+def mat_pow_apply_many(M: np.ndarray, n: int, Js, vs: np.ndarray) -> np.ndarray:
+    """Row j of the result is M^(Js[j]) vs[j] (the binary powers of M formed
+    once for all j)."""
+    Js = [int(J) for J in Js]
+    nb = max(1, max(J.bit_length() for J in Js))
+    jb = np.array([[(J >> i) & 1 for i in range(nb)] for J in Js], dtype=np.uint8)
+    vs = np.ascontiguousarray(vs, dtype=np.uint64).copy()
+    rc = lib().gf2_mat_pow_apply_many(_ptr(np.ascontiguousarray(M), ctypes.c_uint64), n,
+                                      _ptr(jb, ctypes.c_uint8), nb, len(Js), _ptr(vs, ctypes.c_uint64))
+    if rc != 0:
+        raise RuntimeError("mat_pow_apply_many failed")
+    return vs
 
 
 def xpart_jump_poly(params: Params, ring, g: np.ndarray) -> np.ndarray:

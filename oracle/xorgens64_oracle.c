@@ -295,3 +295,28 @@ int xgo64_xpart_jump_poly(const xgo64_params *p, uint64_t *ring, const uint64_t 
     memcpy(ring, acc, p->r * sizeof(uint64_t));
     return 0;
 }
+
+/* The x-part's one-step matrix M (n = 64 r rows of r words, row-major): state
+   bit 64 t + b is bit b of ring word t (ring[t] = x_{pos-r+t}); column k is
+   one step applied to the unit state e_k, so that next = M state. */
+int xgo64_xpart_matrix(const xgo64_params *p, uint64_t *rows)
+{
+    uint64_t ring[XGO64_RMAX];
+    uint32_t n, rw, k, t, b;
+    if (!xgo64_params_valid(p)) return -1;
+    n = p->r * 64;
+    rw = n / 64;
+    memset(rows, 0, (size_t)n * rw * sizeof(uint64_t));
+    for (k = 0; k < n; k++) {
+        memset(ring, 0, sizeof(ring));
+        ring[k / 64] = 1ull << (k % 64);
+        xgo64_xpart_run(p, ring, 1, 0, NULL);
+        for (t = 0; t < p->r; t++)
+            for (b = 0; b < 64; b++)
+                if ((ring[t] >> b) & 1u) {
+                    uint32_t i = t * 64 + b;
+                    rows[(size_t)i * rw + k / 64] |= 1ull << (k % 64);
+                }
+    }
+    return 0;
+}

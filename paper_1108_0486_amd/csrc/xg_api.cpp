@@ -369,6 +369,11 @@ xg_status xg_jump_polynomial(uint64_t J, uint64_t *h_g) {
   return xg::jump_polynomial(J, h_g) ? XG_OK : XG_ENOTSUP;
 }
 
+xg_status xg_family_jump_polynomial(uint32_t family, uint64_t J, uint64_t *h_g) {
+  if (!h_g || family > XG_FAMILY_R64_W64) return XG_EINVAL;
+  return xg::jump_polynomial(family, J, h_g) ? XG_OK : XG_ENOTSUP;
+}
+
 size_t xg_batch_workspace_bytes(void) { return 256; }
 
 xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,

@@ -35,4 +35,9 @@ bool jump_polynomial(uint64_t J, uint64_t g[64]);
 int member_degree(uint32_t family);
 bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g);
 
+// table[k] (member_degree(family) / 64 words each) = z^((k + 1) L) mod P for
+// k < count.  False for an unknown family, if P could not be derived, or if
+// host memory ran out.
+bool jump_table(uint32_t family, uint64_t L, uint32_t count, uint64_t *table);
+
 }  // namespace xg

@@ -2,13 +2,24 @@
 // family member's x-part step and the jump polynomials z^J mod P.
 //
 // The x-part of xorgens is GF(2)-linear (Section 1.5 / Section 2 of
-// arXiv:1108.0486): its n-bit state (n = r w) moves by a fixed matrix T, and
-// by Cayley-Hamilton T^J = g(T) with g = z^J mod P, deg g < n.  The device
-// evaluates g(T) applied to a stream's state.  P is obtained once per process
-// and member from the library's own host stepping of the recurrence, by
-// Berlekamp-Massey on one output bit (the minimal polynomial of that bit
-// sequence is P because P is irreducible of degree n).
-#include <atomic>
+// arXiv:1108.0486): its n-bit state S (n = r w) moves by a fixed matrix T.
+// By Cayley-Hamilton T^J = g(T) with g = z^J mod P, deg g < n; the device
+// evaluates g(T) on a stream's state.
+//
+// Everything here is linear algebra over GF(2) on n-bit vectors:
+//   P      the first linear dependency among the Krylov vectors
+//          S_0, T S_0, ..., T^n S_0 of a fixed non-zero start state, found by
+//          Gauss-Jordan elimination (rank n means S_0 is cyclic and P is the
+//          characteristic polynomial; a primitive P makes every non-zero S_0
+//          cyclic).  T^k S_0 is the ring window after k host steps.
+//   z^J    left-to-right binary powering in the residue ring GF(2)[z] / P, in
+//          which squaring is the linear Frobenius map a -> a^2: a table of
+//          z^(2i) mod P turns a square into the XOR of the entries of a's set
+//          bits, and a multiplication by z is a shift with one conditional XOR
+//          of P.
+//   z^(kL) the server's jump table: multiplication by the fixed residue
+//          h = z^L mod P is linear too; its table z^i h mod P (i < n) gives
+//          each next entry as one table application.
 #include <cstdint>
 #include <cstring>
 #include <mutex>
@@ -19,50 +30,6 @@
 
 namespace xg {
 namespace {
-
-constexpr int kMaxDeg = 4096;
-constexpr int kMaxW = kMaxDeg / 64;  // words of a residue (degree < 4096)
-constexpr int kMaxPW = kMaxW + 1;    // words of P (degree 4096)
-
-// Carry-less 64 x 64 -> 128 product: with the CPU instruction when present.
-__attribute__((target("pclmul,sse4.1"))) void clmul_hw(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
-  typedef long long v2di __attribute__((vector_size(16)));
-  v2di x = {(long long)a, 0}, y = {(long long)b, 0};
-  v2di r = __builtin_ia32_pclmulqdq128(x, y, 0x00);
-  lo = (uint64_t)r[0];
-  hi = (uint64_t)r[1];
-}
-
-void clmul_sw(uint64_t a, uint64_t b, uint64_t &lo, uint64_t &hi) {
-  uint64_t l = 0, h = 0;
-  for (int i = 0; i < 64; ++i)
-    if ((a >> i) & 1u) {
-      l ^= b << i;
-      if (i) h ^= b >> (64 - i);
-    }
-  lo = l;
-  hi = h;
-}
-
-bool have_pclmul() {
-  static const bool yes = __builtin_cpu_supports("pclmul") && __builtin_cpu_supports("sse4.1");
-  return yes;
-}
-
-// out[0 .. wa + wb) = a * b over GF(2).
-void pmul(const uint64_t *a, int wa, const uint64_t *b, int wb, uint64_t *out) {
-  std::memset(out, 0, sizeof(uint64_t) * (size_t)(wa + wb));
-  const bool hw = have_pclmul();
-  for (int i = 0; i < wa; ++i) {
-    if (!a[i]) continue;
-    for (int j = 0; j < wb; ++j) {
-      uint64_t lo, hi;
-      if (hw) clmul_hw(a[i], b[j], lo, hi); else clmul_sw(a[i], b[j], lo, hi);
-      out[i + j] ^= lo;
-      out[i + j + 1] ^= hi;
-    }
-  }
-}
 
 // A member's x-part (Section 2): w-bit words, lags r > s, shifts a..d.
 struct Member {
@@ -76,111 +43,144 @@ constexpr Member kMembers[3] = {
     {64, 64, 33, 24, 22, 37, 45},   // XG_FAMILY_R64_W64
 };
 
-// Host stepping of a member's x-part from a fixed non-zero ring; writes bit 0
-// of x_0 .. x_{nbits-1}.  Words are held in 64 bits and masked to w bits.
-void xpart_bit0(const Member &m, std::vector<uint8_t> &bits) {
+inline bool bit_of(const uint64_t *v, int i) { return (v[i >> 6] >> (i & 63)) & 1u; }
+
+inline void xor_into(uint64_t *dst, const uint64_t *src, int words) {
+  for (int k = 0; k < words; ++k) dst[k] ^= src[k];
+}
+
+// The residue ring of one member: P, and the Frobenius table.
+struct Field {
+  int n = 0, words = 0;           // degree, 64-bit words of a residue
+  std::vector<uint64_t> low;      // P - z^n (the bits below the leading one)
+  std::vector<uint64_t> sq;       // row i: z^(2 i) mod P, i < n
+  bool ok = false;
+
+  // a <- z a mod P.
+  void times_z(uint64_t *a) const {
+    const bool top = bit_of(a, n - 1);
+    for (int k = words - 1; k > 0; --k) a[k] = (a[k] << 1) | (a[k - 1] >> 63);
+    a[0] <<= 1;
+    if (top) xor_into(a, low.data(), words);
+  }
+
+  // out <- a^2 mod P (out != a).
+  void square(const uint64_t *a, uint64_t *out) const {
+    std::memset(out, 0, sizeof(uint64_t) * (size_t)words);
+    for (int k = 0; k < words; ++k)
+      for (uint64_t m = a[k]; m; m &= m - 1) {
+        const int i = 64 * k + __builtin_ctzll(m);
+        xor_into(out, sq.data() + (size_t)i * words, words);
+      }
+  }
+};
+
+Field g_field[3];
+std::once_flag g_once[3];
+
+// The member's x-part words x_{-r} .. x_{count-r-1} from a fixed non-zero
+// ring, by the recurrence of Section 2 (words kept in 64 bits, masked to w).
+std::vector<uint64_t> xpart_words(const Member &m, int count) {
   const uint64_t mask = m.w == 64 ? ~0ull : (1ull << m.w) - 1;
-  std::vector<uint64_t> ring((size_t)m.r);
-  for (int i = 0; i < m.r; ++i) ring[(size_t)i] = (0x9E3779B97F4A7C15ull * (uint64_t)(i + 1) ^ ((uint64_t)i << 7)) & mask;
-  int head = 0;  // slot of x_{k-r}
-  for (size_t k = 0; k < bits.size(); ++k) {
-    const uint64_t xr = ring[(size_t)head], xs = ring[(size_t)((head + m.r - m.s) % m.r)];  // x_{k-r}, x_{k-s}
+  std::vector<uint64_t> x((size_t)count);
+  uint64_t z = 0x243F6A8885A308D3ull;  // any non-zero start ring will do
+  for (int i = 0; i < m.r; ++i) {
+    z ^= z << 13;
+    z ^= z >> 7;
+    z ^= z << 17;
+    x[(size_t)i] = z & mask;
+  }
+  for (int k = m.r; k < count; ++k) {
+    const uint64_t xr = x[(size_t)(k - m.r)], xs = x[(size_t)(k - m.s)];
     uint64_t t = xr ^ ((xr << m.a) & mask);
     t ^= t >> m.b;
     uint64_t v = xs ^ ((xs << m.c) & mask);
     v ^= v >> m.d;
-    const uint64_t x = t ^ v;
-    ring[(size_t)head] = x;
-    head = (head + 1) % m.r;
-    bits[k] = (uint8_t)(x & 1u);
+    x[(size_t)k] = t ^ v;
   }
+  return x;
 }
 
-// Minimal polynomial (as z^L + c_1 z^{L-1} + ... + c_L) of a bit sequence.
-int min_poly(const std::vector<uint8_t> &s, std::vector<uint64_t> &poly) {
-  const int N = (int)s.size();
-  std::vector<uint8_t> C(N + 2, 0), B(N + 2, 0), T;
-  C[0] = B[0] = 1;
-  int L = 0, m = 1;
-  for (int k = 0; k < N; ++k) {
-    int d = s[k];
-    for (int i = 1; i <= L; ++i) d ^= C[i] & s[k - i];
-    if (!d) {
-      ++m;
-      continue;
+// P from the Krylov vectors: column k (k = 0 .. n) of an n x (n + 1) bit
+// matrix is S_k = (x_{k-r}, .., x_{k-1}) with bit j of word t at row t w + j.
+// Gauss-Jordan on columns 0 .. n-1 leaves, at full rank, column n equal to
+// the coefficients c with S_n = sum_k c_k S_k, so P = z^n + sum_k c_k z^k.
+bool derive_p(const Member &m, Field &F) {
+  const int n = m.n(), cols = n + 1, rw = (cols + 63) / 64;
+  const std::vector<uint64_t> x = xpart_words(m, n + m.r);  // x[i] = x_{i-r}
+  std::vector<uint64_t> rows((size_t)n * rw, 0);
+  for (int b = 0; b < n; ++b) {
+    const int t = b / m.w, j = b % m.w;
+    uint64_t *row = rows.data() + (size_t)b * rw;
+    for (int k = 0; k < cols; ++k)
+      if ((x[(size_t)(k + t)] >> j) & 1u) row[k >> 6] |= 1ull << (k & 63);
+  }
+  for (int col = 0; col < n; ++col) {
+    int piv = -1;
+    for (int i = col; i < n; ++i)
+      if (bit_of(rows.data() + (size_t)i * rw, col)) {
+        piv = i;
+        break;
+      }
+    if (piv < 0) return false;  // rank below n: not the characteristic polynomial
+    uint64_t *pr = rows.data() + (size_t)piv * rw;
+    if (piv != col) {
+      uint64_t *cr = rows.data() + (size_t)col * rw;
+      for (int k = 0; k < rw; ++k) std::swap(pr[k], cr[k]);
+      pr = cr;
     }
-    if (2 * L <= k) {
-      T = C;
-      for (int i = 0; i + m <= N + 1; ++i) C[i + m] ^= B[i];
-      L = k + 1 - L;
-      B = T;
-      m = 1;
-    } else {
-      for (int i = 0; i + m <= N + 1; ++i) C[i + m] ^= B[i];
-      ++m;
+    const int from = col >> 6;  // the pivot row is zero left of col
+    for (int i = 0; i < n; ++i) {
+      if (i == col) continue;
+      uint64_t *ri = rows.data() + (size_t)i * rw;
+      if (bit_of(ri, col)) xor_into(ri + from, pr + from, rw - from);
     }
   }
-  poly.assign((size_t)L / 64 + 1, 0);
-  for (int i = 0; i <= L; ++i)
-    if (C[i]) poly[(size_t)(L - i) / 64] |= 1ull << ((L - i) % 64);
-  return L;
+  F.n = n;
+  F.words = n / 64;
+  F.low.assign((size_t)F.words, 0);
+  for (int k = 0; k < n; ++k)
+    if (bit_of(rows.data() + (size_t)k * rw, n)) F.low[(size_t)k >> 6] |= 1ull << (k & 63);
+  return true;
 }
 
-struct Modulus {
-  int deg = 0, w = 0, pw = 0;   // n, words of a residue, words of P
-  uint64_t P[kMaxPW];
-  uint64_t mu[kMaxPW];          // floor(z^(2n) / P)
-  bool ok = false;
-};
-
-Modulus g_mod[3];
-std::once_flag g_once[3];
-
-void init_modulus(int f) {
-  const Member &m = kMembers[f];
-  Modulus &M = g_mod[f];
-  const int n = m.n();
-  M.deg = n;
-  M.w = n / 64;
-  M.pw = M.w + 1;
-  std::vector<uint8_t> bits((size_t)(2 * n + 128));
-  xpart_bit0(m, bits);
-  std::vector<uint64_t> poly;
-  if (min_poly(bits, poly) != n || poly.size() != (size_t)M.pw) return;
-  std::memset(M.P, 0, sizeof(M.P));
-  std::memcpy(M.P, poly.data(), sizeof(uint64_t) * (size_t)M.pw);
-  // mu by long division of z^(2n) by P
-  std::vector<uint64_t> rem((size_t)(2 * M.pw + 1), 0);
-  rem[(size_t)(2 * n) / 64] |= 1ull << ((2 * n) % 64);
-  std::memset(M.mu, 0, sizeof(M.mu));
-  for (int i = 2 * n; i >= n; --i) {
-    if (!((rem[(size_t)i / 64] >> (i % 64)) & 1u)) continue;
-    M.mu[(i - n) / 64] |= 1ull << ((i - n) % 64);
-    const int sh = i - n;
-    for (int j = 0; j <= n; ++j)
-      if ((M.P[j / 64] >> (j % 64)) & 1u) rem[(size_t)(j + sh) / 64] ^= 1ull << ((j + sh) % 64);
+void build_field(int f) {
+  Field &F = g_field[f];
+  if (!derive_p(kMembers[f], F)) return;
+  const int n = F.n, W = F.words;
+  F.sq.assign((size_t)n * W, 0);
+  std::vector<uint64_t> cur((size_t)W, 0);
+  cur[0] = 1;
+  for (int i = 0; i < n; ++i) {  // row i = z^(2 i) mod P
+    std::memcpy(F.sq.data() + (size_t)i * W, cur.data(), sizeof(uint64_t) * (size_t)W);
+    F.times_z(cur.data());
+    F.times_z(cur.data());
   }
-  M.ok = true;
+  F.ok = true;
 }
 
-// out = a >> sh for a of wa words, ow output words.
-void shr(const uint64_t *a, int wa, int sh, uint64_t *out, int ow) {
-  const int q = sh / 64, r = sh % 64;
-  for (int i = 0; i < ow; ++i) {
-    const uint64_t lo = i + q < wa ? a[i + q] : 0, hi = i + q + 1 < wa ? a[i + q + 1] : 0;
-    out[i] = r ? (lo >> r) | (hi << (64 - r)) : lo;
+const Field *field(uint32_t family) {
+  if (family >= 3) return nullptr;
+  try {
+    std::call_once(g_once[family], build_field, (int)family);
+  } catch (const std::bad_alloc &) {  // the once-flag stays unset: a later call retries
+    return nullptr;
   }
+  return g_field[family].ok ? &g_field[family] : nullptr;
 }
 
-// out = a * b mod P (exact Barrett reduction: q = floor(floor(ab / z^n) mu / z^n)).
-void mulmod(const Modulus &M, const uint64_t *a, const uint64_t *b, uint64_t *out) {
-  uint64_t prod[2 * kMaxW], h[kMaxPW], t[2 * kMaxPW], q[kMaxPW], qp[2 * kMaxPW];
-  pmul(a, M.w, b, M.w, prod);
-  shr(prod, 2 * M.w, M.deg, h, M.pw);
-  pmul(h, M.pw, M.mu, M.pw, t);
-  shr(t, 2 * M.pw, M.deg, q, M.pw);
-  pmul(q, M.pw, M.P, M.pw, qp);
-  for (int i = 0; i < M.w; ++i) out[i] = prod[i] ^ qp[i];
+// g <- z^J mod P: for the bits of J from the top, g <- g^2, then g <- z g
+// where the bit is set.
+void z_pow(const Field &F, uint64_t J, uint64_t *g) {
+  std::memset(g, 0, sizeof(uint64_t) * (size_t)F.words);
+  g[0] = 1;
+  if (J == 0) return;
+  std::vector<uint64_t> tmp((size_t)F.words);
+  for (int b = 63 - __builtin_clzll(J); b >= 0; --b) {
+    F.square(g, tmp.data());
+    std::memcpy(g, tmp.data(), sizeof(uint64_t) * (size_t)F.words);
+    if ((J >> b) & 1u) F.times_z(g);
+  }
 }
 
 }  // namespace
@@ -188,33 +188,44 @@ void mulmod(const Modulus &M, const uint64_t *a, const uint64_t *b, uint64_t *ou
 int member_degree(uint32_t family) { return family < 3 ? kMembers[family].n() : 0; }
 
 bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g) {
-  if (family >= 3) return false;
+  const Field *F = field(family);
+  if (!F) return false;
   try {
-    std::call_once(g_once[family], init_modulus, (int)family);
-  } catch (const std::bad_alloc &) {  // the once-flag stays unset: a later call retries
+    z_pow(*F, J, g);
+  } catch (const std::bad_alloc &) {
     return false;
   }
-  const Modulus &M = g_mod[family];
-  if (!M.ok) return false;
-  uint64_t base[kMaxW] = {0}, acc[kMaxW] = {0}, tmp[kMaxW];
-  base[0] = 2;  // z
-  acc[0] = 1;
-  const size_t bytes = sizeof(uint64_t) * (size_t)M.w;
-  while (J) {
-    if (J & 1u) {
-      mulmod(M, acc, base, tmp);
-      std::memcpy(acc, tmp, bytes);
-    }
-    J >>= 1;
-    if (J) {
-      mulmod(M, base, base, tmp);
-      std::memcpy(base, tmp, bytes);
-    }
-  }
-  std::memcpy(g, acc, bytes);
   return true;
 }
 
 bool jump_polynomial(uint64_t J, uint64_t g[64]) { return jump_polynomial(XG_FAMILY_R128_W32, J, g); }
+
+bool jump_table(uint32_t family, uint64_t L, uint32_t count, uint64_t *table) {
+  const Field *F = field(family);
+  if (!F) return false;
+  const int n = F->n, W = F->words;
+  try {
+    // mul row i = z^i h mod P, h = z^L mod P: multiplication by h as a table.
+    std::vector<uint64_t> mul((size_t)n * W), cur((size_t)W);
+    z_pow(*F, L, cur.data());
+    for (int i = 0; i < n; ++i) {
+      std::memcpy(mul.data() + (size_t)i * W, cur.data(), sizeof(uint64_t) * (size_t)W);
+      F->times_z(cur.data());
+    }
+    std::vector<uint64_t> prev((size_t)W, 0);
+    prev[0] = 1;  // z^0
+    for (uint32_t k = 0; k < count; ++k) {
+      uint64_t *out = table + (size_t)k * W;
+      std::memset(out, 0, sizeof(uint64_t) * (size_t)W);
+      for (int q = 0; q < W; ++q)
+        for (uint64_t m = prev[(size_t)q]; m; m &= m - 1)
+          xor_into(out, mul.data() + (size_t)(64 * q + __builtin_ctzll(m)) * W, W);
+      std::memcpy(prev.data(), out, sizeof(uint64_t) * (size_t)W);
+    }
+  } catch (const std::bad_alloc &) {
+    return false;
+  }
+  return true;
+}
 
 }  // namespace xg

@@ -182,7 +182,15 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
     // Wait (keeping this stream's order) when the stream is busy elsewhere,
     // closed by a split request in this batch, or would mix a split request
     // with others in this batch.
-    if (bs == 1 || bs == 3 || (split && bs == 2)) {
+    if (bs == 1 || bs == 3) {
+      ++it;
+      continue;
+    }
+    if (split && bs == 2) {
+      // The split request waits for a later batch, so every later request on
+      // its stream must wait too: close the stream for the rest of this pass
+      // (it is already listed in in_this_batch and becomes busy after it).
+      s->busy_stream[p.stream] = 3;
       ++it;
       continue;
     }
@@ -345,11 +353,9 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
       delete s;
       return XG_ENOMEM;
     }
-    for (uint32_t k = 1; k <= kJumpEntries; ++k) {
-      if (!xg::jump_polynomial((uint64_t)k * cfg->segment_words, table.data() + (size_t)(k - 1) * 64)) {
-        delete s;
-        return XG_ENOTSUP;
-      }
+    if (!xg::jump_table(XG_FAMILY_R128_W32, cfg->segment_words, kJumpEntries, table.data())) {
+      delete s;
+      return XG_ENOTSUP;
     }
     if (hipMemcpy(s->d_jump, table.data(), table.size() * sizeof(uint64_t), hipMemcpyHostToDevice) != hipSuccess) {
       delete s;

@@ -107,6 +107,7 @@ def lib() -> ctypes.CDLL:
         "xg_skip": (st, [vp, u64, u64, u64, vp]),
         "xg_box_muller": (st, [vp, u64, vp, vp]),
         "xg_jump_polynomial": (st, [u64, P(u64)]),
+        "xg_family_jump_polynomial": (st, [u32, u64, P(u64)]),
         "xg_fill_f32": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_fill_value": (st, [vp, u64, u32, vp]),
         "xg_family_state_bytes": (ctypes.c_size_t, [u32, u64]),
@@ -292,6 +293,13 @@ def xg_jump_polynomial(J: int) -> int:
     """z^J mod P as a Python int (bit i = coefficient of z^i)."""
     g = (ctypes.c_uint64 * 64)()
     _check(lib().xg_jump_polynomial(J, g), "xg_jump_polynomial")
+    return sum(int(g[k]) << (64 * k) for k in range(64))
+
+
+def xg_family_jump_polynomial(family: int, J: int) -> int:
+    """z^J mod P of a family member's x-part, as a Python int."""
+    g = (ctypes.c_uint64 * 64)()
+    _check(lib().xg_family_jump_polynomial(family, J, g), "xg_family_jump_polynomial")
     return sum(int(g[k]) << (64 * k) for k in range(64))
 
 

@@ -1,7 +1,8 @@
 """Writes the stored expected values under tests/golden/ from the CPU oracle.
 
 Calls only oracle/ (never the HIP path).  Run from the repository root:
-    python tests/golden/make_golden.py
+    python tests/golden/make_golden.py               (every file)
+    python tests/golden/make_golden.py huge_skips    (the large-skip states only)
 """
 import hashlib
 import os
@@ -43,5 +44,44 @@ def main():
         f.write("\n".join(lines) + "\n")
 
 
+# Large skips whose expected states come from the oracle's matrix form: the
+# x-part's one-step bit matrix T raised to J by binary powering and applied to
+# the start state (no jump polynomial on either side).
+HUGE_SKIPS = [
+    # (name, params, seed, count, stream indices, J values)
+    ("r128_w32", O.PAPER, 7, 5, range(5), [2**32 + 5, 2**50 + 3, 2**63 + 1]),
+    ("r64_w32", O.R64, 21, 7, range(1, 6), [2**40 + 5, 2**63 + 1]),
+    ("r64_w64", O.W64, 21, 7, range(1, 6), [2**40 + 5, 2**63 + 1]),
+]
+
+
+def huge_skips():
+    import numpy as np
+    lines = ["# x-part rings after skipping J words, by the oracle's matrix form",
+             "# (T^J by binary powering of the one-step bit matrix, applied to the",
+             "# seeded ring).  One line per (member, J, stream): sha256 of the ring's",
+             "# little-endian words.  Written by tests/golden/make_golden.py from",
+             "# the CPU oracle alone."]
+    for name, p, seed, count, idx, Js in HUGE_SKIPS:
+        if p.w == 64:
+            ref = O.OracleStreams64(seed, count, p)
+        else:
+            ref = O.OracleStreams(seed, count, params=p)
+        M = O.xpart_matrix(p)
+        idx = list(idx)
+        vs = np.stack([O.ring_to_bits(p, ref.ring[i]) for i in idx for _ in Js])
+        got = O.mat_pow_apply_many(M, p.n, [J for _ in idx for J in Js], vs)
+        for a, i in enumerate(idx):
+            for b, J in enumerate(Js):
+                ring = O.bits_to_ring(p, got[a * len(Js) + b])
+                lines.append("%s seed %d stream %d J %d ring %s" % (name, seed, i, J, digest(ring)))
+    with open(os.path.join(HERE, "huge_skips_matrix_form.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 if __name__ == "__main__":
-    main()
+    if sys.argv[1:] == ["huge_skips"]:
+        huge_skips()
+    else:
+        main()
+        huge_skips()

@@ -40,3 +40,23 @@ def ulp64_error(got: np.ndarray, ref: np.ndarray) -> np.ndarray:
     zero = a == 0
     err[zero] = np.where(got[zero] == 0, 0.0, np.inf)
     return err
+
+
+def huge_skip_digests() -> dict:
+    """Stored sha256 digests of rings after large skips, computed by the
+    oracle's matrix form (tests/golden/huge_skips_matrix_form.txt), keyed by
+    (member name, seed, stream, J)."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "huge_skips_matrix_form.txt")
+    out = {}
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        f = line.split()
+        out[(f[0], int(f[2]), int(f[4]), int(f[6]))] = f[8]
+    return out
+
+
+def ring_digest(ring: np.ndarray) -> str:
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(ring).tobytes()).hexdigest()

@@ -9,7 +9,7 @@ the oracle, and so is the state left behind.
 import numpy as np
 import pytest
 
-from gpu_helpers import needs_gpu, ulp32_error, ulp64_error
+from gpu_helpers import huge_skip_digests, needs_gpu, ring_digest, ulp32_error, ulp64_error
 from oracle import oracle as O
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -226,6 +226,13 @@ def test_family_skip_matches_oracle(fam, J):
     want = _oracle_after_skip(fam, 21, 7, J, idx)
     torch.cuda.synchronize()
     _assert_state(gs, want, idx=idx)
+    if J > 2_000_000:
+        # also the oracle's matrix form (stored digests; no jump polynomial)
+        digests = huge_skip_digests()
+        name = "r64_w64" if PARAMS[fam].w == 64 else "r64_w32"
+        ring, _, _ = gs.host_state()
+        for i in idx:
+            assert ring_digest(ring[i]) == digests[(name, 21, i, J)], i
     _assert_state(gs, _sub(_oracle(fam, 21, 7), 6, 7), idx=[6])
     got = _bits(_words(gs, fam, 1000, first=1, count=5))
     assert (got == _ref_words(want, fam, 1000)).all()

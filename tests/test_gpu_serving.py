@@ -27,6 +27,10 @@ def _check_against_oracle(done, outputs, num_streams):
         by_stream.setdefault(c.stream, []).append(c)
     for s, cs in by_stream.items():
         cs.sort(key=lambda c: c.start_pos)
+        # requests on one stream are served in submission order (ids are
+        # given in submission order by every caller here)
+        ids = [c.id for c in cs]
+        assert ids == sorted(ids), (s, ids)
         ref = O.OracleStreams(SEED + s, 1)
         pos = 0
         for c in cs:
@@ -209,6 +213,30 @@ def test_request_with_more_segments_than_a_batch_runs_unsplit():
             done.append(c)
     assert len(done) == 4, [c.id for c in done]
     _check_against_oracle(done, outputs, 3)
+    srv.close()
+
+
+def test_split_request_keeps_its_streams_order():
+    """A(short), B(long enough to split into segments), C(short), all on
+    one stream and submitted together: B cannot share a batch with A, and C
+    must not overtake it, so the three read consecutive positions in
+    submission order (C after B)."""
+    gs = XorgensStreams(2, seed=SEED)
+    srv = Server(gs, pool_elems=1 << 17, num_lanes=1, max_batch=64, segment_words=4096)
+    plan = [(0, 100, 0), (0, 3 * 4096 + 5, 1), (0, 50, 0), (1, 7, 2), (0, 64, 2)]
+    for rid, (stream, n, dt) in enumerate(plan):
+        srv.submit(rid, stream, n, dt)
+    done, outputs = [], {}
+    deadline = time.monotonic() + 20.0
+    while len(done) < len(plan) and time.monotonic() < deadline:
+        for c in srv.poll():
+            outputs[c.id] = srv.output(c).clone()
+            srv.release(c.id)
+            done.append(c)
+    assert len(done) == len(plan), [c.id for c in done]
+    start = {c.id: c.start_pos for c in done}
+    assert start[0] == 0 and start[1] == 100 and start[2] == 100 + 3 * 4096 + 5 and start[4] == start[2] + 50
+    _check_against_oracle(done, outputs, 2)
     srv.close()
 
 

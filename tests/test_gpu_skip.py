@@ -1,10 +1,10 @@
 """xg_skip: advancing streams by J words, by stepping (J < 2^15) and by the
 polynomial jump (J >= 2^15), against the oracle's stepping and, for J too
-large to step, the oracle's own polynomial jump."""
+large to step, the oracle's matrix form (and its own polynomial jump)."""
 import numpy as np
 import pytest
 
-from gpu_helpers import needs_gpu
+from gpu_helpers import huge_skip_digests, needs_gpu, ring_digest
 from oracle import oracle as O
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -32,14 +32,20 @@ def test_skip_equals_stepping(J):
 
 
 @pytest.mark.parametrize("J", [2**32 + 5, 2**50 + 3, 2**63 + 1])
-def test_skip_huge_equals_oracle_polynomial_jump(J):
+def test_skip_huge_equals_matrix_form(J):
+    """Skips far beyond stepping.  The expected rings are the oracle's matrix
+    form (T^J by binary powering of the one-step bit matrix; stored digests
+    written by tests/golden/make_golden.py), which shares no method with the
+    library's jump polynomial; the oracle's own polynomial jump must agree."""
     gs = XorgensStreams(5, seed=7)
     ref = O.OracleStreams(7, 5)
+    want = huge_skip_digests()
     P = O.charpoly(O.PAPER)
     g = O.poly_to_words(O.z_pow_mod(J, P), 64)
     gs.skip(J)
     ring, weyl, pos = gs.host_state()
     for i in range(5):
+        assert ring_digest(ring[i]) == want[("r128_w32", 7, i, J)], i
         assert (ring[i] == O.xpart_jump_poly(O.PAPER, ref.ring[i], g)).all()
     assert (weyl == ((ref.weyl.astype(np.uint64) + np.uint64(J % 2**32) * np.uint64(O.PAPER.omega))
                      % np.uint64(2**32)).astype(np.uint32)).all()
