@@ -107,6 +107,8 @@ def lib() -> ctypes.CDLL:
         L.xgo_splitmix64.argtypes = [u64p]
         L.xgo_splitmix64.restype = ctypes.c_uint64
         L.xgo_box_muller.argtypes = [ctypes.c_uint32, ctypes.c_uint32, P(ctypes.c_double), P(ctypes.c_double)]
+        L.xgo_box_muller_many.argtypes = [u32p, ctypes.c_uint64, P(ctypes.c_double)]
+        L.xgo_box_muller_many.restype = None
         L.xgo_seed_streams.argtypes = [P(_Params), ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
                                        u32p, u32p, u64p]
         L.xgo_run_streams.argtypes = [P(_Params), u32p, u32p, u64p, ctypes.c_uint64, ctypes.c_int,
@@ -305,6 +307,28 @@ def box_muller_w64(o_even: int, o_odd: int) -> tuple[float, float]:
     z0, z1 = ctypes.c_double(), ctypes.c_double()
     lib().xgo64_box_muller(o_even & (2**64 - 1), o_odd & (2**64 - 1), ctypes.byref(z0), ctypes.byref(z1))
     return z0.value, z1.value
+
+
+def box_muller_many(words: np.ndarray, threads: int | None = None) -> np.ndarray:
+    """The FP64 Box-Muller map of the oracle (xgo_box_muller) on consecutive
+    word pairs: returns an array of shape (pairs, 2).  Slices run in threads
+    (the C call releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    pairs = words.size // 2
+    out = np.empty((pairs, 2), dtype=np.float64)
+    nt = max(1, threads or default_threads())
+    step = -(-pairs // nt) if pairs else 1
+    fn = lib().xgo_box_muller_many
+
+    def run(a):
+        b = min(pairs, a + step)
+        if b > a:
+            fn(_ptr(words[2 * a:2 * b], ctypes.c_uint32), b - a, _ptr(out[a:b], ctypes.c_double))
+
+    with ThreadPoolExecutor(nt) as ex:
+        list(ex.map(run, range(0, pairs, step)))
+    return out
 
 
 def box_muller64(o_even: int, o_odd: int) -> tuple[float, float]:

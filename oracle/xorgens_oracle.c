@@ -190,6 +190,14 @@ void xgo_box_muller(uint32_t o_even, uint32_t o_odd, double *z0, double *z1)
     *z1 = rho * s;
 }
 
+/* The map above over many caller-given word pairs: out[2m], out[2m + 1] are
+   z_0, z_1 of the pair (words[2m], words[2m + 1]), for m < pairs. */
+void xgo_box_muller_many(const uint32_t *words, uint64_t pairs, double *out)
+{
+    uint64_t m;
+    for (m = 0; m < pairs; m++) xgo_box_muller(words[2 * m], words[2 * m + 1], &out[2 * m], &out[2 * m + 1]);
+}
+
 /* ---- single-stream drivers ---------------------------------------------- */
 
 enum { XGO_U32 = 0, XGO_F32 = 1, XGO_NORMAL = 2, XGO_MOMENTS = 3, XGO_SKIP = 4 };

@@ -448,6 +448,18 @@ def test_box_muller_special_cases_and_invariants():
             assert min(d, 2 * math.pi - d) < 1e-12
 
 
+def test_box_muller_many_is_the_pairwise_map():
+    """The oracle's vectorised map (used for the exhaustive GPU sweeps) is the
+    pair map itself, pair by pair, in every thread slice."""
+    rng = np.random.default_rng(4)
+    words = rng.integers(0, 2**32, size=2 * 3001, dtype=np.uint64).astype(np.uint32)
+    words[:2] = [(2**24 - 1) << 8, 0]                     # u1 = 1
+    z = O.box_muller_many(words, threads=3)
+    assert z.shape == (3001, 2)
+    for m in range(3001):
+        assert tuple(z[m]) == O.box_muller64(int(words[2 * m]), int(words[2 * m + 1])), m
+
+
 def test_normals_pairing_and_moments():
     st = O.OracleStreams(42, 2)
     u = st.copy().u32(1002)
