@@ -313,7 +313,11 @@ xg_status xg_family_jump_polynomial(uint32_t family, uint64_t J, uint64_t *h_g);
 
 /* One request: n values of type dtype from stream `stream`'s current
  * position, written at d_out + out_offset (in elements of the handle's word
- * width: 4 bytes, 8 for XG_FAMILY_R64_W64).  flags is 0. */
+ * width: 4 bytes, 8 for XG_FAMILY_R64_W64).  flags is 0.  A request reads its
+ * stream from where the requests before it on that stream (in table order)
+ * leave it, so a batch gives each request the values it would get alone
+ * (Section 2: each stream is an independent subsequence; the batch only
+ * decides which wavefront serves it and when). */
 typedef struct {
     uint64_t stream;
     uint64_t n;
@@ -322,14 +326,82 @@ typedef struct {
     uint32_t flags;
 } xg_request;
 
+/* Device scratch of xg_generate_batch on ctx for up to max_reqs requests and
+ * up to max_tiles tiles per call (0 if ctx is NULL, max_reqs is 0, or
+ * max_reqs + max_tiles > 2^20 or max_tiles > 65536).  It holds the planner's
+ * sort keys, prefix sums and queue items, the served table, the start states of
+ * tiles and the tile jump table: about 60 B per request plus 530 B per tile
+ * (1.1 KB for the 64-bit member) plus 130 KB when tiles are used. */
+size_t xg_batch_scratch_bytes(const xg_ctx *ctx, uint32_t max_reqs, uint32_t max_tiles);
 
-/* Device workspace of a batch: a work counter and an error flag (256 B). */
+/* Gives ctx the device scratch xg_generate_batch works in.
+ *   d_scratch   xg_batch_scratch_bytes(ctx, max_reqs, max_tiles) bytes,
+ *               256-byte aligned, owned by the caller, used by every later
+ *               xg_generate_batch / xg_autotune_batch on ctx (so those calls
+ *               must be ordered on one HIP stream); NULL detaches
+ *   tile_words  0, or L (a multiple of 64, 2^12 .. 2^30): a stream with a
+ *               single request of more than L words (and at most 256 tiles)
+ *               is served as tiles of L words run by separate wavefronts,
+ *               tile k from the request's start state jumped by k L words
+ *               (xg_skip's jump); the values are those of the unsplit request.
+ *               Section 2's member only (XG_ENOTSUP otherwise); max_tiles
+ *               bounds the tiles of one call (later long requests run whole).
+ * With tiles, computes z^(k L) mod P for k = 1 .. 255 on the host and copies
+ * them into the scratch on `stream`, then synchronises it.
+ * The first 256 bytes of d_scratch are the batch workspace: after a call,
+ * ((uint32_t *)d_scratch)[1] is 1 if a request was skipped (stream out of
+ * range, bad dtype or flags), else 0.
+ * Errors: XG_EINVAL, XG_ERANGE (scratch_bytes too small), XG_EALIGN,
+ * XG_ENOTSUP, XG_ENOMEM, XG_EHIP. */
+xg_status xg_set_batch_scratch(xg_ctx *ctx, void *d_scratch, size_t scratch_bytes, uint32_t max_reqs,
+                               uint32_t max_tiles, uint64_t tile_words, void *stream);
+
+/* Serves num_reqs requests in one call (Section 2: many independent
+ * subsequences, one per group of threads).  d_reqs is a table in device memory
+ * in the caller's order; same-stream requests are served in that order.  On
+ * the device, without a host round trip, the library
+ *   - groups the requests by stream (a sort of (stream, index) keys), keeping
+ *     table order inside each group;
+ *   - splits groups of one long request into tiles (xg_set_batch_scratch);
+ *   - orders the queue items (groups and tiles) by cost, largest first;
+ *   - serves them in one persistent launch whose wavefronts take items from
+ *     an atomic queue.
+ * The launch shape is the tuning cache's entry for (this device's
+ * architecture, its compute units, the handle's family, tune_key), written
+ * by xg_autotune_batch or loaded with xg_tune_cache_load; tune_key NULL or
+ * absent from the cache selects a default shape.  Only kernels are
+ * enqueued, so the call can be captured in a HIP graph and replayed (each
+ * replay serves the table again from the streams' current positions).
+ *   d_out   output buffer; every request's [out_offset, out_offset + n) must
+ *           lie inside it (the caller's guarantee, as for the plain calls)
+ * A request with stream >= num_streams, dtype other than XG_U32 / XG_F32 /
+ * XG_NORMAL, or flags != 0 is skipped and sets the scratch's error word.
+ * The further members take the same table as for xg_generate_batch_planned.
+ * Errors: XG_EINVAL (NULL pointer, no scratch attached), XG_EBUSY (num_reqs
+ * above the scratch's max_reqs), XG_EALIGN, XG_EHIP. */
+xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs, void *d_out,
+                            const char *tune_key, void *stream);
+
+/* Copies the table the last xg_generate_batch on ctx planned into host
+ * memory (for inspection and tests), after synchronising `stream`:
+ *   h_table    receives *num_entries served entries (at least max_entries):
+ *              the requests, grouped by stream in table order; a tile of a
+ *              split request appears as a segment entry (flags bit 0 set, bit 1
+ *              on its last tile, bits 8..15 the tile number k, bits 16..31 its
+ *              start-state slot; n and out_offset cover the tile's values)
+ *   h_groups   receives *num_groups + 1 offsets into h_table (at least
+ *              max_groups + 1): the queue items in serving order
+ * Errors: XG_EINVAL (NULL pointer, no scratch), XG_ERANGE (a buffer too
+ * small; the counts are still written), XG_EHIP. */
+xg_status xg_batch_read_plan(const xg_ctx *ctx, xg_request *h_table, uint32_t max_entries, uint32_t *h_groups,
+                             uint32_t max_groups, uint32_t *num_entries, uint32_t *num_groups, void *stream);
+
+/* Device workspace of xg_generate_batch_planned: a work counter, an error
+ * word and the table's counts (256 B). */
 size_t xg_batch_workspace_bytes(void);
 
-/* Orders a request table for the batched kernel (host memory only).
- * Requests on one stream keep their relative order and form one group that a
- * single wavefront serves in that order; groups are sorted by total words,
- * largest first, so the dynamic queue balances uneven lengths.
+/* Orders a request table on the host, as xg_generate_batch does on the device
+ * (without tiles), for callers that plan on the host.
  *   h_reqs      num_reqs requests (host)
  *   h_sorted    receives the ordered requests (host, num_reqs entries)
  *   h_groups    receives num_groups + 1 offsets into h_sorted (host, at least
@@ -345,9 +417,10 @@ xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t nu
                         uint64_t out_elems, xg_request *h_sorted, uint32_t *h_groups,
                         uint32_t *num_groups);
 
-/* Serves a planned table in one persistent launch (preceded by a small kernel
- * that clears the workspace, so the pair can be captured in a HIP graph and
- * replayed).  Wavefronts take groups from a device-side atomic queue.
+/* Serves a table planned by xg_plan_batch in one persistent launch (preceded
+ * by a small kernel that fills the workspace, so the pair can be captured in a
+ * HIP graph and replayed).  Wavefronts take groups from a device-side atomic
+ * queue.
  *   d_reqs, d_groups  device copies of xg_plan_batch's output (num_reqs
  *                     requests, num_groups + 1 offsets)
  *   num_groups        groups in the table
@@ -366,27 +439,69 @@ xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t nu
  * together (a half waits while its request has another dtype); store_words of
  * tune is not used, and d_out must be 8-byte aligned for the 64-bit member.
  * Errors: XG_EINVAL, XG_ERANGE, XG_EALIGN, XG_EHIP. */
-xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
-                            const uint32_t *d_groups, uint32_t num_groups, void *d_out,
-                            uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream);
+xg_status xg_generate_batch_planned(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
+                                    const uint32_t *d_groups, uint32_t num_groups, void *d_out,
+                                    uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream);
 
-/* Times candidate launch shapes of xg_generate_batch on the given table and
- * returns the fastest in *best (median of `reps` timed runs per shape after
- * one warm-up).  It works on a scratch copy of the state:
+/* Times candidate launch shapes of xg_generate_batch on the given table
+ * (array order, as for xg_generate_batch) and returns the fastest in *best
+ * (median of `reps` timed runs per shape after one warm-up).  The table is
+ * planned once in ctx's batch scratch; each run times the persistent launch
+ * (with the tiles' start states) on a scratch copy of the state:
  *   d_scratch_state  xg_family_state_bytes(family, num_streams of ctx) bytes,
  *                    overwritten
- *   d_scratch_out    out_elems elements, overwritten
- * so the streams of ctx do not advance.  Synchronises `stream`.
- * times_ms, if non-NULL, receives up to max_times (shape, time) records as
- * consecutive groups of 5 floats: waves_per_block, unroll, blocks_per_cu, ms,
- * store_words.  *num_times receives their count.
- * Errors: those of xg_generate_batch, XG_EHIP. */
-xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
-                            const uint32_t *d_groups, uint32_t num_groups,
-                            void *d_scratch_out, uint64_t out_elems,
-                            void *d_scratch_state, void *d_work, int reps, xg_tune *best,
-                            float *times_ms, uint32_t max_times, uint32_t *num_times,
-                            void *stream);
+ *   d_scratch_out    as large as the requests' outputs need, overwritten
+ * so the streams of ctx do not advance.  With tune_key non-NULL the best shape
+ * is stored in the tuning cache under (device architecture, compute units,
+ * family, tune_key), where xg_generate_batch looks it up.  Synchronises
+ * `stream`.  times_ms, if non-NULL, receives up to max_times (shape, time)
+ * records as consecutive groups of 5 floats: waves_per_block, unroll,
+ * blocks_per_cu, ms, store_words.  *num_times receives their count.
+ * Errors: those of xg_generate_batch, XG_EINVAL (tune_key not a valid key). */
+xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs, void *d_scratch_out,
+                            void *d_scratch_state, const char *tune_key, int reps, xg_tune *best,
+                            float *times_ms, uint32_t max_times, uint32_t *num_times, void *stream);
+
+/* ---- tuning cache ------------------------------------------------------------ */
+
+/* Batch launch shapes keyed by (arch, cus, family, tune_key): the device
+ * architecture name without feature suffixes (e.g. "gfx950"), its compute
+ * units, the family member, and the caller's name of the workload signature
+ * and its output types (e.g. "ragged65536/u32").  Keys are 1 .. 256
+ * printable characters without '"' or '\'.  The cache lives in the process
+ * and is thread-safe; the file named by the environment variable
+ * XG_TUNE_CACHE, if any, is merged in before the first lookup.
+ * File format (JSON): {"xg_tune_cache": 1, "entries": [{"arch": ..., "key":
+ * ..., "cus": ..., "family": ..., "waves_per_block": ..., "unroll": ...,
+ * "blocks_per_cu": ..., "store_words": ..., "ms": ...}, ...]}. */
+
+/* Merges the entries of a cache file (later entries replace equal keys).
+ * Errors: XG_EINVAL (unreadable, or not a valid cache file: then nothing is
+ * merged), XG_ENOMEM. */
+xg_status xg_tune_cache_load(const char *path);
+
+/* Writes every entry to path (through a temporary file renamed into place).
+ * Errors: XG_EINVAL (cannot write), XG_ENOMEM. */
+xg_status xg_tune_cache_save(const char *path);
+
+/* Stores a shape (and its measured ms, or NaN) under a key.
+ * Errors: XG_EINVAL (bad key, cus 0, unknown family, shape out of range). */
+xg_status xg_tune_cache_put(const char *arch, uint32_t cus, uint32_t family, const char *tune_key,
+                            const xg_tune *tune, float ms);
+
+/* Looks a key up; *ms (if non-NULL) receives its time, or -1.
+ * Errors: XG_EINVAL (bad key or NULL tune), XG_ERANGE (no such entry). */
+xg_status xg_tune_cache_get(const char *arch, uint32_t cus, uint32_t family, const char *tune_key,
+                            xg_tune *tune, float *ms);
+
+/* Number of entries; and removal of all of them. */
+uint32_t xg_tune_cache_size(void);
+void xg_tune_cache_clear(void);
+
+/* The (arch, cus) part of the key under which calls on ctx look shapes up:
+ * arch receives the architecture name (NUL-terminated, at most arch_len
+ * bytes with the NUL).  Errors: XG_EINVAL (NULL or arch_len too small). */
+xg_status xg_tune_identity(const xg_ctx *ctx, char *arch, size_t arch_len, uint32_t *cus);
 
 /* ---- serving: continuous batching over device-resident streams ------------- */
 
@@ -406,12 +521,15 @@ typedef struct xg_server xg_server;
 typedef struct {
     uint32_t num_lanes;   /* HIP streams, each with at most one batch in flight: 1 .. 8 */
     uint32_t max_batch;   /* table entries per batch (requests and segments): 1 .. 65536 */
-    xg_tune tune;         /* batch launch shape; all zero selects the default */
+    xg_tune tune;         /* batch launch shape; all zero: the tuning cache's entry for
+                             tune_key if there is one, else the default */
     uint64_t segment_words; /* 0, or L (a multiple of 64, 2^12 .. 2^30): a request of more
                                than L words is served as up to 256 segments of L words run
                                by separate wavefronts, segment k starting from the request's
                                start state jumped by k L words (xg_skip's jump); the values
                                are those of the unsplit request */
+    const char *tune_key; /* NULL, or a tuning-cache key (see xg_tune_cache_get) looked up
+                             at creation when tune is all zero */
 } xg_server_config;
 
 typedef struct {

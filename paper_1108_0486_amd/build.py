@@ -14,7 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libxg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["xg_kernels.hip", "xg_family.hip", "xg_util.hip", "xg_api.cpp", "xg_serve.cpp", "xg_jump.cpp", "xg_plan.cpp"]
+SOURCES = ["xg_kernels.hip", "xg_family.hip", "xg_plan_dev.hip", "xg_util.hip", "xg_api.cpp", "xg_serve.cpp",
+           "xg_jump.cpp", "xg_plan.cpp", "xg_tune.cpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions in generated code.
 # -ffp-contract=off: every FP32 operation rounds as written (no implicit FMA).
@@ -26,15 +27,16 @@ FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+def build(verbose: bool = False, out: str | None = None) -> str:
+    target = out or LIB_PATH
+    tmp = target + ".tmp%d" % os.getpid()
     cmd = [HIPCC, *FLAGS, "-I", INCLUDE, "-I", CSRC,
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB_PATH)
-    return LIB_PATH
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -18,7 +18,7 @@ namespace {
 
 constexpr uint64_t kMaxStreams = 0xFFFFFFFFull;
 
-xg_status current_gfx950(int *device, int *num_cus) {
+xg_status current_gfx950(int *device, int *num_cus, char *arch = nullptr, size_t arch_len = 0) {
   int d = 0;
   if (hipGetDevice(&d) != hipSuccess) return XG_EHIP;
   hipDeviceProp_t prop;
@@ -26,6 +26,11 @@ xg_status current_gfx950(int *device, int *num_cus) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return XG_ENOTSUP;
   *device = d;
   *num_cus = prop.multiProcessorCount;
+  if (arch && arch_len) {  // the name up to its first ':' (feature suffixes)
+    size_t i = 0;
+    for (; i + 1 < arch_len && prop.gcnArchName[i] && prop.gcnArchName[i] != ':'; ++i) arch[i] = prop.gcnArchName[i];
+    arch[i] = '\0';
+  }
   return XG_OK;
 }
 
@@ -38,16 +43,19 @@ xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num
   if (state_bytes / per_stream < num_streams) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_state) % 16 != 0) return XG_EALIGN;
   int dev = 0, cus = 0;
-  const xg_status st = current_gfx950(&dev, &cus);
+  char arch[sizeof(xg_ctx::arch)];
+  const xg_status st = current_gfx950(&dev, &cus, arch, sizeof arch);
   if (st != XG_OK) return st;
-  xg_ctx *c = new (std::nothrow) xg_ctx;
+  xg_ctx *c = new (std::nothrow) xg_ctx{};
   if (!c) return XG_ENOMEM;
   c->d_state = static_cast<uint32_t *>(d_state);
   c->num_streams = num_streams;
   c->device = dev;
   c->num_cus = cus;
+  std::memcpy(c->arch, arch, sizeof arch);
   c->plain = xg::kDefaultPlain;
   c->family = family;
+  c->d_batch = nullptr;
   *out = c;
   return XG_OK;
 }
@@ -181,6 +189,62 @@ bool tune_to_shape(const xg_tune *t, uint32_t blocks_per_cu, xg::Shape *s) {
   const uint32_t sw = t->store_words ? t->store_words : (t->unroll >= 4 ? 4u : 1u);
   *s = xg::Shape{t->waves_per_block, t->unroll, blocks_per_cu, sw};
   return xg::shape_valid(*s);
+}
+
+// Families with a batch kernel.
+bool batch_member(const xg_ctx *ctx) {
+  return ctx->family == XG_FAMILY_R128_W32 || ctx->family == XG_FAMILY_R64_W32 || ctx->family == XG_FAMILY_R64_W64;
+}
+
+// Tile start-state slots are numbered in 16 bits of a table entry's flags.
+constexpr uint32_t kMaxTileSlots = 65536;
+
+xg::PlanLayout batch_layout(const xg_ctx *ctx, uint32_t max_reqs, uint32_t max_tiles) {
+  const uint32_t jump_bytes = (uint32_t)(xg::member_degree(ctx->family) / 8);
+  return xg::plan_layout(max_reqs, max_tiles, xg::family_state_bytes(ctx->family), jump_bytes);
+}
+
+// The batch launch shape for tune_key: the tuning cache's entry for this
+// handle's device and family, else the default.
+xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, xg::Shape *shape) {
+  *shape = xg::kDefaultBatch;
+  if (!tune_key) return XG_OK;
+  xg_tune t;
+  const xg_status st = xg_tune_cache_get(ctx->arch, ctx->num_cus, ctx->family, tune_key, &t, nullptr);
+  if (st == XG_EINVAL) return XG_EINVAL;
+  xg::Shape cached;
+  if (st == XG_OK && tune_to_shape(&t, t.blocks_per_cu, &cached)) *shape = cached;
+  return XG_OK;
+}
+
+// Plans num_reqs requests into the scratch at base (tiles as configured on
+// ctx).
+hipError_t plan_on_device(const xg_ctx *ctx, void *base, const xg::PlanLayout &layout, const xg_request *d_reqs,
+                          uint32_t num_reqs, hipStream_t s) {
+  const xg::PlanPtrs p = xg::plan_ptrs(base, layout);
+  return xg::launch_plan(p, layout, d_reqs, num_reqs, ctx->num_streams, ctx->tile_words,
+                         ctx->tile_words ? ctx->batch_max_tiles : 0, s);
+}
+
+// Serves the table the planner left in the scratch at base on the streams at
+// state: the tiles' start states, then the persistent launch.  requeue
+// re-arms the queue first (to serve the same plan again).
+hipError_t serve_planned(const xg_ctx *ctx, void *base, const xg::PlanLayout &layout, uint32_t num_reqs,
+                         uint32_t *state, void *d_out, const xg::Shape &shape, hipStream_t s, bool requeue = false) {
+  const xg::PlanPtrs p = xg::plan_ptrs(base, layout);
+  const uint32_t tiles = ctx->tile_words ? ctx->batch_max_tiles : 0;
+  const uint32_t max_items = num_reqs + tiles;
+  hipError_t e = requeue ? xg::launch_work_requeue(p.work, s) : hipSuccess;
+  if (e != hipSuccess) return e;
+  if (!paper_member(ctx))
+    return xg::launch_family_batch(ctx->family, shape, ctx->num_cus, reinterpret_cast<unsigned char *>(state),
+                                   ctx->num_streams, p.table, p.offs, max_items, d_out, UINT64_MAX, p.work, s);
+  const xg::SegmentArgs seg{p.jump, ctx->tile_words, tiles ? xg::kMaxSegments - 1 : 0u, p.stage, tiles};
+  if (tiles) e = xg::launch_seg_starts(state, ctx->num_streams, p.table, max_items, p.work, seg, s);
+  if (e == hipSuccess)
+    e = xg::launch_batch(shape, ctx->num_cus, state, ctx->num_streams, p.table, p.offs, max_items,
+                         static_cast<uint32_t *>(d_out), UINT64_MAX, p.work, s, tiles ? &seg : nullptr);
+  return e;
 }
 
 }  // namespace
@@ -376,12 +440,11 @@ xg_status xg_family_jump_polynomial(uint32_t family, uint64_t J, uint64_t *h_g) 
 
 size_t xg_batch_workspace_bytes(void) { return 256; }
 
-xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
-                            const uint32_t *d_groups, uint32_t num_groups, void *d_out,
-                            uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream) {
+xg_status xg_generate_batch_planned(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
+                                    const uint32_t *d_groups, uint32_t num_groups, void *d_out,
+                                    uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream) {
   if (!ctx || !d_reqs || !d_groups || !d_out || !d_work) return XG_EINVAL;
-  const bool member = !paper_member(ctx);
-  if (member && ctx->family != XG_FAMILY_R64_W32 && ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
+  if (!batch_member(ctx)) return XG_ENOTSUP;
   if (num_groups > num_reqs) return XG_ERANGE;
   const uintptr_t out_align = ctx->family == XG_FAMILY_R64_W64 ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_groups) % 4 ||
@@ -392,37 +455,135 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   xg_status st = check_ctx_device(ctx);
   if (st != XG_OK) return st;
   if (num_groups == 0) return XG_OK;
-  if (member) {
-    const hipError_t e = xg::launch_family_batch(ctx->family, shape, ctx->num_cus,
-                                                 reinterpret_cast<unsigned char *>(ctx->d_state), ctx->num_streams,
-                                                 d_reqs, num_reqs, d_groups, num_groups, d_out, out_elems,
-                                                 static_cast<uint32_t *>(d_work), static_cast<hipStream_t>(stream));
-    return e == hipSuccess ? XG_OK : XG_EHIP;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  uint32_t *work = static_cast<uint32_t *>(d_work);
+  hipError_t e = xg::launch_work_init(work, num_groups, num_reqs, s);
+  if (e == hipSuccess) {
+    if (paper_member(ctx))
+      e = xg::launch_batch(shape, ctx->num_cus, ctx->d_state, ctx->num_streams, d_reqs, d_groups, num_groups,
+                           static_cast<uint32_t *>(d_out), out_elems, work, s);
+    else
+      e = xg::launch_family_batch(ctx->family, shape, ctx->num_cus, reinterpret_cast<unsigned char *>(ctx->d_state),
+                                  ctx->num_streams, d_reqs, d_groups, num_groups, d_out, out_elems, work, s);
   }
-  const hipError_t e = xg::launch_batch(shape, ctx->num_cus, ctx->d_state, ctx->num_streams, d_reqs,
-                                        num_reqs, d_groups, num_groups,
-                                        static_cast<uint32_t *>(d_out), out_elems,
-                                        static_cast<uint32_t *>(d_work),
-                                        static_cast<hipStream_t>(stream));
   return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
+size_t xg_batch_scratch_bytes(const xg_ctx *ctx, uint32_t max_reqs, uint32_t max_tiles) {
+  if (!ctx || max_reqs == 0 || max_tiles > kMaxTileSlots ||
+      (uint64_t)max_reqs + max_tiles > xg::kPlanMaxElems)
+    return 0;
+  return batch_layout(ctx, max_reqs, max_tiles).total;
+}
+
+xg_status xg_set_batch_scratch(xg_ctx *ctx, void *d_scratch, size_t scratch_bytes, uint32_t max_reqs,
+                               uint32_t max_tiles, uint64_t tile_words, void *stream) {
+  if (!ctx) return XG_EINVAL;
+  if (!d_scratch) {
+    ctx->d_batch = nullptr;
+    return XG_OK;
+  }
+  if (!batch_member(ctx)) return XG_ENOTSUP;
+  if (max_reqs == 0 || max_tiles > kMaxTileSlots || (uint64_t)max_reqs + max_tiles > xg::kPlanMaxElems)
+    return XG_EINVAL;
+  const bool tiles = tile_words != 0 && max_tiles != 0;
+  if (tile_words && (tile_words % 64 || tile_words < (1ull << 12) || tile_words > (1ull << 30))) return XG_EINVAL;
+  if (tiles && !paper_member(ctx)) return XG_ENOTSUP;
+  if (reinterpret_cast<uintptr_t>(d_scratch) % 256) return XG_EALIGN;
+  const xg::PlanLayout layout = batch_layout(ctx, max_reqs, tiles ? max_tiles : 0);
+  if (scratch_bytes < layout.total) return XG_ERANGE;
+  xg_status st = check_ctx_device(ctx);
+  if (st != XG_OK) return st;
+  if (tiles) {
+    std::vector<uint64_t> table;
+    try {
+      table.resize((size_t)(xg::kMaxSegments - 1) * 64);
+    } catch (const std::bad_alloc &) {
+      return XG_ENOMEM;
+    }
+    if (!xg::jump_table(ctx->family, tile_words, xg::kMaxSegments - 1, table.data())) return XG_ENOTSUP;
+    const hipStream_t s = static_cast<hipStream_t>(stream);
+    const xg::PlanPtrs p = xg::plan_ptrs(d_scratch, layout);
+    if (hipMemcpyAsync(p.jump, table.data(), table.size() * sizeof(uint64_t), hipMemcpyHostToDevice, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return XG_EHIP;
+  }
+  ctx->d_batch = d_scratch;
+  ctx->batch_layout = layout;
+  ctx->batch_max_reqs = max_reqs;
+  ctx->batch_max_tiles = tiles ? max_tiles : 0;
+  ctx->tile_words = tiles ? tile_words : 0;
+  return XG_OK;
+}
+
+xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs, void *d_out,
+                            const char *tune_key, void *stream) {
+  if (!ctx || !d_reqs || !d_out || !ctx->d_batch) return XG_EINVAL;
+  if (!batch_member(ctx)) return XG_ENOTSUP;
+  if (num_reqs > ctx->batch_max_reqs) return XG_EBUSY;
+  const uintptr_t out_align = ctx->family == XG_FAMILY_R64_W64 ? 8 : 4;
+  if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_out) % out_align) return XG_EALIGN;
+  xg::Shape shape;
+  xg_status st = batch_shape(ctx, tune_key, &shape);
+  if (st != XG_OK) return st;
+  st = check_ctx_device(ctx);
+  if (st != XG_OK) return st;
+  // An empty table still runs the planner, which clears the workspace's
+  // counts and error word.
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  hipError_t e = plan_on_device(ctx, ctx->d_batch, ctx->batch_layout, d_reqs, num_reqs, s);
+  if (e == hipSuccess)
+    e = serve_planned(ctx, ctx->d_batch, ctx->batch_layout, num_reqs, ctx->d_state, d_out, shape, s);
+  return e == hipSuccess ? XG_OK : XG_EHIP;
+}
+
+xg_status xg_batch_read_plan(const xg_ctx *ctx, xg_request *h_table, uint32_t max_entries, uint32_t *h_groups,
+                             uint32_t max_groups, uint32_t *num_entries, uint32_t *num_groups, void *stream) {
+  if (!ctx || !ctx->d_batch || !h_table || !h_groups || !num_entries || !num_groups) return XG_EINVAL;
+  const hipStream_t s = static_cast<hipStream_t>(stream);
+  const xg::PlanPtrs p = xg::plan_ptrs(ctx->d_batch, ctx->batch_layout);
+  uint32_t counts[4];
+  if (hipMemcpyAsync(counts, p.work, sizeof counts, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return XG_EHIP;
+  *num_groups = counts[2];
+  *num_entries = counts[3];
+  if (counts[3] > max_entries || counts[2] > max_groups) return XG_ERANGE;
+  if (hipMemcpyAsync(h_table, p.table, (size_t)counts[3] * sizeof(xg_request), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(h_groups, p.offs, ((size_t)counts[2] + 1) * sizeof(uint32_t), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return XG_EHIP;
+  return XG_OK;
 }
 
 constexpr int kMaxReps = 100;  // timed repetitions per candidate shape
 
-xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs,
-                            const uint32_t *d_groups, uint32_t num_groups, void *d_scratch_out,
-                            uint64_t out_elems, void *d_scratch_state, void *d_work, int reps,
-                            xg_tune *best, float *times_ms, uint32_t max_times,
-                            uint32_t *num_times, void *stream) {
-  if (!ctx || !best || !d_scratch_state || reps < 1 || reps > kMaxReps) return XG_EINVAL;
-  const bool member = !paper_member(ctx);
-  if (member && ctx->family != XG_FAMILY_R64_W32 && ctx->family != XG_FAMILY_R64_W64) return XG_ENOTSUP;
+xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs, void *d_scratch_out,
+                            void *d_scratch_state, const char *tune_key, int reps, xg_tune *best,
+                            float *times_ms, uint32_t max_times, uint32_t *num_times, void *stream) {
   if (num_times) *num_times = 0;
+  if (!ctx || !d_reqs || !d_scratch_out || !best || !d_scratch_state || reps < 1 || reps > kMaxReps ||
+      !ctx->d_batch)
+    return XG_EINVAL;
+  if (!batch_member(ctx)) return XG_ENOTSUP;
+  if (num_reqs > ctx->batch_max_reqs) return XG_EBUSY;
+  if (tune_key) {  // a valid key (the lookup's own check)
+    xg_tune probe;
+    if (xg_tune_cache_get(ctx->arch, ctx->num_cus, ctx->family, tune_key, &probe, nullptr) == XG_EINVAL)
+      return XG_EINVAL;
+  }
+  const uintptr_t out_align = ctx->family == XG_FAMILY_R64_W64 ? 8 : 4;
+  if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_scratch_out) % out_align ||
+      reinterpret_cast<uintptr_t>(d_scratch_state) % 16)
+    return XG_EALIGN;
+  xg_status result = check_ctx_device(ctx);
+  if (result != XG_OK) return result;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t state_bytes = xg_family_state_bytes(ctx->family, ctx->num_streams);
-  xg_ctx scratch = *ctx;
-  scratch.d_state = static_cast<uint32_t *>(d_scratch_state);
-  if (reinterpret_cast<uintptr_t>(d_scratch_state) % 16) return XG_EALIGN;
+  if (plan_on_device(ctx, ctx->d_batch, ctx->batch_layout, d_reqs, num_reqs, s) != hipSuccess) return XG_EHIP;
 
   static const uint32_t kWpb[] = {1, 2, 4, 8, 16};
   static const uint32_t kUnroll[] = {1, 2, 4, 8};
@@ -434,33 +595,33 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
     return XG_EHIP;
   }
   float best_ms = -1.f;
-  xg_status result = XG_OK;
   uint32_t recorded = 0;
+  const bool member = !paper_member(ctx);
   for (uint32_t wpb : kWpb) {
     for (uint32_t un : kUnroll) {
       for (uint32_t bpc : kBpc) {
         for (uint32_t sw : kStoreWords) {
-          if (wpb * bpc > 32) continue;  // more waves than a compute unit holds
+          if (result != XG_OK) break;
+          if (wpb * bpc > 32) continue;                 // more waves than a compute unit holds
           if (sw == 4 && (un < 4 || member)) continue;  // the members' batch kernel has no wide stores
           const xg_tune cand{wpb, un, bpc, sw};
+          xg::Shape shape;
+          (void)tune_to_shape(&cand, bpc, &shape);
           float ms[kMaxReps];
           int nms = 0;
-          for (int rep = 0; rep <= reps && result == XG_OK; ++rep) {
-            if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) !=
-                hipSuccess) {
-              result = XG_EHIP;
-              break;
-            }
-            if (hipEventRecord(t0, s) != hipSuccess) { result = XG_EHIP; break; }
-            result = xg_generate_batch(&scratch, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out,
-                                       out_elems, &cand, d_work, stream);
-            if (result != XG_OK) break;
-            if (hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess) {
-              result = XG_EHIP;
-              break;
-            }
+          for (int rep = 0; rep <= reps; ++rep) {
             float t = 0.f;
-            if (hipEventElapsedTime(&t, t0, t1) != hipSuccess) { result = XG_EHIP; break; }
+            if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) !=
+                    hipSuccess ||
+                hipEventRecord(t0, s) != hipSuccess ||
+                serve_planned(ctx, ctx->d_batch, ctx->batch_layout, num_reqs,
+                              static_cast<uint32_t *>(d_scratch_state), d_scratch_out, shape, s, true) !=
+                    hipSuccess ||
+                hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
+                hipEventElapsedTime(&t, t0, t1) != hipSuccess) {
+              result = XG_EHIP;
+              break;
+            }
             if (rep > 0) ms[nms++] = t;  // rep 0 is the warm-up
           }
           if (result != XG_OK) break;
@@ -476,16 +637,22 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
             *best = cand;
           }
         }
-        if (result != XG_OK) break;
       }
-      if (result != XG_OK) break;
     }
-    if (result != XG_OK) break;
   }
   (void)hipEventDestroy(t0);
   (void)hipEventDestroy(t1);
   if (num_times) *num_times = recorded;
+  if (result == XG_OK && tune_key) result = xg_tune_cache_put(ctx->arch, ctx->num_cus, ctx->family, tune_key,
+                                                              best, best_ms);
   return result;
+}
+
+xg_status xg_tune_identity(const xg_ctx *ctx, char *arch, size_t arch_len, uint32_t *cus) {
+  if (!ctx || !arch || !cus || arch_len <= std::strlen(ctx->arch)) return XG_EINVAL;
+  std::memcpy(arch, ctx->arch, std::strlen(ctx->arch) + 1);
+  *cus = (uint32_t)ctx->num_cus;
+  return XG_OK;
 }
 
 const char *xg_strerror(xg_status status) {

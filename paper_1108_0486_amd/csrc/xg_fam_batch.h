@@ -11,14 +11,16 @@
 
 namespace xg {
 
-// Clears the 256-byte workspace, then serves the planned table (num_groups
-// groups of reqs) with blocks_per_cu x CUs persistent workgroups of
-// waves_per_block wavefronts, two groups per wavefront; shape.store_words is
-// not used.  out holds out_elems elements of the member's word width.
+// Serves the table described by the workspace (work[2] groups of reqs,
+// work[3] entries; see launch_work_init) with blocks_per_cu x CUs persistent
+// workgroups of waves_per_block wavefronts, two groups per wavefront (fewer
+// workgroups when max_groups, an upper bound of work[2], is smaller);
+// shape.store_words is not used.  out holds out_elems elements of the
+// member's word width.
 hipError_t launch_family_batch(uint32_t family, const Shape &shape, int num_cus, unsigned char *state,
-                               uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
-                               const uint32_t *groups, uint32_t num_groups, void *out, uint64_t out_elems,
-                               uint32_t *work, hipStream_t stream);
+                               uint64_t num_streams, const xg_request *reqs, const uint32_t *groups,
+                               uint32_t max_groups, void *out, uint64_t out_elems, uint32_t *work,
+                               hipStream_t stream);
 
 // Byte offset of the 64-bit position in one stream's state of a family.
 uint32_t family_pos_offset(uint32_t family);

@@ -28,6 +28,7 @@
 #include "xg_device.h"
 #include "xg_normal.h"
 #include "xg_internal.h"
+#include "xg_launch.h"
 #include "xg_fam_batch.h"
 
 namespace xg {
@@ -522,7 +523,7 @@ __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict
 // (XG_NORMAL), in elements of the member's word width; a request or group
 // that fails the bounds check (stream, dtype, flags 0, output range, group
 // offsets) is skipped and sets work[1].  Every wavefront exits once the queue
-// passes num_groups.
+// passes work[2] groups.
 // ---------------------------------------------------------------------------
 // One generator step of the stream at st, of which this half writes the
 // first `head` words (head < 32, per half; 0 writes nothing and leaves the
@@ -562,10 +563,6 @@ __device__ __forceinline__ void fam_head(unsigned char *__restrict__ st, bool on
   }
 }
 
-__global__ void k_fam_clear_work(uint32_t *work) {
-  if (threadIdx.x < 64) work[threadIdx.x] = 0u;
-}
-
 // Lane src's value of v, held in scalar registers.
 __device__ __forceinline__ uint64_t lane_value(uint64_t v, int src) {
   const uint64_t x = shfl_word(v, src);
@@ -575,10 +572,11 @@ __device__ __forceinline__ uint64_t lane_value(uint64_t v, int src) {
 
 template <class M, int UNROLL>
 __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ state, uint64_t num_streams,
-                                                    const xg_request *__restrict__ reqs, uint32_t num_reqs,
-                                                    const uint32_t *__restrict__ groups, uint32_t num_groups,
+                                                    const xg_request *__restrict__ reqs,
+                                                    const uint32_t *__restrict__ groups,
                                                     void *__restrict__ out_v, uint64_t out_elems,
                                                     uint32_t *__restrict__ work) {
+  const uint32_t num_groups = work[2], num_reqs = work[3];
   using word = typename M::word;
   constexpr uint32_t kInt = sizeof(word) == 4 ? kU32 : kU64;
   constexpr uint32_t kReal = sizeof(word) == 4 ? kF32 : kF64;
@@ -691,15 +689,17 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
 }
 
 template <class M>
-void launch_fam_batch_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t num_streams,
-                        const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups, uint32_t num_groups,
-                        void *out, uint64_t out_elems, uint32_t *work, hipStream_t stream) {
+hipError_t launch_fam_batch_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t num_streams,
+                              const xg_request *reqs, const uint32_t *groups, void *out, uint64_t out_elems,
+                              uint32_t *work, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_fam_batch<M, 1>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    case 2: hipLaunchKernelGGL((k_fam_batch<M, 2>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    case 4: hipLaunchKernelGGL((k_fam_batch<M, 4>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
-    default: hipLaunchKernelGGL((k_fam_batch<M, 8>), grid, block, 0, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work); break;
+    case 1: e = launch((k_fam_batch<M, 1>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
+    case 2: e = launch((k_fam_batch<M, 2>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
+    case 4: e = launch((k_fam_batch<M, 4>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
+    default: e = launch((k_fam_batch<M, 8>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
   }
+  return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -780,21 +780,23 @@ __global__ __launch_bounds__(256) void k_fam_skip(unsigned char *__restrict__ st
 }
 
 template <class M, uint32_t KIND, bool FILL>
-void launch_fam_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t first,
+hipError_t launch_fam_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t first,
                   uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   switch (unroll) {
-    case 1: hipLaunchKernelGGL((k_fam_generate<M, KIND, 1, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
-    case 2: hipLaunchKernelGGL((k_fam_generate<M, KIND, 2, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
-    case 4: hipLaunchKernelGGL((k_fam_generate<M, KIND, 4, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
-    default: hipLaunchKernelGGL((k_fam_generate<M, KIND, 8, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 1: e = launch((k_fam_generate<M, KIND, 1, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 2: e = launch((k_fam_generate<M, KIND, 2, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 4: e = launch((k_fam_generate<M, KIND, 4, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
+    default: e = launch((k_fam_generate<M, KIND, 8, FILL>), grid, block, 0, stream, state, first, count, n, out); break;
   }
+  return e;
 }
 
 template <class M, uint32_t KIND>
-void launch_fam_layout(bool fill, uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t first,
-                       uint64_t count, uint64_t n, void *out, hipStream_t stream) {
-  if (fill) launch_fam_k<M, KIND, true>(unroll, grid, block, state, first, count, n, out, stream);
-  else launch_fam_k<M, KIND, false>(unroll, grid, block, state, first, count, n, out, stream);
+hipError_t launch_fam_layout(bool fill, uint32_t unroll, dim3 grid, dim3 block, unsigned char *state,
+                             uint64_t first, uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  if (fill) return launch_fam_k<M, KIND, true>(unroll, grid, block, state, first, count, n, out, stream);
+  return launch_fam_k<M, KIND, false>(unroll, grid, block, state, first, count, n, out, stream);
 }
 
 }  // namespace
@@ -819,92 +821,93 @@ uint32_t family_pos_offset(uint32_t family) {
 
 hipError_t launch_family_init(uint32_t family, unsigned char *state, uint64_t num_streams, uint64_t seed,
                               hipStream_t stream) {
+  hipError_t e = hipSuccess;
   const uint64_t pairs = (num_streams + 1) / 2;
   const dim3 grid((uint32_t)((pairs + 3) / 4)), block(256);
   if (family == XG_FAMILY_R64_W32)
-    hipLaunchKernelGGL(k_fam_init<MemberN2048>, grid, block, 0, stream, state, num_streams, seed);
+    e = launch(k_fam_init<MemberN2048>, grid, block, 0, stream, state, num_streams, seed);
   else if (family == XG_FAMILY_R64_W64)
-    hipLaunchKernelGGL(k_fam_init<MemberW64>, grid, block, 0, stream, state, num_streams, seed);
+    e = launch(k_fam_init<MemberW64>, grid, block, 0, stream, state, num_streams, seed);
   else
     return hipErrorInvalidValue;
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_family_skip(uint32_t family, unsigned char *state, uint64_t first, uint64_t count, uint64_t J,
                               const JumpPoly *g, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   const uint64_t pairs = (count + 1) / 2;
   const dim3 grid((uint32_t)((pairs + 3) / 4)), block(256);
   JumpPoly zero{};
   const JumpPoly &gp = g ? *g : zero;
   if (family == XG_FAMILY_R64_W32) {
-    if (g) hipLaunchKernelGGL((k_fam_skip<MemberN2048, true>), grid, block, 4 * 192 * 4, stream, state, first, count, J, gp);
-    else hipLaunchKernelGGL((k_fam_skip<MemberN2048, false>), grid, block, 0, stream, state, first, count, J, gp);
+    if (g) e = launch((k_fam_skip<MemberN2048, true>), grid, block, 4 * 192 * 4, stream, state, first, count, J, gp);
+    else e = launch((k_fam_skip<MemberN2048, false>), grid, block, 0, stream, state, first, count, J, gp);
   } else if (family == XG_FAMILY_R64_W64) {
-    if (g) hipLaunchKernelGGL((k_fam_skip<MemberW64, true>), grid, block, 4 * 192 * 8, stream, state, first, count, J, gp);
-    else hipLaunchKernelGGL((k_fam_skip<MemberW64, false>), grid, block, 0, stream, state, first, count, J, gp);
+    if (g) e = launch((k_fam_skip<MemberW64, true>), grid, block, 4 * 192 * 8, stream, state, first, count, J, gp);
+    else e = launch((k_fam_skip<MemberW64, false>), grid, block, 0, stream, state, first, count, J, gp);
   } else {
     return hipErrorInvalidValue;
   }
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_family_generate(uint32_t family, Kind kind, bool fill, const Shape &shape, unsigned char *state,
                                   uint64_t first, uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   const uint64_t pairs = (count + 1) / 2;
   const uint64_t wpb = shape.waves_per_block;
   const dim3 grid((uint32_t)((pairs + wpb - 1) / wpb)), block((uint32_t)(wpb * kWave));
   if (family == XG_FAMILY_R64_W32 && (kind == kNormal || kind == kMoments)) {
     float *o = static_cast<float *>(out);
     if (kind == kNormal)
-      hipLaunchKernelGGL((k_fam_normals<MemberN2048, false>), grid, block, 0, stream, state, first, count, n, out,
+      e = launch((k_fam_normals<MemberN2048, false>), grid, block, 0, stream, state, first, count, n, out,
                          nullptr);
     else
-      hipLaunchKernelGGL((k_fam_normals<MemberN2048, true>), grid, block, 0, stream, state, first, count, n, nullptr,
+      e = launch((k_fam_normals<MemberN2048, true>), grid, block, 0, stream, state, first, count, n, nullptr,
                          o);
-    return hipGetLastError();
+    return e;
   }
   if (family == XG_FAMILY_R64_W64 && (kind == kNormal || kind == kMoments)) {
     if (kind == kNormal)
-      hipLaunchKernelGGL((k_fam_normals<MemberW64, false>), grid, block, 0, stream, state, first, count, n, out,
+      e = launch((k_fam_normals<MemberW64, false>), grid, block, 0, stream, state, first, count, n, out,
                          nullptr);
     else
-      hipLaunchKernelGGL((k_fam_normals<MemberW64, true>), grid, block, 0, stream, state, first, count, n, nullptr,
+      e = launch((k_fam_normals<MemberW64, true>), grid, block, 0, stream, state, first, count, n, nullptr,
                          out);
-    return hipGetLastError();
+    return e;
   }
   if (family == XG_FAMILY_R64_W32 && kind == kU32)
-    launch_fam_layout<MemberN2048, kU32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+    e = launch_fam_layout<MemberN2048, kU32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
   else if (family == XG_FAMILY_R64_W32 && kind == kF32)
-    launch_fam_layout<MemberN2048, kF32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+    e = launch_fam_layout<MemberN2048, kF32>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
   else if (family == XG_FAMILY_R64_W64 && kind == kU64)
-    launch_fam_layout<MemberW64, kU64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+    e = launch_fam_layout<MemberW64, kU64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
   else if (family == XG_FAMILY_R64_W64 && kind == kF64)
-    launch_fam_layout<MemberW64, kF64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
+    e = launch_fam_layout<MemberW64, kF64>(fill, shape.unroll, grid, block, state, first, count, n, out, stream);
   else
     return hipErrorInvalidValue;
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_family_batch(uint32_t family, const Shape &shape, int num_cus, unsigned char *state,
-                               uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
-                               const uint32_t *groups, uint32_t num_groups, void *out, uint64_t out_elems,
-                               uint32_t *work, hipStream_t stream) {
+                               uint64_t num_streams, const xg_request *reqs, const uint32_t *groups,
+                               uint32_t max_groups, void *out, uint64_t out_elems, uint32_t *work,
+                               hipStream_t stream) {
   if (family != XG_FAMILY_R64_W32 && family != XG_FAMILY_R64_W64) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_fam_clear_work, dim3(1), dim3(64), 0, stream, work);
-  const hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const uint64_t pairs = ((uint64_t)num_groups + 1) / 2;
+  hipError_t e = hipSuccess;
+  const uint64_t pairs = ((uint64_t)max_groups + 1) / 2;
   uint64_t blocks = (uint64_t)(num_cus > 0 ? num_cus : 1) * shape.blocks_per_cu;
   const uint64_t need = (pairs + shape.waves_per_block - 1) / shape.waves_per_block;
   if (need < blocks) blocks = need ? need : 1;
   const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
   if (family == XG_FAMILY_R64_W32)
-    launch_fam_batch_k<MemberN2048>(shape.unroll, grid, block, state, num_streams, reqs, num_reqs, groups,
-                                    num_groups, out, out_elems, work, stream);
+    e = launch_fam_batch_k<MemberN2048>(shape.unroll, grid, block, state, num_streams, reqs, groups, out,
+                                        out_elems, work, stream);
   else
-    launch_fam_batch_k<MemberW64>(shape.unroll, grid, block, state, num_streams, reqs, num_reqs, groups,
-                                  num_groups, out, out_elems, work, stream);
-  return hipGetLastError();
+    e = launch_fam_batch_k<MemberW64>(shape.unroll, grid, block, state, num_streams, reqs, groups, out,
+                                      out_elems, work, stream);
+  return e;
 }
 
 }  // namespace xg

@@ -9,12 +9,14 @@
 
 namespace xg {
 
-// Request flags of server-built tables (the public batch call takes flags 0).
-// A segment covers words [k L, k L + n') of a longer request on its stream: it
-// reads the stream's state, jumps by k L (jump_table entry k - 1 holds
-// z^(k L) mod P) and generates its n values; it never writes the stream's
-// state.  The last segment writes the end state to staging slot (flags >> 16),
-// which k_commit copies into the stream's state after the batch.
+// Request flags of library-built tables (callers' requests take flags 0).  A
+// segment covers values [k L, k L + n') of a longer request on its stream
+// (bits 8..15: k; bits 16..31: its staging slot).  Its start state is the
+// stream's state jumped by k L words (jump_table entry k - 1 holds
+// z^(k L) mod P), staged in its slot before the batch; it generates its n'
+// values from there.  Only the last segment (kReqLast) writes the stream's
+// state, so a request split into segments must be alone on its stream within
+// its table.
 constexpr uint32_t kReqSegment = 1u;
 constexpr uint32_t kReqLast = 2u;
 constexpr uint32_t kReqUndefinedBits = 0x000000FCu;

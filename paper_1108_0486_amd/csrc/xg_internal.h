@@ -7,6 +7,7 @@
 
 #include "xg.h"
 #include "xg_host.h"
+#include "xg_plan_dev.h"
 
 namespace xg {
 
@@ -57,23 +58,37 @@ struct JumpPoly {
 hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
                        hipStream_t stream);
 
+// Segment entries of a batch table (kReqSegment, see xg_host.h): tile k of a
+// request starts from its stream's state jumped by k L words, staged in slot
+// (flags >> 16) by launch_seg_starts before the batch kernel runs.
 struct SegmentArgs {
-  const uint64_t *jump_table;  // (max_k) x 64 words
+  const uint64_t *jump_table;  // (max_k) x 64 words: entry k - 1 = z^(k L) mod P
   uint64_t seg_words;          // L
   uint32_t max_k;              // entries in jump_table
   uint32_t *stage;             // max_slots x kStateWords words
   uint32_t max_slots;
 };
 
-hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
-                        const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,
-                        uint32_t num_groups,
-                        uint32_t *out, uint64_t out_elems, uint32_t *work, hipStream_t stream,
-                        const SegmentArgs *seg = nullptr);
+// The batch kernels' workspace (64 words): work[0] queue counter, work[1]
+// error word (set to 1 by a skipped request or group), work[2] groups in the
+// table, work[3] table entries.  launch_work_init fills it for a host-built
+// table; the device planner fills it itself.
+hipError_t launch_work_init(uint32_t *work, uint32_t num_groups, uint32_t num_reqs, hipStream_t stream);
+// Clears only the queue counter, to serve the same table again.
+hipError_t launch_work_requeue(uint32_t *work, hipStream_t stream);
 
-// Copies the staged end states of a batch's last segments into their streams.
-hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
-                         const SegmentArgs &seg, hipStream_t stream);
+// Stages the start state of every segment entry among the table's first
+// work[3] entries (max_entries bounds the grid).
+hipError_t launch_seg_starts(const uint32_t *state, uint64_t num_streams, const xg_request *reqs,
+                             uint32_t max_entries, const uint32_t *work, const SegmentArgs &seg, hipStream_t stream);
+
+// Serves the table described by work (groups: work[2] + 1 offsets into reqs)
+// with blocks_per_cu x CUs persistent workgroups (fewer when max_groups, an
+// upper bound of work[2], is smaller).  seg may be null when the table has no
+// segment entries.
+hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
+                        const xg_request *reqs, const uint32_t *groups, uint32_t max_groups, uint32_t *out,
+                        uint64_t out_elems, uint32_t *work, hipStream_t stream, const SegmentArgs *seg = nullptr);
 
 // Write-only reference: out[0 .. words) = value with 16-byte non-temporal
 // stores (out 16-byte aligned).
@@ -104,6 +119,12 @@ struct xg_ctx {
   uint64_t num_streams;
   int device;
   int num_cus;
+  char arch[32];    // device architecture name without feature suffixes
   xg::Shape plain;
   uint32_t family;  // XG_FAMILY_*
+  // Scratch of the one-call batch (xg_set_batch_scratch); d_batch == nullptr: none.
+  void *d_batch;
+  xg::PlanLayout batch_layout;
+  uint32_t batch_max_reqs, batch_max_tiles;
+  uint64_t tile_words;  // 0: no tiles
 };

@@ -24,6 +24,7 @@
 #include "xg_device.h"
 #include "xg_normal.h"
 #include "xg_internal.h"
+#include "xg_launch.h"
 
 namespace xg {
 namespace {
@@ -617,21 +618,60 @@ __global__ __launch_bounds__(256) void k_box_muller(const uint32_t *__restrict__
   out[2 * m + 1] = z1;
 }
 
-__global__ void k_clear_work(uint32_t *work) {
-  if (threadIdx.x < 64) work[threadIdx.x] = 0u;
+// Workspace words of the batch kernels: work[0] the queue counter, work[1]
+// the error word, work[2] the queue items (groups), work[3] the table entries.
+__global__ void k_work_init(uint32_t *work, uint32_t num_groups, uint32_t num_reqs) {
+  if (threadIdx.x < 64) work[threadIdx.x] = threadIdx.x == 2 ? num_groups : threadIdx.x == 3 ? num_reqs : 0u;
+}
+
+// Re-arms the queue of a table that is already in place.
+__global__ void k_work_requeue(uint32_t *work) {
+  if (threadIdx.x == 0) work[0] = 0u;
+}
+
+// Checks of a segment entry (kReqSegment): tile k of a longer request, whose
+// start state sits in staging slot `slot`.
+__device__ __forceinline__ bool seg_entry_ok(const xg_request &q, uint64_t num_streams, const SegmentArgs &seg) {
+  const uint32_t k = (q.flags >> 8) & 0xFFu, slot = q.flags >> 16;
+  return (q.flags & kReqSegment) && !(q.flags & kReqUndefinedBits) && q.stream < num_streams &&
+         q.dtype <= XG_NORMAL && seg.stage && slot < seg.max_slots && k <= seg.max_k && (k == 0 || seg.jump_table);
+}
+
+// Start state of every segment entry of a table: its stream's state jumped by
+// k L words (k = 0: a copy) into staging slot `slot`.  One wavefront per
+// entry (work[3] entries); others, and entries that fail the checks, are
+// skipped (the batch kernel skips those too).  The batch kernel then starts
+// each segment from its slot, so no segment reads a stream state that the
+// request's last segment rewrites.
+__global__ __launch_bounds__(256) void k_seg_starts(const uint32_t *__restrict__ state, uint64_t num_streams,
+                                                    const xg_request *__restrict__ reqs,
+                                                    const uint32_t *__restrict__ work, SegmentArgs seg) {
+  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+  if (r >= work[3]) return;
+  const xg_request q = reqs[r];
+  if (!(q.flags & kReqSegment) || !seg_entry_ok(q, num_streams, seg)) return;
+  const uint32_t k = (q.flags >> 8) & 0xFFu, slot = q.flags >> 16;
+  StreamState s = load_state(state + q.stream * kStateWords);
+  if (k) {
+    const uint64_t *gk = seg.jump_table + (uint64_t)(k - 1) * 64;
+    jump_state(s, [&](int c) { return gk[c]; }, (uint64_t)k * seg.seg_words);
+  }
+  write_state(seg.stage + (uint64_t)slot * kStateWords, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane_id());
 }
 
 // Persistent batched kernel: wavefronts take request groups from an atomic
-// queue (work[0]) until it is exhausted; every wavefront reaches the exit.
+// queue (work[0]) until it passes work[2] groups; every wavefront reaches the
+// exit.  A plain entry reads and rewrites its stream's state; a segment entry
+// starts from its staged start state and only the request's last segment
+// writes the stream's state.
 template <int UNROLL, bool WIDE>
 __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, uint64_t num_streams,
                                                 const xg_request *__restrict__ reqs,
-                                                uint32_t num_reqs,
-                                                const uint32_t *__restrict__ groups,
-                                                uint32_t num_groups, uint32_t *__restrict__ out,
+                                                const uint32_t *__restrict__ groups, uint32_t *__restrict__ out,
                                                 uint64_t out_elems, uint32_t *__restrict__ work,
                                                 SegmentArgs seg) {
   const uint32_t lane = lane_id();
+  const uint32_t num_groups = work[2], num_reqs = work[3];
   for (;;) {
     uint32_t g = 0;
     if (lane == 0) g = atomicAdd(&work[0], 1u);
@@ -645,33 +685,18 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
     for (uint32_t r = r0; r < r1; ++r) {
       const xg_request q = reqs[r];
       const bool is_seg = (q.flags & kReqSegment) != 0;
-      const uint32_t k = (q.flags >> 8) & 0xFFu, slot = q.flags >> 16;
-      const bool seg_ok = !is_seg || (seg.jump_table && (q.flags & kReqUndefinedBits) == 0 &&
-                                      k <= seg.max_k && (!(q.flags & kReqLast) || slot < seg.max_slots));
-      const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && (is_seg ? seg_ok : q.flags == 0u) &&
+      const bool ok = (is_seg ? seg_entry_ok(q, num_streams, seg)
+                              : q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u) &&
                       q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
       if (!ok) {
         if (lane == 0) atomicOr(&work[1], 1u);
         continue;
       }
       uint32_t *st = state + q.stream * kStateWords;
+      const uint32_t *src = is_seg ? seg.stage + (uint64_t)(q.flags >> 16) * kStateWords : st;
+      uint32_t *dst = !is_seg || (q.flags & kReqLast) ? st : nullptr;
+      const StreamState s0 = load_state(src);
       uint32_t *o = out + q.out_offset;
-      if (!is_seg) {
-        if (q.dtype == XG_U32) {
-          serve_words<kU32, UNROLL, WIDE>(st, q.n, o);
-        } else if (q.dtype == XG_F32) {
-          serve_words<kF32, UNROLL, WIDE>(st, q.n, o);
-        } else {
-          serve_normals<false, UNROLL>(st, q.n, reinterpret_cast<float *>(o), nullptr);
-        }
-        continue;
-      }
-      StreamState s0 = load_state(st);
-      if (k) {
-        const uint64_t *gk = seg.jump_table + (uint64_t)(k - 1) * 64;
-        jump_state(s0, [&](int c) { return gk[c]; }, (uint64_t)k * seg.seg_words);
-      }
-      uint32_t *dst = (q.flags & kReqLast) ? seg.stage + (uint64_t)slot * kStateWords : nullptr;
       if (q.dtype == XG_U32) {
         serve_words_from<kU32, UNROLL, WIDE>(s0, q.n, o, dst);
       } else if (q.dtype == XG_F32) {
@@ -683,45 +708,28 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
   }
 }
 
-// One wavefront per request: a last segment's staged end state becomes its
-// stream's state.
-__global__ __launch_bounds__(256) void k_commit(uint32_t *__restrict__ state, uint64_t num_streams,
-                                                const xg_request *__restrict__ reqs, uint32_t num_reqs,
-                                                const uint32_t *__restrict__ stage, uint32_t max_slots) {
-  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (r >= num_reqs) return;
-  const xg_request q = reqs[r];
-  const uint32_t slot = q.flags >> 16;
-  if (!(q.flags & kReqSegment) || !(q.flags & kReqLast) || slot >= max_slots || q.stream >= num_streams) return;
-  const uint32_t lane = lane_id();
-  const uint32_t *src = stage + (uint64_t)slot * kStateWords;
-  uint32_t *dst = state + q.stream * kStateWords;
-  dst[lane] = src[lane];
-  dst[64 + lane] = src[64 + lane];
-  if (lane < kStateWords - 128) dst[128 + lane] = src[128 + lane];
-}
-
 template <uint32_t KIND>
 hipError_t launch_generate_k(const Shape &sh, dim3 grid, dim3 block, uint32_t *state, uint64_t first,
                              uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   constexpr bool kWords = KIND == kU32 || KIND == kF32;
   const bool wide = kWords && sh.store_words == 4;
   const size_t lds = wide ? (size_t)sh.waves_per_block * 1024u : 0u;
   if (wide) {
     if (sh.unroll == 4) {
-      hipLaunchKernelGGL((k_generate<KIND, 4, kWords>), grid, block, lds, stream, state, first, count, n, out);
+      e = launch((k_generate<KIND, 4, kWords>), grid, block, lds, stream, state, first, count, n, out);
     } else {
-      hipLaunchKernelGGL((k_generate<KIND, 8, kWords>), grid, block, lds, stream, state, first, count, n, out);
+      e = launch((k_generate<KIND, 8, kWords>), grid, block, lds, stream, state, first, count, n, out);
     }
-    return hipGetLastError();
+    return e;
   }
   switch (sh.unroll) {
-    case 1: hipLaunchKernelGGL((k_generate<KIND, 1, false>), grid, block, 0, stream, state, first, count, n, out); break;
-    case 2: hipLaunchKernelGGL((k_generate<KIND, 2, false>), grid, block, 0, stream, state, first, count, n, out); break;
-    case 4: hipLaunchKernelGGL((k_generate<KIND, 4, false>), grid, block, 0, stream, state, first, count, n, out); break;
-    default: hipLaunchKernelGGL((k_generate<KIND, 8, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 1: e = launch((k_generate<KIND, 1, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 2: e = launch((k_generate<KIND, 2, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    case 4: e = launch((k_generate<KIND, 4, false>), grid, block, 0, stream, state, first, count, n, out); break;
+    default: e = launch((k_generate<KIND, 8, false>), grid, block, 0, stream, state, first, count, n, out); break;
   }
-  return hipGetLastError();
+  return e;
 }
 
 }  // namespace
@@ -742,50 +750,54 @@ bool shape_valid(const Shape &s) {
 }
 
 hipError_t launch_init(uint32_t *state, uint64_t num_streams, uint64_t seed, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   const uint64_t blocks = (num_streams + 3) / 4;
-  hipLaunchKernelGGL(k_init, dim3((uint32_t)blocks), dim3(256), 0, stream, state, num_streams, seed);
-  return hipGetLastError();
+  e = launch(k_init, dim3((uint32_t)blocks), dim3(256), 0, stream, state, num_streams, seed);
+  return e;
 }
 
 hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t first, uint64_t count,
                        uint64_t n, uint32_t *out, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   const uint64_t wpb = shape.waves_per_block;
   const dim3 grid((uint32_t)((count + wpb - 1) / wpb));
   const dim3 block((uint32_t)(wpb * kWave));
   const bool f = kind == kF32;
   switch (shape.unroll) {
-    case 1: if (f) hipLaunchKernelGGL((k_fill<kF32, 1>), grid, block, 0, stream, state, first, count, n, out);
-            else hipLaunchKernelGGL((k_fill<kU32, 1>), grid, block, 0, stream, state, first, count, n, out);
+    case 1: if (f) e = launch((k_fill<kF32, 1>), grid, block, 0, stream, state, first, count, n, out);
+            else e = launch((k_fill<kU32, 1>), grid, block, 0, stream, state, first, count, n, out);
             break;
-    case 2: if (f) hipLaunchKernelGGL((k_fill<kF32, 2>), grid, block, 0, stream, state, first, count, n, out);
-            else hipLaunchKernelGGL((k_fill<kU32, 2>), grid, block, 0, stream, state, first, count, n, out);
+    case 2: if (f) e = launch((k_fill<kF32, 2>), grid, block, 0, stream, state, first, count, n, out);
+            else e = launch((k_fill<kU32, 2>), grid, block, 0, stream, state, first, count, n, out);
             break;
-    case 4: if (f) hipLaunchKernelGGL((k_fill<kF32, 4>), grid, block, 0, stream, state, first, count, n, out);
-            else hipLaunchKernelGGL((k_fill<kU32, 4>), grid, block, 0, stream, state, first, count, n, out);
+    case 4: if (f) e = launch((k_fill<kF32, 4>), grid, block, 0, stream, state, first, count, n, out);
+            else e = launch((k_fill<kU32, 4>), grid, block, 0, stream, state, first, count, n, out);
             break;
-    default: if (f) hipLaunchKernelGGL((k_fill<kF32, 8>), grid, block, 0, stream, state, first, count, n, out);
-             else hipLaunchKernelGGL((k_fill<kU32, 8>), grid, block, 0, stream, state, first, count, n, out);
+    default: if (f) e = launch((k_fill<kF32, 8>), grid, block, 0, stream, state, first, count, n, out);
+             else e = launch((k_fill<kU32, 8>), grid, block, 0, stream, state, first, count, n, out);
              break;
   }
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_box_muller(const uint32_t *words, uint64_t pairs, float *out, hipStream_t stream) {
-  hipLaunchKernelGGL(k_box_muller, dim3((uint32_t)((pairs + 255) / 256)), dim3(256), 0, stream, words, pairs, out);
-  return hipGetLastError();
+  hipError_t e = hipSuccess;
+  e = launch(k_box_muller, dim3((uint32_t)((pairs + 255) / 256)), dim3(256), 0, stream, words, pairs, out);
+  return e;
 }
 
 hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
                        hipStream_t stream) {
+  hipError_t e = hipSuccess;
   const dim3 grid((uint32_t)((count + 3) / 4)), block(256);
   if (g) {
-    hipLaunchKernelGGL((k_skip<true>), grid, block, 4 * 1024, stream, state, first, count, J, *g);
+    e = launch((k_skip<true>), grid, block, 4 * 1024, stream, state, first, count, J, *g);
   } else {
     JumpPoly none;
     for (int i = 0; i < 64; ++i) none.w[i] = 0;
-    hipLaunchKernelGGL((k_skip<false>), grid, block, 0, stream, state, first, count, J, none);
+    e = launch((k_skip<false>), grid, block, 0, stream, state, first, count, J, none);
   }
-  return hipGetLastError();
+  return e;
 }
 
 hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint64_t first,
@@ -801,44 +813,44 @@ hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint6
   }
 }
 
-hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
-                        const xg_request *reqs, uint32_t num_reqs, const uint32_t *groups,
-                        uint32_t num_groups, uint32_t *out, uint64_t out_elems, uint32_t *work,
-                        hipStream_t stream, const SegmentArgs *seg) {
-  hipLaunchKernelGGL(k_clear_work, dim3(1), dim3(64), 0, stream, work);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  const uint64_t want_waves = (uint64_t)num_groups;
-  uint64_t blocks = (uint64_t)num_cus * shape.blocks_per_cu;
-  const uint64_t need = (want_waves + shape.waves_per_block - 1) / shape.waves_per_block;
-  if (need < blocks) blocks = need ? need : 1;
-  const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
-  const size_t lds = (size_t)shape.waves_per_block * 1024u;  // staging slots (wide stores, jumps)
-  SegmentArgs sa{};
-  if (seg) sa = *seg;
-  if (shape.store_words == 4) {
-    if (shape.unroll == 4) {
-      hipLaunchKernelGGL((k_batch<4, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa);
-    } else {
-      hipLaunchKernelGGL((k_batch<8, true>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa);
-    }
-    return hipGetLastError();
-  }
-  switch (shape.unroll) {
-    case 1: hipLaunchKernelGGL((k_batch<1, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
-    case 2: hipLaunchKernelGGL((k_batch<2, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
-    case 4: hipLaunchKernelGGL((k_batch<4, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
-    default: hipLaunchKernelGGL((k_batch<8, false>), grid, block, lds, stream, state, num_streams, reqs, num_reqs, groups, num_groups, out, out_elems, work, sa); break;
-  }
-  return hipGetLastError();
+hipError_t launch_work_init(uint32_t *work, uint32_t num_groups, uint32_t num_reqs, hipStream_t stream) {
+  return launch(k_work_init, dim3(1), dim3(64), 0, stream, work, num_groups, num_reqs);
 }
 
-hipError_t launch_commit(uint32_t *state, uint64_t num_streams, const xg_request *reqs, uint32_t num_reqs,
-                         const SegmentArgs &seg, hipStream_t stream) {
-  if (num_reqs == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_commit, dim3((num_reqs + 3) / 4), dim3(256), 0, stream, state, num_streams, reqs, num_reqs,
-                     seg.stage, seg.max_slots);
-  return hipGetLastError();
+hipError_t launch_work_requeue(uint32_t *work, hipStream_t stream) {
+  return launch(k_work_requeue, dim3(1), dim3(64), 0, stream, work);
+}
+
+hipError_t launch_seg_starts(const uint32_t *state, uint64_t num_streams, const xg_request *reqs,
+                             uint32_t max_entries, const uint32_t *work, const SegmentArgs &seg, hipStream_t stream) {
+  if (max_entries == 0) return hipSuccess;
+  return launch(k_seg_starts, dim3((max_entries + 3) / 4), dim3(256), 4 * 1024, stream, state, num_streams, reqs,
+                work, seg);
+}
+
+hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,
+                        const xg_request *reqs, const uint32_t *groups, uint32_t max_groups, uint32_t *out,
+                        uint64_t out_elems, uint32_t *work, hipStream_t stream, const SegmentArgs *seg) {
+  uint64_t blocks = (uint64_t)(num_cus > 0 ? num_cus : 1) * shape.blocks_per_cu;
+  const uint64_t need = ((uint64_t)max_groups + shape.waves_per_block - 1) / shape.waves_per_block;
+  if (need < blocks) blocks = need ? need : 1;
+  const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  const size_t lds = shape.store_words == 4 ? (size_t)shape.waves_per_block * 1024u : 0u;  // wide-store staging
+  SegmentArgs sa{};
+  if (seg) sa = *seg;
+  hipError_t e = hipSuccess;
+  if (shape.store_words == 4) {
+    if (shape.unroll == 4) e = launch((k_batch<4, true>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa);
+    else e = launch((k_batch<8, true>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa);
+    return e;
+  }
+  switch (shape.unroll) {
+    case 1: e = launch((k_batch<1, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
+    case 2: e = launch((k_batch<2, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
+    case 4: e = launch((k_batch<4, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
+    default: e = launch((k_batch<8, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
+  }
+  return e;
 }
 
 }  // namespace xg

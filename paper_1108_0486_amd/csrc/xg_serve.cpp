@@ -16,9 +16,9 @@
 // batches, so every request reads the exact positions it would read alone.
 // With segment_words = L, a request of more than L words becomes segments of
 // L words, each its own group (so separate wavefronts run them at once):
-// segment k jumps from the request's start state by k L words; only the last
-// one produces the end state, staged and committed after the batch.  A split
-// request is alone on its stream within its batch.
+// segment k starts from the request's start state jumped by k L words, staged
+// before the batch kernel; only the last one writes the stream's end state.
+// A split request is alone on its stream within its batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -57,7 +57,7 @@ struct Pending {
 };
 
 struct Lane {
-  uint32_t *d_stage = nullptr;   // max_batch staging states (split requests)
+  uint32_t *d_stage = nullptr;   // max_batch staged start states (segments)
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
@@ -168,7 +168,8 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
   Lane &l = s->lanes[li];
   *admitted = 0;
   std::vector<uint64_t> in_this_batch;
-  uint32_t k = 0, slots = 0, nreq = 0;
+  uint32_t k = 0, nreq = 0;
+  bool any_split = false;
   bool waited = false;
   for (auto it = s->pending.begin(); it != s->pending.end() && k < s->max_batch;) {
     const Pending &p = *it;
@@ -215,12 +216,14 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
     if (!split) {
       l.h_scratch[k++] = xg_request{p.stream, p.n, off, p.dtype, 0};
     } else {
-      const uint32_t slot = slots++;
+      // Segment j's start state goes to staging slot k (its place in
+      // this table before planning; k < max_batch <= 65536).
+      any_split = true;
       for (uint64_t j = 0; j < nseg; ++j) {
         const uint64_t first = j * s->seg_words;
         const uint64_t n_j = std::min<uint64_t>(s->seg_words, p.n - first);
-        uint32_t flags = xg::kReqSegment | ((uint32_t)j << 8);
-        if (j + 1 == nseg) flags |= xg::kReqLast | (slot << 16);
+        uint32_t flags = xg::kReqSegment | ((uint32_t)j << 8) | (k << 16);
+        if (j + 1 == nseg) flags |= xg::kReqLast;
         l.h_scratch[k++] = xg_request{p.stream, n_j, off + first, p.dtype, flags};
       }
     }
@@ -244,18 +247,20 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
   if (!s->default_tune)
     shape = xg::Shape{s->tune.waves_per_block, s->tune.unroll, s->tune.blocks_per_cu,
                       s->tune.store_words ? s->tune.store_words : (s->tune.unroll >= 4 ? 4u : 1u)};
+  if (xg::launch_work_init(l.d_work, num_groups, k, l.stream) != hipSuccess) return XG_EHIP;
   if (s->ctx->family != XG_FAMILY_R128_W32) {  // a further member (no segments)
     if (xg::launch_family_batch(s->ctx->family, shape, s->ctx->num_cus,
-                                reinterpret_cast<unsigned char *>(s->ctx->d_state), s->ctx->num_streams, l.d_reqs, k,
+                                reinterpret_cast<unsigned char *>(s->ctx->d_state), s->ctx->num_streams, l.d_reqs,
                                 l.d_groups, num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream) != hipSuccess)
       return XG_EHIP;
   } else {
-    xg::SegmentArgs seg{s->d_jump, s->seg_words, s->d_jump ? kJumpEntries : 0u, l.d_stage, s->max_batch};
-    if (xg::launch_batch(shape, s->ctx->num_cus, s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_groups,
+    const xg::SegmentArgs seg{s->d_jump, s->seg_words, s->d_jump ? kJumpEntries : 0u, l.d_stage, s->max_batch};
+    if (any_split &&
+        xg::launch_seg_starts(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_work, seg, l.stream) != hipSuccess)
+      return XG_EHIP;
+    if (xg::launch_batch(shape, s->ctx->num_cus, s->ctx->d_state, s->ctx->num_streams, l.d_reqs, l.d_groups,
                          num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream,
                          s->seg_words ? &seg : nullptr) != hipSuccess)
-      return XG_EHIP;
-    if (slots && xg::launch_commit(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, seg, l.stream) != hipSuccess)
       return XG_EHIP;
   }
   if (hipEventRecord(l.done, l.stream) != hipSuccess) return XG_EHIP;
@@ -295,11 +300,18 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
   if (tables_bytes < xg_server_device_bytes(cfg)) return XG_ERANGE;
   if (reinterpret_cast<uintptr_t>(d_pool) % kAlignBytes || reinterpret_cast<uintptr_t>(d_tables) % kAlignBytes)
     return XG_EALIGN;
-  const bool default_tune = cfg->tune.waves_per_block == 0 && cfg->tune.unroll == 0 &&
-                            cfg->tune.blocks_per_cu == 0 && cfg->tune.store_words == 0;
+  bool default_tune = cfg->tune.waves_per_block == 0 && cfg->tune.unroll == 0 &&
+                      cfg->tune.blocks_per_cu == 0 && cfg->tune.store_words == 0;
+  xg_tune tune = cfg->tune;
+  if (default_tune && cfg->tune_key) {  // the tuning cache's shape for this device, member and key
+    const xg_status st = xg_tune_cache_get(ctx->arch, (uint32_t)ctx->num_cus, ctx->family, cfg->tune_key, &tune,
+                                           nullptr);
+    if (st == XG_EINVAL || st == XG_ENOMEM) return st;
+    default_tune = st != XG_OK;
+  }
   if (!default_tune) {
-    xg::Shape sh{cfg->tune.waves_per_block, cfg->tune.unroll, cfg->tune.blocks_per_cu,
-                 cfg->tune.store_words ? cfg->tune.store_words : (cfg->tune.unroll >= 4 ? 4u : 1u)};
+    xg::Shape sh{tune.waves_per_block, tune.unroll, tune.blocks_per_cu,
+                 tune.store_words ? tune.store_words : (tune.unroll >= 4 ? 4u : 1u)};
     if (!xg::shape_valid(sh)) return XG_EINVAL;
   }
   xg_server *s = new (std::nothrow) xg_server;
@@ -309,7 +321,7 @@ xg_status xg_server_create(xg_server **out, xg_ctx *ctx, const xg_server_config 
     s->d_pool = static_cast<uint32_t *>(d_pool);
     s->pool_elems = pool_elems;
     s->max_batch = cfg->max_batch;
-    s->tune = cfg->tune;
+    s->tune = tune;
     s->default_tune = default_tune;
     s->pool = xg::Pool(pool_elems);
     s->busy_stream.assign(ctx->num_streams, 0);

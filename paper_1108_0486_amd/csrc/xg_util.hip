@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "xg_internal.h"
+#include "xg_launch.h"
 
 namespace xg {
 namespace {
@@ -28,13 +29,14 @@ __global__ __launch_bounds__(256) void k_fill_value(uint32_t *__restrict__ out, 
 }  // namespace
 
 hipError_t launch_fill_value(uint32_t *out, uint64_t words, uint32_t value, int num_cus, hipStream_t stream) {
+  hipError_t e = hipSuccess;
   (void)num_cus;
   const uint64_t quads = words / 4;
   const uint64_t blocks = quads ? (quads + 255) / 256 : 1;
   if (blocks > 0xFFFFFFFFull) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_fill_value, dim3((uint32_t)blocks), dim3(256), 0, stream, out, quads, (uint32_t)(words % 4),
+  e = launch(k_fill_value, dim3((uint32_t)blocks), dim3(256), 0, stream, out, quads, (uint32_t)(words % 4),
                      value);
-  return hipGetLastError();
+  return e;
 }
 
 }  // namespace xg

@@ -56,6 +56,28 @@ class XorgensStreams:
         except Exception:
             pass
 
+    # ---- batch scratch ---------------------------------------------------------
+    def batch_scratch(self, max_reqs: int, max_tiles: int = 0, tile_words: int = 0,
+                      stream: torch.cuda.Stream | None = None) -> torch.Tensor:
+        """Device scratch of xg_generate_batch on these streams, attached to the
+        handle: reused while it holds max_reqs requests with the same tile
+        setting, else replaced by a new one."""
+        cfg = getattr(self, "_batch_cfg", None)
+        max_reqs = max(1, int(max_reqs))
+        if cfg is not None and cfg[0] >= max_reqs and cfg[1:] == (max_tiles, tile_words):
+            return self._batch_scratch
+        nbytes = xg.xg_batch_scratch_bytes(self.ctx, max_reqs, max_tiles)
+        if nbytes == 0:
+            raise ValueError("no batch scratch for %d requests and %d tiles" % (max_reqs, max_tiles))
+        buf = torch.empty((nbytes + 3) // 4, dtype=torch.int32, device=self.device)
+        if buf.data_ptr() % 256:
+            raise RuntimeError("batch scratch is not 256-byte aligned")
+        with torch.cuda.device(self.device):
+            xg.xg_set_batch_scratch(self.ctx, buf.data_ptr(), nbytes, max_reqs, max_tiles, tile_words,
+                                    _stream_handle(stream))
+        self._batch_scratch, self._batch_cfg = buf, (max_reqs, max_tiles, tile_words)
+        return buf
+
     # ---- tuning -----------------------------------------------------------
     def set_plain_tune(self, waves_per_block: int, unroll: int, store_words: int = 0) -> None:
         xg.xg_set_plain_tune(self.ctx, waves_per_block, unroll, store_words)

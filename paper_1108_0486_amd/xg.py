@@ -58,7 +58,7 @@ class xg_tune(ctypes.Structure):
 
 class xg_server_config(ctypes.Structure):
     _fields_ = [("num_lanes", ctypes.c_uint32), ("max_batch", ctypes.c_uint32), ("tune", xg_tune),
-                ("segment_words", ctypes.c_uint64)]
+                ("segment_words", ctypes.c_uint64), ("tune_key", ctypes.c_char_p)]
 
 
 class xg_completion(ctypes.Structure):
@@ -122,9 +122,21 @@ def lib() -> ctypes.CDLL:
         "xg_normal_moments_f64": (st, [vp, u64, u64, u64, vp, vp]),
         "xg_batch_workspace_bytes": (ctypes.c_size_t, []),
         "xg_plan_batch": (st, [P(xg_request), u32, u64, u64, P(xg_request), P(u32), P(u32)]),
-        "xg_generate_batch": (st, [vp, vp, u32, vp, u32, vp, u64, P(xg_tune), vp, vp]),
-        "xg_autotune_batch": (st, [vp, vp, u32, vp, u32, vp, u64, vp, vp, i32, P(xg_tune),
+        "xg_generate_batch_planned": (st, [vp, vp, u32, vp, u32, vp, u64, P(xg_tune), vp, vp]),
+        "xg_batch_scratch_bytes": (ctypes.c_size_t, [vp, u32, u32]),
+        "xg_set_batch_scratch": (st, [vp, vp, ctypes.c_size_t, u32, u32, u64, vp]),
+        "xg_generate_batch": (st, [vp, vp, u32, vp, ctypes.c_char_p, vp]),
+        "xg_autotune_batch": (st, [vp, vp, u32, vp, vp, ctypes.c_char_p, i32, P(xg_tune),
                                    P(ctypes.c_float), u32, P(u32), vp]),
+        "xg_tune_cache_load": (st, [ctypes.c_char_p]),
+        "xg_tune_cache_save": (st, [ctypes.c_char_p]),
+        "xg_tune_cache_put": (st, [ctypes.c_char_p, u32, u32, ctypes.c_char_p, P(xg_tune), ctypes.c_float]),
+        "xg_tune_cache_get": (st, [ctypes.c_char_p, u32, u32, ctypes.c_char_p, P(xg_tune),
+                                   P(ctypes.c_float)]),
+        "xg_tune_cache_size": (u32, []),
+        "xg_tune_cache_clear": (None, []),
+        "xg_tune_identity": (st, [vp, ctypes.c_char_p, ctypes.c_size_t, P(u32)]),
+        "xg_batch_read_plan": (st, [vp, P(xg_request), u32, P(u32), u32, P(u32), P(u32), vp]),
         "xg_strerror": (ctypes.c_char_p, [st]),
         "xg_server_device_bytes": (ctypes.c_size_t, [P(xg_server_config)]),
         "xg_server_create": (st, [P(vp), vp, P(xg_server_config), vp, u64, vp, ctypes.c_size_t]),
@@ -322,39 +334,108 @@ def xg_plan_batch(requests, num_streams: int, out_elems: int):
     return out, list(groups[: ng.value + 1])
 
 
-def xg_generate_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int, d_out: int,
-                      out_elems: int, tune: tuple | None, d_work: int, stream: int = 0) -> None:
+def xg_generate_batch_planned(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int, d_out: int,
+                              out_elems: int, tune: tuple | None, d_work: int, stream: int = 0) -> None:
     t = None if tune is None else ctypes.byref(xg_tune.of(tune))
-    _check(lib().xg_generate_batch(ctx, d_reqs, num_reqs, d_groups, num_groups, d_out, out_elems, t,
-                                   d_work, stream), "xg_generate_batch")
+    _check(lib().xg_generate_batch_planned(ctx, d_reqs, num_reqs, d_groups, num_groups, d_out, out_elems, t,
+                                           d_work, stream), "xg_generate_batch_planned")
 
 
-def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_groups: int, num_groups: int,
-                      d_scratch_out: int, out_elems: int, d_scratch_state: int, d_work: int,
-                      reps: int = 3, stream: int = 0):
+def _key(tune_key: str | None):
+    return None if tune_key is None else tune_key.encode()
+
+
+def xg_batch_scratch_bytes(ctx, max_reqs: int, max_tiles: int = 0) -> int:
+    return int(lib().xg_batch_scratch_bytes(ctx, max_reqs, max_tiles))
+
+
+def xg_set_batch_scratch(ctx, d_scratch: int | None, scratch_bytes: int, max_reqs: int, max_tiles: int = 0,
+                         tile_words: int = 0, stream: int = 0) -> None:
+    _check(lib().xg_set_batch_scratch(ctx, d_scratch, scratch_bytes, max_reqs, max_tiles, tile_words, stream),
+           "xg_set_batch_scratch")
+
+
+def xg_generate_batch(ctx, d_reqs: int, num_reqs: int, d_out: int, tune_key: str | None = None,
+                      stream: int = 0) -> None:
+    _check(lib().xg_generate_batch(ctx, d_reqs, num_reqs, d_out, _key(tune_key), stream), "xg_generate_batch")
+
+
+def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_scratch_out: int, d_scratch_state: int,
+                      tune_key: str | None = None, reps: int = 3, stream: int = 0):
     """Returns (best (wpb, unroll, bpc, store_words), [(wpb, unroll, bpc, store_words, ms), ...])."""
     best = xg_tune()
     maxt = 256
     times = (ctypes.c_float * (5 * maxt))()
     nt = ctypes.c_uint32()
-    _check(lib().xg_autotune_batch(ctx, d_reqs, num_reqs, d_groups, num_groups, d_scratch_out, out_elems,
-                                   d_scratch_state, d_work, reps, ctypes.byref(best), times, maxt,
-                                   ctypes.byref(nt), stream), "xg_autotune_batch")
+    _check(lib().xg_autotune_batch(ctx, d_reqs, num_reqs, d_scratch_out, d_scratch_state, _key(tune_key), reps,
+                                   ctypes.byref(best), times, maxt, ctypes.byref(nt), stream), "xg_autotune_batch")
     recs = [(int(times[5 * i]), int(times[5 * i + 1]), int(times[5 * i + 2]), int(times[5 * i + 4]),
              float(times[5 * i + 3])) for i in range(nt.value)]
     return best.as_tuple(), recs
 
 
+def xg_batch_read_plan(ctx, max_entries: int, max_groups: int, stream: int = 0):
+    """The last planned table: ([(stream, n, out_offset, dtype, flags)], [group offsets])."""
+    table = (xg_request * max(1, max_entries))()
+    groups = (ctypes.c_uint32 * (max_groups + 1))()
+    ne, ng = ctypes.c_uint32(), ctypes.c_uint32()
+    _check(lib().xg_batch_read_plan(ctx, table, max_entries, groups, max_groups, ctypes.byref(ne), ctypes.byref(ng),
+                                    stream), "xg_batch_read_plan")
+    rows = [(table[i].stream, table[i].n, table[i].out_offset, table[i].dtype, table[i].flags) for i in range(ne.value)]
+    return rows, list(groups[: ng.value + 1])
+
+
+def xg_tune_cache_load(path: str) -> None:
+    _check(lib().xg_tune_cache_load(path.encode()), "xg_tune_cache_load")
+
+
+def xg_tune_cache_save(path: str) -> None:
+    _check(lib().xg_tune_cache_save(path.encode()), "xg_tune_cache_save")
+
+
+def xg_tune_cache_put(arch: str, cus: int, family: int, tune_key: str, tune, ms: float = float("nan")) -> None:
+    _check(lib().xg_tune_cache_put(arch.encode(), cus, family, tune_key.encode(), ctypes.byref(xg_tune.of(tune)),
+                                   ms), "xg_tune_cache_put")
+
+
+def xg_tune_cache_get(arch: str, cus: int, family: int, tune_key: str):
+    """(shape tuple, ms) of an entry, or None when the cache has no such key."""
+    t = xg_tune()
+    ms = ctypes.c_float()
+    st = lib().xg_tune_cache_get(arch.encode(), cus, family, tune_key.encode(), ctypes.byref(t), ctypes.byref(ms))
+    if st == XG_ERANGE:
+        return None
+    _check(st, "xg_tune_cache_get")
+    return t.as_tuple(), float(ms.value)
+
+
+def xg_tune_cache_size() -> int:
+    return int(lib().xg_tune_cache_size())
+
+
+def xg_tune_cache_clear() -> None:
+    lib().xg_tune_cache_clear()
+
+
+def xg_tune_identity(ctx):
+    """(arch, compute units) under which calls on ctx look shapes up."""
+    buf = ctypes.create_string_buffer(64)
+    cus = ctypes.c_uint32()
+    _check(lib().xg_tune_identity(ctx, buf, 64, ctypes.byref(cus)), "xg_tune_identity")
+    return buf.value.decode(), int(cus.value)
+
+
 # ---- serving -----------------------------------------------------------------
 
 def xg_server_device_bytes(num_lanes: int, max_batch: int, segment_words: int = 0) -> int:
-    cfg = xg_server_config(num_lanes, max_batch, xg_tune(), segment_words)
+    cfg = xg_server_config(num_lanes, max_batch, xg_tune(), segment_words, None)
     return int(lib().xg_server_device_bytes(ctypes.byref(cfg)))
 
 
 def xg_server_create(ctx, num_lanes: int, max_batch: int, tune, d_pool: int, pool_elems: int,
-                     d_tables: int, tables_bytes: int, segment_words: int = 0):
-    cfg = xg_server_config(num_lanes, max_batch, xg_tune() if tune is None else xg_tune.of(tune), segment_words)
+                     d_tables: int, tables_bytes: int, segment_words: int = 0, tune_key: str | None = None):
+    cfg = xg_server_config(num_lanes, max_batch, xg_tune() if tune is None else xg_tune.of(tune), segment_words,
+                           _key(tune_key))
     srv = ctypes.c_void_p()
     _check(lib().xg_server_create(ctypes.byref(srv), ctx, ctypes.byref(cfg), d_pool, pool_elems, d_tables,
                                   tables_bytes), "xg_server_create")

@@ -44,7 +44,13 @@ def test_null_arguments_rejected_without_gpu():
     assert L.xg_init_streams(ctypes.byref(ctx), 0x1000, 527, 1, 0, None) == xg.XG_ERANGE
     assert L.xg_init_streams(ctypes.byref(ctx), 0x1004, 528, 1, 0, None) == xg.XG_EALIGN
     assert L.xg_init_streams(ctypes.byref(ctx), 0x1000, 528, 0, 0, None) == xg.XG_EINVAL
-    assert L.xg_generate_batch(None, None, 0, None, 0, None, 0, None, None, None) == xg.XG_EINVAL
+    assert L.xg_generate_batch_planned(None, None, 0, None, 0, None, 0, None, None, None) == xg.XG_EINVAL
+    assert L.xg_generate_batch(None, None, 0, None, None, None) == xg.XG_EINVAL
+    assert L.xg_generate_batch(None, None, 0, None, b"k", None) == xg.XG_EINVAL
+    assert L.xg_autotune_batch(None, None, 0, None, None, None, 1, None, None, 0, None, None) == xg.XG_EINVAL
+    assert L.xg_set_batch_scratch(None, None, 0, 1, 0, 0, None) == xg.XG_EINVAL
+    assert L.xg_batch_scratch_bytes(None, 1, 0) == 0
+    assert L.xg_tune_identity(None, None, 0, None) == xg.XG_EINVAL
     assert L.xg_set_plain_tune(None, None) == xg.XG_EINVAL
     L.xg_destroy(None)
     assert L.xg_num_streams(None) == 0
@@ -167,3 +173,102 @@ def test_fill_value_arguments_without_gpu():
     aligned = (ctypes.addressof(buf) + 15) // 16 * 16
     assert L.xg_fill_value(aligned + 4, 4, 7, None) == xg.XG_EALIGN
     assert L.xg_fill_value(aligned, 2**63, 7, None) == xg.XG_ERANGE
+
+
+# ---- tuning cache (host only) -------------------------------------------------
+
+def _fresh_cache():
+    xg.xg_tune_cache_clear()
+    assert xg.xg_tune_cache_size() == 0
+
+
+def test_tune_cache_round_trip(tmp_path):
+    _fresh_cache()
+    xg.xg_tune_cache_put("gfx950", 256, xg.XG_FAMILY_R128_W32, "ragged65536/u32", (1, 1, 8, 1), 7.31)
+    xg.xg_tune_cache_put("gfx950", 256, xg.XG_FAMILY_R64_W32, "ragged65536/u32", (8, 2, 1, 0), 7.26)
+    xg.xg_tune_cache_put("gfx950", 304, xg.XG_FAMILY_R128_W32, "ragged65536/u32", (4, 8, 4, 4), 9.0)
+    xg.xg_tune_cache_put("gfx950", 256, xg.XG_FAMILY_R128_W32, "serve/mixed", (2, 4, 16, 1))
+    assert xg.xg_tune_cache_size() == 4
+    # the key has four parts: each one tells entries apart
+    assert xg.xg_tune_cache_get("gfx950", 256, 0, "ragged65536/u32")[0] == (1, 1, 8, 1)
+    assert xg.xg_tune_cache_get("gfx950", 256, 1, "ragged65536/u32")[0] == (8, 2, 1, 0)
+    assert xg.xg_tune_cache_get("gfx950", 304, 0, "ragged65536/u32")[0] == (4, 8, 4, 4)
+    assert xg.xg_tune_cache_get("gfx942", 256, 0, "ragged65536/u32") is None
+    assert xg.xg_tune_cache_get("gfx950", 256, 0, "ragged65536/f32") is None
+    path = str(tmp_path / "tune.json")
+    xg.xg_tune_cache_save(path)
+    _fresh_cache()
+    xg.xg_tune_cache_load(path)
+    assert xg.xg_tune_cache_size() == 4
+    shape, ms = xg.xg_tune_cache_get("gfx950", 256, 0, "ragged65536/u32")
+    assert shape == (1, 1, 8, 1) and abs(ms - 7.31) < 1e-4
+    assert xg.xg_tune_cache_get("gfx950", 256, 0, "serve/mixed")[1] == -1.0  # stored without a time
+    # loading merges: a later file replaces equal keys and keeps the others
+    _fresh_cache()
+    xg.xg_tune_cache_put("gfx950", 256, 0, "ragged65536/u32", (16, 8, 2, 4), 1.0)
+    xg.xg_tune_cache_put("gfx950", 256, 0, "only-here", (1, 2, 1, 1), 2.0)
+    xg.xg_tune_cache_load(path)
+    assert xg.xg_tune_cache_size() == 5
+    assert xg.xg_tune_cache_get("gfx950", 256, 0, "ragged65536/u32")[0] == (1, 1, 8, 1)
+    assert xg.xg_tune_cache_get("gfx950", 256, 0, "only-here")[0] == (1, 2, 1, 1)
+    _fresh_cache()
+
+
+def test_tune_cache_rejects_bad_arguments_and_files(tmp_path):
+    _fresh_cache()
+    bad_shapes = [(3, 1, 1, 1), (1, 3, 1, 1), (1, 1, 0, 1), (1, 1, 33, 1), (1, 2, 1, 4), (1, 1, 1, 2)]
+    for t in bad_shapes:
+        with pytest.raises(xg.XgError) as e:
+            xg.xg_tune_cache_put("gfx950", 256, 0, "k", t)
+        assert e.value.status == xg.XG_EINVAL
+    for arch, cus, fam, key in [("", 256, 0, "k"), ("gfx950", 0, 0, "k"), ("gfx950", 256, 3, "k"),
+                                ("gfx950", 256, 0, ""), ("gfx950", 256, 0, 'a"b'), ("gfx950", 256, 0, "a\\b"),
+                                ("gfx950", 256, 0, "x" * 257), ("gfx950", 256, 0, "tab\tkey")]:
+        with pytest.raises(xg.XgError) as e:
+            xg.xg_tune_cache_put(arch, cus, fam, key, (1, 1, 1, 1))
+        assert e.value.status == xg.XG_EINVAL
+    xg.xg_tune_cache_put("gfx950", 256, 0, "x" * 256, (1, 1, 1, 1))
+    assert xg.xg_tune_cache_size() == 1
+    # malformed files are refused whole
+    good = ('{"xg_tune_cache": 1, "entries": [{"arch": "gfx950", "key": "k", "cus": 256, "family": 0, '
+            '"waves_per_block": 1, "unroll": 1, "blocks_per_cu": 8, "store_words": 1, "ms": 7.0}]}')
+    broken = [
+        "", "{", "[]", good.replace('"xg_tune_cache": 1', '"xg_tune_cache": 2'),
+        good.replace('"unroll": 1', '"unroll": 3'), good.replace('"cus": 256', '"cus": -1'),
+        good.replace('"cus": 256', '"cus": 2.5'), good.replace('"arch": "gfx950", ', ''),
+        good.replace('"key": "k"', '"key": 5'), good[:-1], good + "x",
+        good.replace('"family": 0', '"family": 7'), good.replace('"key": "k"', '"key": "\\u00e9"'),
+    ]
+    path = str(tmp_path / "bad.json")
+    for text in broken:
+        with open(path, "w") as f:
+            f.write(text)
+        with pytest.raises(xg.XgError) as e:
+            xg.xg_tune_cache_load(path)
+        assert e.value.status == xg.XG_EINVAL, text
+        assert xg.xg_tune_cache_size() == 1  # nothing merged
+    with open(path, "w") as f:
+        f.write(good)
+    xg.xg_tune_cache_load(path)
+    assert xg.xg_tune_cache_get("gfx950", 256, 0, "k")[0] == (1, 1, 8, 1)
+    with pytest.raises(xg.XgError):
+        xg.xg_tune_cache_load(str(tmp_path / "missing.json"))
+    with pytest.raises(xg.XgError):
+        xg.xg_tune_cache_save(str(tmp_path / "no-such-dir" / "t.json"))
+    _fresh_cache()
+
+
+def test_tune_cache_env_file_loaded_before_first_lookup(tmp_path):
+    """XG_TUNE_CACHE names a file merged in before the first lookup (in a fresh process)."""
+    import sys
+    path = tmp_path / "env.json"
+    path.write_text('{"xg_tune_cache": 1, "entries": [{"arch": "gfx950", "key": "env", "cus": 8, "family": 1, '
+                    '"waves_per_block": 2, "unroll": 4, "blocks_per_cu": 3, "store_words": 0, "ms": 1.5}]}')
+    code = ("from paper_1108_0486_amd import xg; r = xg.xg_tune_cache_get('gfx950', 8, 1, 'env'); "
+            "print(r[0], xg.xg_tune_cache_size())")
+    import os
+    env = dict(os.environ, XG_TUNE_CACHE=str(path))
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=root,
+                         check=True).stdout
+    assert out.split() == ["(2,", "4,", "3,", "0)", "1"]

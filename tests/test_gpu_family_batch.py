@@ -13,7 +13,7 @@ pytestmark = [pytest.mark.gpu, needs_gpu]
 torch = pytest.importorskip("torch")
 
 from paper_1108_0486_amd import xg  # noqa: E402
-from paper_1108_0486_amd.batch import Batch  # noqa: E402
+from paper_1108_0486_amd.batch import Batch, PlannedBatch  # noqa: E402
 from paper_1108_0486_amd.streams import XorgensStreams  # noqa: E402
 
 R64W32, R64W64 = xg.XG_FAMILY_R64_W32, xg.XG_FAMILY_R64_W64
@@ -75,18 +75,19 @@ def _check(fam, out, reqs, want):
             assert (got == w).all(), (s, n, off, dt)
 
 
+@pytest.mark.parametrize("path", ["device", "planned"])
 @pytest.mark.parametrize("fam", FAMILIES)
 @pytest.mark.parametrize("tune", [None, (1, 1, 1), (2, 2, 4), (4, 4, 8), (16, 8, 2), (1, 8, 32)])
-def test_member_batch_matches_oracle(fam, tune):
+def test_member_batch_matches_oracle(fam, tune, path):
     rng = np.random.default_rng(17)
     S = 37
     reqs, out_elems = _requests(rng, S, 120, 3000)
     gs = XorgensStreams(S, seed=9, family=fam)
-    b = Batch(gs, reqs, out_elems)
+    b = (Batch if path == "device" else PlannedBatch)(gs, reqs, out_elems)
     b.run(tune=None if tune is None else (tune[0], tune[1], tune[2], 1))
     torch.cuda.synchronize()
     assert b.error_flag() == 0
-    # Served order: the planner's (groups by stream, arrival order inside).
+    # Each stream serves its requests in table order.
     ref = _oracle(fam, 9, S)
     want = _oracle_serve(fam, ref, b.requests_in_order())
     _check(fam, b.out, b.requests_in_order(), want)
@@ -181,10 +182,10 @@ def test_member_batch_odd_normal_pieces(fam):
     reqs = [(0, 5, 0, 2), (1, 10, 5, 2), (0, 3, 15, 2), (1, 7, 18, 0), (0, 1, 25, 2)]
     gs = XorgensStreams(S, seed=77, family=fam)
     b = Batch(gs, reqs, 26)
-    assert b.num_groups == 2
     b.run()
     torch.cuda.synchronize()
     assert b.error_flag() == 0
+    assert b.served_counts() == (2, 5)
     ref = _oracle(fam, 77, S)
     want = _oracle_serve(fam, ref, b.requests_in_order())
     _check(fam, b.out, b.requests_in_order(), want)
