@@ -396,6 +396,27 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
 xg_status xg_batch_read_plan(const xg_ctx *ctx, xg_request *h_table, uint32_t max_entries, uint32_t *h_groups,
                              uint32_t max_groups, uint32_t *num_entries, uint32_t *num_groups, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * call as xg_generate_batch, with the planner's scratch in a file-scope device
+ * array of the library instead of memory attached with xg_set_batch_scratch.
+ * It allocates nothing.  The array (XG_STATIC_SCRATCH_BYTES, 5 MiB) is held
+ * on each GPU the library runs on until the process ends; its device address
+ * is looked up once per GPU, on the first call there.
+ *   num_reqs  at most XG_STATIC_MAX_REQS (65536); more gives XG_EBUSY, with
+ *             nothing enqueued.  No tiles: long requests run whole.
+ *   d_error   NULL, or a device word (caller-owned) that receives 1 if a
+ *             request was skipped (as xg_generate_batch's error word), else 0
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * plan: calls that overlap on one GPU (on different HIP streams, or from
+ * host threads without ordering) race and must not be made.
+ * Errors: XG_EINVAL (NULL pointer, handle of another device, malformed
+ * tune_key), XG_EBUSY, XG_EALIGN, XG_ENOTSUP, XG_EHIP. */
+#define XG_STATIC_MAX_REQS      65536u
+#define XG_STATIC_SCRATCH_BYTES (5u << 20)
+xg_status xg_generate_batch_static(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_reqs, void *d_out,
+                                   const char *tune_key, uint32_t *d_error, void *stream);
+
 /* Device workspace of xg_generate_batch_planned: a work counter, an error
  * word and the table's counts (256 B). */
 size_t xg_batch_workspace_bytes(void);

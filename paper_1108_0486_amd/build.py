@@ -14,8 +14,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB_PATH = os.path.join(PKG, "libxg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-SOURCES = ["xg_kernels.hip", "xg_family.hip", "xg_plan_dev.hip", "xg_util.hip", "xg_api.cpp", "xg_serve.cpp",
-           "xg_jump.cpp", "xg_plan.cpp", "xg_tune.cpp"]
+SOURCES = ["xg_kernels.hip", "xg_family.hip", "xg_plan_dev.hip", "xg_static.hip", "xg_util.hip", "xg_api.cpp",
+           "xg_serve.cpp", "xg_jump.cpp", "xg_plan.cpp", "xg_tune.cpp"]
 
 # -packed-fp32-ops: no packed FP32 instructions in generated code.
 # -ffp-contract=off: every FP32 operation rounds as written (no implicit FMA).

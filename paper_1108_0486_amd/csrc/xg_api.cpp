@@ -46,6 +46,9 @@ xg_status make_ctx(xg_ctx **out, void *d_state, size_t state_bytes, uint64_t num
   char arch[sizeof(xg_ctx::arch)];
   const xg_status st = current_gfx950(&dev, &cus, arch, sizeof arch);
   if (st != XG_OK) return st;
+  // The static batch scratch's address on this device, set up before any
+  // caller can be capturing a graph (a failure surfaces in that call).
+  (void)xg::static_scratch_prepare(dev);
   xg_ctx *c = new (std::nothrow) xg_ctx{};
   if (!c) return XG_ENOMEM;
   c->d_state = static_cast<uint32_t *>(d_state);
@@ -202,49 +205,6 @@ constexpr uint32_t kMaxTileSlots = 65536;
 xg::PlanLayout batch_layout(const xg_ctx *ctx, uint32_t max_reqs, uint32_t max_tiles) {
   const uint32_t jump_bytes = (uint32_t)(xg::member_degree(ctx->family) / 8);
   return xg::plan_layout(max_reqs, max_tiles, xg::family_state_bytes(ctx->family), jump_bytes);
-}
-
-// The batch launch shape for tune_key: the tuning cache's entry for this
-// handle's device and family, else the default.
-xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, xg::Shape *shape) {
-  *shape = xg::kDefaultBatch;
-  if (!tune_key) return XG_OK;
-  xg_tune t;
-  const xg_status st = xg_tune_cache_get(ctx->arch, ctx->num_cus, ctx->family, tune_key, &t, nullptr);
-  if (st == XG_EINVAL) return XG_EINVAL;
-  xg::Shape cached;
-  if (st == XG_OK && tune_to_shape(&t, t.blocks_per_cu, &cached)) *shape = cached;
-  return XG_OK;
-}
-
-// Plans num_reqs requests into the scratch at base (tiles as configured on
-// ctx).
-hipError_t plan_on_device(const xg_ctx *ctx, void *base, const xg::PlanLayout &layout, const xg_request *d_reqs,
-                          uint32_t num_reqs, hipStream_t s) {
-  const xg::PlanPtrs p = xg::plan_ptrs(base, layout);
-  return xg::launch_plan(p, layout, d_reqs, num_reqs, ctx->num_streams, ctx->tile_words,
-                         ctx->tile_words ? ctx->batch_max_tiles : 0, s);
-}
-
-// Serves the table the planner left in the scratch at base on the streams at
-// state: the tiles' start states, then the persistent launch.  requeue
-// re-arms the queue first (to serve the same plan again).
-hipError_t serve_planned(const xg_ctx *ctx, void *base, const xg::PlanLayout &layout, uint32_t num_reqs,
-                         uint32_t *state, void *d_out, const xg::Shape &shape, hipStream_t s, bool requeue = false) {
-  const xg::PlanPtrs p = xg::plan_ptrs(base, layout);
-  const uint32_t tiles = ctx->tile_words ? ctx->batch_max_tiles : 0;
-  const uint32_t max_items = num_reqs + tiles;
-  hipError_t e = requeue ? xg::launch_work_requeue(p.work, s) : hipSuccess;
-  if (e != hipSuccess) return e;
-  if (!paper_member(ctx))
-    return xg::launch_family_batch(ctx->family, shape, ctx->num_cus, reinterpret_cast<unsigned char *>(state),
-                                   ctx->num_streams, p.table, p.offs, max_items, d_out, UINT64_MAX, p.work, s);
-  const xg::SegmentArgs seg{p.jump, ctx->tile_words, tiles ? xg::kMaxSegments - 1 : 0u, p.stage, tiles};
-  if (tiles) e = xg::launch_seg_starts(state, ctx->num_streams, p.table, max_items, p.work, seg, s);
-  if (e == hipSuccess)
-    e = xg::launch_batch(shape, ctx->num_cus, state, ctx->num_streams, p.table, p.offs, max_items,
-                         static_cast<uint32_t *>(d_out), UINT64_MAX, p.work, s, tiles ? &seg : nullptr);
-  return e;
 }
 
 }  // namespace
@@ -525,16 +485,18 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   const uintptr_t out_align = ctx->family == XG_FAMILY_R64_W64 ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_out) % out_align) return XG_EALIGN;
   xg::Shape shape;
-  xg_status st = batch_shape(ctx, tune_key, &shape);
+  xg_status st = xg::batch_shape(ctx, tune_key, &shape);
   if (st != XG_OK) return st;
   st = check_ctx_device(ctx);
   if (st != XG_OK) return st;
   // An empty table still runs the planner, which clears the workspace's
   // counts and error word.
   const hipStream_t s = static_cast<hipStream_t>(stream);
-  hipError_t e = plan_on_device(ctx, ctx->d_batch, ctx->batch_layout, d_reqs, num_reqs, s);
+  hipError_t e = xg::plan_on_device(ctx, ctx->d_batch, ctx->batch_layout, d_reqs, num_reqs, ctx->tile_words,
+                                    ctx->batch_max_tiles, s);
   if (e == hipSuccess)
-    e = serve_planned(ctx, ctx->d_batch, ctx->batch_layout, num_reqs, ctx->d_state, d_out, shape, s);
+    e = xg::serve_planned(ctx, ctx->d_batch, ctx->batch_layout, num_reqs, ctx->tile_words, ctx->batch_max_tiles,
+                          ctx->d_state, d_out, shape, s);
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 
@@ -583,7 +545,9 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   if (result != XG_OK) return result;
   const hipStream_t s = static_cast<hipStream_t>(stream);
   const size_t state_bytes = xg_family_state_bytes(ctx->family, ctx->num_streams);
-  if (plan_on_device(ctx, ctx->d_batch, ctx->batch_layout, d_reqs, num_reqs, s) != hipSuccess) return XG_EHIP;
+  if (xg::plan_on_device(ctx, ctx->d_batch, ctx->batch_layout, d_reqs, num_reqs, ctx->tile_words,
+                         ctx->batch_max_tiles, s) != hipSuccess)
+    return XG_EHIP;
 
   static const uint32_t kWpb[] = {1, 2, 4, 8, 16};
   static const uint32_t kUnroll[] = {1, 2, 4, 8};
@@ -614,8 +578,9 @@ xg_status xg_autotune_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
             if (hipMemcpyAsync(d_scratch_state, ctx->d_state, state_bytes, hipMemcpyDeviceToDevice, s) !=
                     hipSuccess ||
                 hipEventRecord(t0, s) != hipSuccess ||
-                serve_planned(ctx, ctx->d_batch, ctx->batch_layout, num_reqs,
-                              static_cast<uint32_t *>(d_scratch_state), d_scratch_out, shape, s, true) !=
+                xg::serve_planned(ctx, ctx->d_batch, ctx->batch_layout, num_reqs, ctx->tile_words,
+                                  ctx->batch_max_tiles, static_cast<uint32_t *>(d_scratch_state), d_scratch_out,
+                                  shape, s, true) !=
                     hipSuccess ||
                 hipEventRecord(t1, s) != hipSuccess || hipEventSynchronize(t1) != hipSuccess ||
                 hipEventElapsedTime(&t, t0, t1) != hipSuccess) {
@@ -670,3 +635,46 @@ const char *xg_strerror(xg_status status) {
 }
 
 }  // extern "C"
+
+namespace xg {
+
+xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, Shape *shape) {
+  *shape = kDefaultBatch;
+  if (!tune_key) return XG_OK;
+  xg_tune t;
+  const xg_status st = xg_tune_cache_get(ctx->arch, (uint32_t)ctx->num_cus, ctx->family, tune_key, &t, nullptr);
+  if (st == XG_EINVAL) return XG_EINVAL;
+  if (st == XG_OK) {
+    const Shape cached{t.waves_per_block, t.unroll, t.blocks_per_cu,
+                       t.store_words ? t.store_words : (t.unroll >= 4 ? 4u : 1u)};
+    if (shape_valid(cached)) *shape = cached;
+  }
+  return XG_OK;
+}
+
+hipError_t plan_on_device(const xg_ctx *ctx, void *base, const PlanLayout &layout, const xg_request *d_reqs,
+                          uint32_t num_reqs, uint64_t tile_words, uint32_t max_tiles, hipStream_t s) {
+  const PlanPtrs p = plan_ptrs(base, layout);
+  return launch_plan(p, layout, d_reqs, num_reqs, ctx->num_streams, tile_words, tile_words ? max_tiles : 0, s);
+}
+
+hipError_t serve_planned(const xg_ctx *ctx, void *base, const PlanLayout &layout, uint32_t num_reqs,
+                         uint64_t tile_words, uint32_t max_tiles, uint32_t *state, void *d_out, const Shape &shape,
+                         hipStream_t s, bool requeue) {
+  const PlanPtrs p = plan_ptrs(base, layout);
+  const uint32_t tiles = tile_words ? max_tiles : 0;
+  const uint32_t max_items = num_reqs + tiles;
+  hipError_t e = requeue ? launch_work_requeue(p.work, s) : hipSuccess;
+  if (e != hipSuccess) return e;
+  if (ctx->family != XG_FAMILY_R128_W32)
+    return launch_family_batch(ctx->family, shape, ctx->num_cus, reinterpret_cast<unsigned char *>(state),
+                               ctx->num_streams, p.table, p.offs, max_items, d_out, UINT64_MAX, p.work, s);
+  const SegmentArgs seg{p.jump, tile_words, tiles ? kMaxSegments - 1 : 0u, p.stage, tiles};
+  if (tiles) e = launch_seg_starts(state, ctx->num_streams, p.table, max_items, p.work, seg, s);
+  if (e == hipSuccess)
+    e = launch_batch(shape, ctx->num_cus, state, ctx->num_streams, p.table, p.offs, max_items,
+                     static_cast<uint32_t *>(d_out), UINT64_MAX, p.work, s, tiles ? &seg : nullptr);
+  return e;
+}
+
+}  // namespace xg

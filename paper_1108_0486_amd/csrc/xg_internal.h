@@ -113,6 +113,31 @@ hipError_t launch_family_skip(uint32_t family, unsigned char *state, uint64_t fi
 
 }  // namespace xg
 
+struct xg_ctx;
+
+namespace xg {
+
+// The one-call batch, shared by its entry points (xg_api.cpp).
+// The launch shape for tune_key: the tuning cache's entry for ctx's device
+// and family, else the default (XG_EINVAL for a malformed key).
+xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, Shape *shape);
+// Plans num_reqs requests (device memory, table order) into the scratch at
+// base, with tiles of tile_words words in up to max_tiles slots (0: none).
+hipError_t plan_on_device(const xg_ctx *ctx, void *base, const PlanLayout &layout, const xg_request *d_reqs,
+                          uint32_t num_reqs, uint64_t tile_words, uint32_t max_tiles, hipStream_t s);
+// Serves the table the planner left in the scratch at base on the streams at
+// state (the tiles' start states, then the persistent launch); requeue
+// re-arms the queue first, to serve the same plan again.
+hipError_t serve_planned(const xg_ctx *ctx, void *base, const PlanLayout &layout, uint32_t num_reqs,
+                         uint64_t tile_words, uint32_t max_tiles, uint32_t *state, void *d_out, const Shape &shape,
+                         hipStream_t s, bool requeue = false);
+
+// Looks up the device address of xg_generate_batch_static's scratch array on
+// device dev (current) once; called when a handle is created there.
+hipError_t static_scratch_prepare(int dev);
+
+}  // namespace xg
+
 // The handle behind xg_ctx (include/xg.h).
 struct xg_ctx {
   uint32_t *d_state;

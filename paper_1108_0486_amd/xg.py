@@ -137,6 +137,7 @@ def lib() -> ctypes.CDLL:
         "xg_tune_cache_clear": (None, []),
         "xg_tune_identity": (st, [vp, ctypes.c_char_p, ctypes.c_size_t, P(u32)]),
         "xg_batch_read_plan": (st, [vp, P(xg_request), u32, P(u32), u32, P(u32), P(u32), vp]),
+        "xg_generate_batch_static": (st, [vp, vp, u32, vp, ctypes.c_char_p, vp, vp]),
         "xg_strerror": (ctypes.c_char_p, [st]),
         "xg_server_device_bytes": (ctypes.c_size_t, [P(xg_server_config)]),
         "xg_server_create": (st, [P(vp), vp, P(xg_server_config), vp, u64, vp, ctypes.c_size_t]),
@@ -358,6 +359,15 @@ def xg_set_batch_scratch(ctx, d_scratch: int | None, scratch_bytes: int, max_req
 def xg_generate_batch(ctx, d_reqs: int, num_reqs: int, d_out: int, tune_key: str | None = None,
                       stream: int = 0) -> None:
     _check(lib().xg_generate_batch(ctx, d_reqs, num_reqs, d_out, _key(tune_key), stream), "xg_generate_batch")
+
+
+XG_STATIC_MAX_REQS = 65536
+
+
+def xg_generate_batch_static(ctx, d_reqs: int, num_reqs: int, d_out: int, tune_key: str | None = None,
+                             d_error: int | None = None, stream: int = 0) -> None:
+    _check(lib().xg_generate_batch_static(ctx, d_reqs, num_reqs, d_out, _key(tune_key), d_error, stream),
+           "xg_generate_batch_static")
 
 
 def xg_autotune_batch(ctx, d_reqs: int, num_reqs: int, d_scratch_out: int, d_scratch_state: int,
