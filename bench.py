@@ -4,11 +4,11 @@
 Workload (one step): 1024 independent streams (stream i seeded from 42 + i),
 2^20 outputs each as uint32, then 2^20 more each as FP32 uniforms in [0, 1)
 by the top-24-bit mapping; each type written contiguously to HBM by one plain
-launch in the bulk-fill layout (xg_fill_*: 64-word chunks of the streams
-interleaved, so the wavefronts write one dense region).  A step produces 2^31
-random numbers.  The streams advance across steps, so every step generates
-new numbers.  The stream-major layout (xg_generate_*) is timed beside it and
-reported under "stream_major".
+launch in the stream-major layout (xg_generate_*: stream i's outputs at
+out[i * 2^20 + t]).  A step produces 2^31 random numbers.  The streams advance
+across steps, so every step generates new numbers.  The bulk-fill layout
+(xg_fill_*: 64-word chunks of the streams interleaved, so the wavefronts write
+one dense region) is timed beside it and reported under "bulk_fill".
 
 Prints one JSON line: RN/s of the whole job, the roofline of the uint32
 kernel (HBM write bound, per-launch duration from HIP events on the launch
@@ -32,7 +32,7 @@ STREAMS = 1024
 N = 1 << 20
 SEED = 42
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_bulk_u32.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_major_u32.json")
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_fused_moments.json")
 # VALU issue capacity: 256 CUs x 4 SIMDs at 2.4 GHz, each SIMD issuing one
 # wave64 instruction per 4 cycles for 32-bit integer and conversion work (16
@@ -82,13 +82,49 @@ def measured_valu():
     return insts, insts * sum(f * cyc[k] for k, f in mix.items()) / SIMD_CYCLES_PER_S
 
 
+def host_threads() -> int:
+    """Host cores this process may run on."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
+
+
+# The method's own work per normal pair (independent of the kernel's
+# instruction mix): two generator words at 13 integer operations each
+# (recurrence 9, Weyl 1, tempering 2, combine 1); two uniform maps (a shift and
+# an integer-to-float conversion at the 32-bit rate, an FP32 scale); one FP32
+# multiply for -2 ln u; two FP32 multiplies (rho cos, rho sin); four FP32
+# moment updates (fused kernel only); and four transcendentals (log, sqrt,
+# sin, cos).  Issue cycles per wave64 instruction on one SIMD: 4 for 32-bit
+# integer and conversion, 2 for FP32 add / mul / FMA, 8 for transcendentals.
+FUSED_PAIR_OPS = {"int32": 2 * 13 + 2 + 2, "fp32": 2 + 1 + 2 + 4, "transcendental": 4}
+FUSED_OPS_PER_PAIR = sum(FUSED_PAIR_OPS.values())
+FUSED_CYCLES_PER_64_PAIRS = 4 * FUSED_PAIR_OPS["int32"] + 2 * FUSED_PAIR_OPS["fp32"] + 8 * FUSED_PAIR_OPS["transcendental"]
+
+
+def fused_algorithmic_floor(pairs: int):
+    """(operations, minimum seconds) of the fused normal moments over `pairs`
+    pairs at full VALU issue on every SIMD."""
+    return FUSED_OPS_PER_PAIR * pairs, pairs / 64 * FUSED_CYCLES_PER_64_PAIRS / SIMD_CYCLES_PER_S
+
+
+def normals_floor(pairs: int):
+    """The same without the four moment updates (the unfused normals)."""
+    cycles = FUSED_CYCLES_PER_64_PAIRS - 2 * 4
+    return (FUSED_OPS_PER_PAIR - 4) * pairs, pairs / 64 * cycles / SIMD_CYCLES_PER_S
+
+
 def cpu_baseline(threads: int):
     """The oracle on one full step of the workload (u32 and f32 of all 1024
-    streams), in slices of 64 streams to bound host memory."""
+    streams), in slices of at least 64 streams (and at least one per thread)
+    to bound host memory."""
     import numpy as np
     from oracle import oracle as O
 
-    slice_ = 64
+    slice_ = max(64, threads)
+    while STREAMS % slice_:
+        slice_ += 1
     t0 = time.perf_counter()
     total = 0
     for first in range(0, STREAMS, slice_):
@@ -105,14 +141,23 @@ def cpu_baseline(threads: int):
 
 
 def cpu_model() -> str:
+    """The host CPU as /proc/cpuinfo names it: model name, vendor, family /
+    model / stepping, and the logical CPUs it lists."""
+    fields, cpus = {}, 0
     try:
         with open("/proc/cpuinfo") as f:
             for line in f:
-                if line.startswith("model name"):
-                    return line.split(":", 1)[1].strip()
+                if ":" not in line:
+                    continue
+                k, v = (x.strip() for x in line.split(":", 1))
+                if k == "processor":
+                    cpus += 1
+                fields.setdefault(k, v)
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    return "%s (%s, family %s model %s stepping %s; %d logical CPUs listed, %d usable here)" % (
+        fields.get("model name", "unknown"), fields.get("vendor_id", "?"), fields.get("cpu family", "?"),
+        fields.get("model", "?"), fields.get("stepping", "?"), cpus, host_threads())
 
 
 # The paper's own throughput (Section 3, Table 1), for context only: other
@@ -123,63 +168,91 @@ PAPER_TABLE1 = {"source": "Section 3, Table 1 (context, not a target)",
                 "hardware": "NVIDIA GeForce GTX 480; one GPU of a GeForce GTX 295; CUDA 3.2"}
 
 
-def extra_ragged_batch(torch, dev):
-    """65536 streams, lengths log-uniform in [2^10, 2^20] (seed 7), uint32, one
-    persistent launch in a HIP graph with the autotuner's shape, against one
-    plain launch per stream on the same GPU."""
-    from paper_1108_0486_amd import workloads as W
-    from paper_1108_0486_amd.batch import Batch
-    from paper_1108_0486_amd.streams import XorgensStreams
+RAGGED_KEY = "ragged65536/u32"
 
-    lengths = W.ragged_lengths()
-    off = W.csr_offsets(lengths)
-    total = int(off[-1])
-    S = len(lengths)
-    gs = XorgensStreams(S, seed=SEED, device=dev)
-    b = Batch(gs, [(i, int(lengths[i]), int(off[i]), 0) for i in range(S)], total)
-    t0 = time.perf_counter()
-    best, recs = b.autotune(reps=1)
-    tune_s = time.perf_counter() - t0
-    default_ms = [r[4] for r in recs if r[:4] == (4, 8, 8, 4)]
-    g = b.capture_graph(tune=best)
+
+def _graph_ms(torch, g, reps=5):
     g.replay()
     torch.cuda.synchronize()
-    reps = 5
     a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
         g.replay()
     e.record()
     torch.cuda.synchronize()
-    batch_ms = a.elapsed_time(e) / reps
-    # baseline: one plain launch per stream (one wavefront each), in order on one stream
-    out = b.out
-    stream = torch.cuda.current_stream()
-    torch.cuda.synchronize()
-    a.record()
+    return a.elapsed_time(e) / reps
+
+
+def extra_ragged_batch(torch, dev, shape=None, per_stream=True):
+    """65536 streams, lengths log-uniform in [2^10, 2^20] (seed 7), uint32:
+    the one-call batch (xg_generate_batch: the table in stream order, grouped
+    and ordered on the device, served by one persistent launch) captured in a
+    HIP graph, with the shape the autotuner stored in the tuning cache under
+    RAGGED_KEY; the host-planned batch kernel alone in the same shape; and one
+    plain launch per stream on the same GPU."""
+    from paper_1108_0486_amd import workloads as W
+    from paper_1108_0486_amd import xg
+    from paper_1108_0486_amd.batch import Batch, PlannedBatch
+    from paper_1108_0486_amd.streams import XorgensStreams
+
+    lengths = W.ragged_lengths()
+    off = W.csr_offsets(lengths)
+    total = int(off[-1])
+    S = len(lengths)
+    reqs = [(i, int(lengths[i]), int(off[i]), 0) for i in range(S)]
+    gs = XorgensStreams(S, seed=SEED, device=dev)
+    b = Batch(gs, reqs, total)
     t0 = time.perf_counter()
-    for i in range(S):
-        gs.u32(int(lengths[i]), first=i, count=1, out=out[int(off[i]):int(off[i + 1])], stream=stream)
-    e.record()
-    torch.cuda.synchronize()
-    plain_wall = time.perf_counter() - t0
-    plain_ms = a.elapsed_time(e)
+    recs = []
+    if shape is None:
+        best, recs = b.autotune(reps=1, tune_key=RAGGED_KEY)
+    else:
+        best = tuple(shape)
+        arch, cus = xg.xg_tune_identity(gs.ctx)
+        xg.xg_tune_cache_put(arch, cus, xg.XG_FAMILY_R128_W32, RAGGED_KEY, best)
+    tune_s = time.perf_counter() - t0
+    default_ms = [r[4] for r in recs if r[:4] == (4, 8, 8, 4)]
+    batch_ms = _graph_ms(torch, b.capture_graph(tune_key=RAGGED_KEY))
+    err = b.error_flag()
+    out = b.out
+    del b
+    pb = PlannedBatch(gs, reqs, total, out=out)
+    kernel_ms = _graph_ms(torch, pb.capture_graph(tune=best))
+    err |= pb.error_flag()
+    del pb
     res = {
         "workload": "65536 streams, n_i = floor(2^(10 + 10 U_i)) (U from seed 7), uint32, CSR offsets",
         "total_rn": total,
+        "path": "xg_generate_batch (one call: device grouping and ordering, then the persistent launch), "
+                "captured in a HIP graph, shape from the tuning cache key %r" % RAGGED_KEY,
         "batched_graph_ms": batch_ms,
         "batched_rn_per_s": total / (batch_ms * 1e-3),
         "batched_frac_of_hbm_peak": 4 * total / (batch_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "batch_kernel_graph_ms": kernel_ms,
+        "batch_kernel_frac_of_hbm_peak": 4 * total / (kernel_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "device_planning_ms": batch_ms - kernel_ms,
         "autotuned_shape": {"waves_per_block": best[0], "unroll": best[1], "blocks_per_cu": best[2],
                             "store_words": best[3]},
         "default_shape_ms": default_ms[0] if default_ms else None,
         "autotune_s": tune_s,
         "autotune_candidates": len(recs),
-        "per_stream_plain_launches_ms": plain_ms,
-        "per_stream_plain_wall_s": plain_wall,
-        "speedup_batched_vs_per_stream": plain_ms / batch_ms,
+        "error_flag": err,
     }
-    del b, g, gs, out
+    if per_stream:
+        # baseline: one plain launch per stream (one wavefront each), in order on one stream
+        stream = torch.cuda.current_stream()
+        a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        t0 = time.perf_counter()
+        for i in range(S):
+            gs.u32(int(lengths[i]), first=i, count=1, out=out[int(off[i]):int(off[i + 1])], stream=stream)
+        e.record()
+        torch.cuda.synchronize()
+        res["per_stream_plain_wall_s"] = time.perf_counter() - t0
+        res["per_stream_plain_launches_ms"] = a.elapsed_time(e)
+        res["speedup_batched_vs_per_stream"] = res["per_stream_plain_launches_ms"] / batch_ms
+    del gs, out
     torch.cuda.empty_cache()
     return res
 
@@ -218,7 +291,7 @@ def extra_fused_moments(torch, dev):
     torch.cuda.empty_cache()
     # the FP64 oracle on a sample of the same workload (host cores)
     from oracle import oracle as O
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_threads()
     sample = 64
     st = O.OracleStreams(SEED, sample)
     t0 = time.perf_counter()
@@ -226,17 +299,30 @@ def extra_fused_moments(torch, dev):
     dt = time.perf_counter() - t0
     cpu = {"value": sample * N / dt, "unit": "normals/s", "cores": threads, "kind": "oracle",
            "sample": "64 of the 4096 streams x 2^18 FP64 Box-Muller normals and their sums (%.2f s)" % dt}
+    pairs = S * N // 2
+    ops, t_min = fused_algorithmic_floor(pairs)
+    roof = {"bound": "alu", "achieved": ops / (ms * 1e-3) / 1e9, "peak": ops / t_min / 1e9,
+            "unit": "Gop/s (the method's operations: %d per normal pair, weighted by their VALU issue "
+                    "rates)" % FUSED_OPS_PER_PAIR,
+            "frac": t_min / (ms * 1e-3), "ops_per_pair": dict(FUSED_PAIR_OPS),
+            "issue_cycles_per_64_pairs": FUSED_CYCLES_PER_64_PAIRS, "min_ms": t_min * 1e3}
     valu = measured_valu()
-    roof = None
+    issue = None
     if valu is not None:
-        insts, t_min = valu
-        lane_ops = 64 * insts
-        roof = {"bound": "alu", "achieved": lane_ops / (ms * 1e-3) / 1e12, "peak": lane_ops / t_min / 1e12,
-                "unit": "TOP/s (32-bit VALU lane operations; peak = this instruction mix at full issue)",
-                "frac": t_min / (ms * 1e-3), "valu_wave_insts_per_launch": insts, "min_issue_ms": t_min * 1e3}
+        insts, t_issue = valu
+        issue = {"valu_wave_insts_per_launch": insts, "min_issue_ms_of_this_mix": t_issue * 1e3,
+                 "frac": t_issue / (ms * 1e-3),
+                 "note": "how busy the VALU is with the kernel's own instructions (not the method's work)"}
+    unfused_ops, unfused_t = normals_floor(pairs)
     return {"workload": "4096 streams x 2^18 FP32 normals (Box-Muller), sums of z and z^2 in-kernel",
-            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3), "roofline": roof, "cpu_oracle": cpu,
-            "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3)}
+            "kernel_ms": ms, "rn_per_s": S * N / (ms * 1e-3), "roofline": roof, "issue_efficiency": issue,
+            "cpu_oracle": cpu,
+            "unfused_normals_ms": unfused_ms, "unfused_rn_per_s": S * N / (unfused_ms * 1e-3),
+            "unfused_roofline": {"hbm_floor_ms": 4 * S * N / (HBM_PEAK_GBS * 1e9) * 1e3,
+                                 "alu_floor_ms": unfused_t * 1e3,
+                                 "frac_of_hbm_peak": 4 * S * N / (unfused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                                 "frac_of_larger_floor": max(4 * S * N / (HBM_PEAK_GBS * 1e9), unfused_t)
+                                 / (unfused_ms * 1e-3)}}
 
 
 def _member_ragged_batch(torch, dev, fam):
@@ -413,6 +499,12 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=200_000)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run one 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--only-extras", action="store_true",
+                    help="run only the chosen extras and print their JSON (for profiling one workload)")
+    ap.add_argument("--ragged-shape", default=None,
+                    help="waves_per_block,unroll,blocks_per_cu,store_words for the ragged batch (no autotune)")
+    ap.add_argument("--no-per-stream", action="store_true",
+                    help="skip the ragged batch's one-launch-per-stream baseline")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the library has no multi-GPU path "
@@ -424,6 +516,21 @@ def main() -> int:
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    ragged_shape = tuple(int(v) for v in args.ragged_shape.split(",")) if args.ragged_shape else None
+    extra_runs = [("ragged_batch", "ragged",
+                   lambda: extra_ragged_batch(torch, dev, ragged_shape, not args.no_per_stream)),
+                  ("fused_moments", "fused", lambda: extra_fused_moments(torch, dev)),
+                  ("family_members", "family", lambda: extra_family_members(torch, dev)),
+                  ("serving", "serving", lambda: extra_serving(torch, dev, args.serve_requests))]
+    if args.only_extras:
+        chosen = set(args.extras.split(","))
+        res = {}
+        for key, name, f in extra_runs:
+            if name in chosen:
+                print("extra: %s" % key, file=sys.stderr, flush=True)
+                res[key] = f()
+        print(json.dumps({"extras": res}), flush=True)
+        return 0
     gs = XorgensStreams(STREAMS, seed=SEED, device=dev)
     if args.waves_per_block or args.unroll or args.store_words:
         wpb, un, sw = gs.plain_tune()
@@ -463,8 +570,8 @@ def main() -> int:
     torch.cuda.synchronize()
 
     K = args.steps
-    u32_ms, f32_ms, wall = timed(fill_u, fill_f, K)
-    sm_u32_ms, sm_f32_ms, _ = timed(gen_u, gen_f, max(5, K // 2))
+    u32_ms, f32_ms, wall = timed(gen_u, gen_f, K)
+    fill_u32_ms, fill_f32_ms, _ = timed(fill_u, fill_f, max(5, K // 2))
     rn_per_step = 2 * STREAMS * N
     ms_per_step = wall * 1e3 / K
     bytes_per_launch = 4 * STREAMS * N
@@ -503,18 +610,14 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     traffic = measured_traffic()
-    threads = max(1, min(16, os.cpu_count() or 1))
+    threads = host_threads()
     cpu = None if args.no_cpu_baseline else cpu_baseline(threads)
     del out_u, out_f
     torch.cuda.empty_cache()
     extras = None
     if not args.no_extras:
         chosen = set(args.extras.split(","))
-        run = [("ragged_batch", "ragged", lambda: extra_ragged_batch(torch, dev)),
-               ("fused_moments", "fused", lambda: extra_fused_moments(torch, dev)),
-               ("family_members", "family", lambda: extra_family_members(torch, dev)),
-               ("serving", "serving", lambda: extra_serving(torch, dev, args.serve_requests))]
-        extras = {key: f() for key, name, f in run if name in chosen}
+        extras = {key: f() for key, name, f in extra_runs if name in chosen}
 
     wpb, un, sw = gs.plain_tune()
     line = {
@@ -533,14 +636,14 @@ def main() -> int:
         "config": {
             "workload": "bulk uniform generation: 1024 xorgens streams (seed 42 + i) x 2^20 outputs, "
                         "uint32 then FP32 [0,1) (top-24-bit), one plain launch per type, written contiguously "
-                        "to HBM in the bulk-fill layout (64-word chunks of the streams interleaved)",
-            "layout": "bulk-fill (xg_fill_u32 / xg_fill_f32)",
+                        "to HBM stream-major (stream i at out[i * 2^20 + t])",
+            "layout": "stream-major (xg_generate_u32 / xg_generate_f32)",
             "streams": STREAMS,
             "outputs_per_stream_per_type": N,
             "rn_per_step": rn_per_step,
             "params": "(r,s,a,b,c,d)=(128,65,15,14,12,17), w=32, omega=0x9E3779B9, gamma=16",
             "launch": {"waves_per_block": wpb or "auto: 4 (one stream per SIMD)",
-                       "unroll": un or "auto: 4 for the uint32 fill, 8 for FP32", "store_words": sw},
+                       "unroll": un or "auto: 2 for the stream-major launches", "store_words": sw},
         },
         "roofline": {
             "bound": "hbm",
@@ -549,18 +652,19 @@ def main() -> int:
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "kernel": "k_fill<u32> (xg_fill_u32)",
+            "kernel": "k_generate<u32> (xg_generate_u32, stream-major)",
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "avg_launch_ms": u32_ms,
         },
-        "kernels_ms": {"fill_u32": u32_ms, "fill_f32": f32_ms,
-                       "stream_major_u32": sm_u32_ms, "stream_major_f32": sm_f32_ms},
+        "kernels_ms": {"stream_major_u32": u32_ms, "stream_major_f32": f32_ms,
+                       "fill_u32": fill_u32_ms, "fill_f32": fill_f32_ms},
         "f32_GBs": bytes_per_launch / (f32_ms * 1e-3) / 1e9,
-        "stream_major": {
-            "layout": "stream-major (xg_generate_u32 / xg_generate_f32): out[i * 2^20 + t]",
-            "rn_per_s_kernels": rn_per_step / ((sm_u32_ms + sm_f32_ms) * 1e-3),
-            "u32_GBs": bytes_per_launch / (sm_u32_ms * 1e-3) / 1e9,
-            "u32_frac_of_peak": bytes_per_launch / (sm_u32_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+        "bulk_fill": {
+            "layout": "bulk-fill (xg_fill_u32 / xg_fill_f32): 64-word chunks of the streams interleaved",
+            "rn_per_s_kernels": rn_per_step / ((fill_u32_ms + fill_f32_ms) * 1e-3),
+            "u32_GBs": bytes_per_launch / (fill_u32_ms * 1e-3) / 1e9,
+            "u32_frac_of_peak": bytes_per_launch / (fill_u32_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "f32_GBs": bytes_per_launch / (fill_f32_ms * 1e-3) / 1e9,
         },
         "fill_ceiling_GBs": fill_gbs,
         "frac_of_fill_ceiling": achieved / fill_gbs,

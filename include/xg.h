@@ -619,6 +619,10 @@ uint64_t xg_server_outstanding(const xg_server *srv);
 
 xg_status xg_server_get_stats(const xg_server *srv, xg_server_stats *out);
 
+/* The launch shape the server's batches use (all zero: the default shape).
+ * Errors: XG_EINVAL (NULL). */
+xg_status xg_server_get_tune(const xg_server *srv, xg_tune *out);
+
 /* Waits for in-flight batches, then frees the server's host resources and
  * streams (never the caller's buffers).  NULL is accepted. */
 void xg_server_destroy(xg_server *srv);

@@ -151,7 +151,12 @@ def _ptr(a: np.ndarray, ctype):
 
 
 def default_threads() -> int:
-    return max(1, min(16, os.cpu_count() or 1))
+    """Host cores this process may run on (the oracle's streams are independent,
+    so each thread takes a share of them)."""
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except (AttributeError, OSError):
+        return max(1, os.cpu_count() or 1)
 
 
 # ---------------------------------------------------------------------------

@@ -484,6 +484,12 @@ xg_status xg_server_get_stats(const xg_server *s, xg_server_stats *out) {
   return XG_OK;
 }
 
+xg_status xg_server_get_tune(const xg_server *s, xg_tune *out) {
+  if (!s || !out) return XG_EINVAL;
+  *out = s->default_tune ? xg_tune{0, 0, 0, 0} : s->tune;
+  return XG_OK;
+}
+
 void xg_server_destroy(xg_server *s) {
   if (!s) return;
   destroy_lanes(s);

@@ -36,7 +36,7 @@ class Completion:
 
 class Server:
     def __init__(self, streams: XorgensStreams, pool_elems: int, num_lanes: int = 4, max_batch: int = 1024,
-                 tune=None, segment_words: int = 0):
+                 tune=None, segment_words: int = 0, tune_key: str | None = None):
         self.streams = streams
         # Pool elements are the member's word width: 8 bytes for the 64-bit member.
         wide = streams.family == xg.XG_FAMILY_R64_W64
@@ -46,7 +46,7 @@ class Server:
             raise ValueError("invalid server configuration")
         self.tables = torch.empty(nbytes, dtype=torch.uint8, device=streams.device)
         self.srv = xg.xg_server_create(streams.ctx, num_lanes, max_batch, tune, self.pool.data_ptr(), pool_elems,
-                                       self.tables.data_ptr(), nbytes, segment_words)
+                                       self.tables.data_ptr(), nbytes, segment_words, tune_key)
         self._cap = 4096
         self._buf = (xg.xg_completion * self._cap)()
 

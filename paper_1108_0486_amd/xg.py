@@ -147,6 +147,7 @@ def lib() -> ctypes.CDLL:
         "xg_server_outstanding": (u64, [vp]),
         "xg_server_get_stats": (st, [vp, P(xg_server_stats)]),
         "xg_server_destroy": (None, [vp]),
+        "xg_server_get_tune": (st, [vp, P(xg_tune)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -475,6 +476,12 @@ def xg_server_get_stats(srv) -> dict:
     st = xg_server_stats()
     _check(lib().xg_server_get_stats(srv, ctypes.byref(st)), "xg_server_get_stats")
     return st.as_dict()
+
+
+def xg_server_get_tune(srv) -> tuple:
+    t = xg_tune()
+    _check(lib().xg_server_get_tune(srv, ctypes.byref(t)), "xg_server_get_tune")
+    return t.as_tuple()
 
 
 def xg_server_destroy(srv) -> None:

@@ -284,41 +284,81 @@ def _oracle_at(stream: int, q: int, P: int):
     return O.OracleStreams.from_state(ring[None, :], np.array([weyl], dtype=np.uint32), np.array([q], dtype=np.uint64))
 
 
-def test_serving_full_size_sampled():
+def test_server_takes_its_shape_from_the_tuning_cache():
+    """A server created with a tuning-cache key and no explicit shape runs
+    the cached shape (and its values still equal the oracle's); an absent key
+    leaves the default; a malformed key is refused."""
+    S = 16
+    gs = XorgensStreams(S, seed=SEED)
+    arch, cus = xg.xg_tune_identity(gs.ctx)
+    xg.xg_tune_cache_put(arch, cus, xg.XG_FAMILY_R128_W32, "test/serve/small", (2, 4, 3, 1), 0.5)
+    srv = Server(gs, pool_elems=1 << 20, num_lanes=2, max_batch=16, tune_key="test/serve/small")
+    assert xg.xg_server_get_tune(srv.srv) == (2, 4, 3, 1)
+    trace = W.serving_trace(60, num_streams=S, rate=100_000.0, seed=4, lo_exp=2, hi_exp=13)
+    summary, done, outputs = run_trace(srv, trace, keep_outputs=True, timeout_s=60)
+    assert summary["server"]["completed"] == len(trace)
+    _check_against_oracle(done, outputs, S)
+    srv.close()
+    gs2 = XorgensStreams(S, seed=SEED)
+    srv2 = Server(gs2, pool_elems=1 << 20, num_lanes=1, max_batch=16, tune_key="test/serve/absent")
+    assert xg.xg_server_get_tune(srv2.srv) == (0, 0, 0, 0)
+    srv2.close()
+    with pytest.raises(xg.XgError) as e:
+        Server(gs2, pool_elems=1 << 20, num_lanes=1, max_batch=16, tune_key='bad"key')
+    assert e.value.status == xg.XG_EINVAL
+
+
+def _check_request(c, host, P):
+    """A completed request's values against the oracle from its start
+    position; returns None or a description of the mismatch."""
+    ref = _oracle_at(c.stream, c.start_pos, P)
+    if c.dtype == xg.XG_U32:
+        ok = np.array_equal(host.view(np.uint32), ref.u32(c.n)[0])
+    elif c.dtype == xg.XG_F32:
+        ok = np.array_equal(host.view(np.float32), ref.f32(c.n)[0])
+    else:
+        ok = bool(ulp32_error(host.view(np.float32), ref.normal(c.n)[0]).max() <= 4.0)
+    return None if ok else (c.id, c.stream, c.start_pos, c.n, c.dtype)
+
+
+def test_serving_full_size_every_value():
     """The serving workload at full size: 10^5 resident streams, the bench's
     server (8 GiB pool, 4 lanes, batches of up to 8192 entries, requests over
     2^16 words split into jumped segments) and the first 1500 requests of the
-    seed-11 trace (N up to 2^24, all three dtypes), submitted at once so the
-    batches mix.  Every request's first 64 values, and for the 60 longest and
-    90 random others also 64 values in the middle and at the end (inside
-    jumped segments), equal the oracle's at the request's start position; and
-    every touched stream ends in the oracle's state after the words its
-    requests consumed."""
+    seed-11 trace (N up to 2^24, all three dtypes, 2.3 x 10^9 values),
+    submitted at once so the batches mix.  Every value of every request equals
+    the oracle's from the request's start position (checked on host threads
+    while the server runs), and every touched stream ends in the oracle's
+    state after the words its requests consumed."""
+    from concurrent.futures import ThreadPoolExecutor
+
     trace = W.serving_trace(1500)
     gs = XorgensStreams(W.SERVE_STREAMS, seed=SEED)
     srv = Server(gs, pool_elems=1 << 31, num_lanes=4, max_batch=8192, segment_words=1 << 16)
-    by_n = sorted(trace, key=lambda r: -r.n)
-    rng = np.random.default_rng(5)
-    deep = {r.rid for r in by_n[:60]} | {int(i) for i in rng.choice(len(trace), size=90, replace=False)}
     for r in trace:
         srv.submit(r.rid, r.stream, r.n, r.dtype)
-    got = {}
-    deadline = time.monotonic() + 120.0
-    while len(got) < len(trace) and time.monotonic() < deadline:
-        for c in srv.poll():
-            out = srv.output(c)
-            offs = [0]
-            if c.id in deep and c.n > 128:
-                offs += [(c.n // 2) & ~1, (c.n - 64) & ~1]
-            got[c.id] = (c, {t: out[t:t + 64].cpu().numpy().copy() for t in offs})
-            srv.release(c.id)
-    srv.close()
-    assert len(got) == len(trace)
     P = O.charpoly(O.PAPER)
+    done, futures, values = [], [], 0
+    with ThreadPoolExecutor(max_workers=O.default_threads()) as pool:
+        deadline = time.monotonic() + 300.0
+        while len(done) < len(trace) and time.monotonic() < deadline:
+            for c in srv.poll():
+                host = srv.output(c).cpu().numpy().copy()
+                srv.release(c.id)
+                done.append(c)
+                values += c.n
+                futures.append(pool.submit(_check_request, c, host, P))
+        bad = [f.result() for f in futures]
+    srv.close()
+    assert len(done) == len(trace)
+    bad = [x for x in bad if x is not None]
+    assert not bad, bad[:10]
+    assert values == sum(r.n for r in trace) and values > 2 * 10**9
+    assert sum(1 for c in done if c.n > (1 << 16)) > 100     # many requests ran as jumped segments
     # End state of every stream the trace touched: it depends on every word
     # its requests (and their jumped segments) generated.
     used = {}
-    for c, _ in got.values():
+    for c in done:
         used[c.stream] = used.get(c.stream, 0) + c.n + (c.n & 1 if c.dtype == xg.XG_NORMAL else 0)
     touched = sorted(used)
     ring, weyl, pos = gs.host_state(touched)
@@ -326,19 +366,6 @@ def test_serving_full_size_sampled():
         ref = _oracle_at(st, used[st], P)
         assert int(pos[j]) == used[st], st
         assert (ring[j] == ref.ring[0]).all() and int(weyl[j]) == int(ref.weyl[0]), st
-    splits = 0
-    for c, slices in got.values():
-        for t, v in slices.items():
-            ref = _oracle_at(c.stream, c.start_pos + t, P)
-            L = v.size
-            if c.dtype == xg.XG_U32:
-                assert (v.view(np.uint32) == ref.u32(L)[0]).all(), (c.id, t)
-            elif c.dtype == xg.XG_F32:
-                assert (v == ref.f32(L)[0]).all(), (c.id, t)
-            else:
-                assert ulp32_error(v, ref.normal(L)[0]).max() <= 4.0, (c.id, t)
-            splits += t >= (1 << 16)
-    assert splits >= 100          # many checked slices lie beyond the first segment
 
 
 @pytest.mark.parametrize("seed,seg,pool,lanes,max_batch", [
