@@ -8,6 +8,8 @@ undefined (any report aborts the program):
     which include no HIP header), whose jump polynomials must also equal the
     oracle's z^J mod P;
   * the request server's output pool, fuzzed against a brute-force model;
+  * the tuning cache's file reader on thousands of damaged files, and its
+    put / get from several threads;
   * the jump polynomials' lazy initialisation under ThreadSanitizer.
 """
 import os
@@ -68,6 +70,27 @@ def test_server_pool_under_sanitizers(tmp_path):
     _need("g++")
     cmd = ["g++", "-std=c++17", *SAN, "-I", CSRC, os.path.join(HERE, "sanitize", "pool_driver.cpp")]
     _run(cmd, tmp_path)
+
+
+def test_tune_cache_under_sanitizers(tmp_path):
+    """The tuning cache's JSON reader on damaged files (each loads or is
+    refused whole) and concurrent put / get, under ASan and UBSan."""
+    _need("g++")
+    cmd = ["g++", "-std=c++17", *SAN, "-I", os.path.join(ROOT, "include"), "-I", CSRC,
+           os.path.join(HERE, "sanitize", "tune_driver.cpp"), os.path.join(CSRC, "xg_tune.cpp"), "-lpthread"]
+    _run(cmd, tmp_path, str(tmp_path))
+
+
+def test_tune_cache_under_thread_sanitizer(tmp_path):
+    _need("g++")
+    exe = str(tmp_path / "tt")
+    subprocess.run(["g++", "-std=c++17", "-O1", "-g", "-fsanitize=thread", "-I", os.path.join(ROOT, "include"),
+                    "-I", CSRC, os.path.join(HERE, "sanitize", "tune_driver.cpp"), os.path.join(CSRC, "xg_tune.cpp"),
+                    "-o", exe, "-lpthread"], check=True, cwd=ROOT)
+    p = subprocess.run([exe, str(tmp_path)], capture_output=True, text=True, timeout=300,
+                       env=dict(os.environ, TSAN_OPTIONS="halt_on_error=1"))
+    assert p.returncode == 0 and p.stdout.strip().endswith("OK"), p.stdout + p.stderr
+    assert "ThreadSanitizer" not in p.stderr, p.stderr
 
 
 def test_jump_polynomials_under_thread_sanitizer(tmp_path):
