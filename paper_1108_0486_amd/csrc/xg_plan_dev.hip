@@ -11,7 +11,7 @@
 // Grouping is a sort of 64-bit keys (stream << 32 | request index): the keys
 // are distinct, so any correct sort leaves each stream's requests in array
 // order.  A bitonic network (compare-exchange passes in LDS within a
-// workgroup's 2048 keys, global passes above that) sorts them; the queue items
+// workgroup's 8192 keys, global passes above that) sorts them; the queue items
 // are sorted the same way on (inverted cost << 32 | group << 8 | tile).
 // Prefix sums are three-kernel block scans.
 #include <hip/hip_runtime.h>
@@ -25,7 +25,7 @@
 namespace xg {
 namespace {
 
-constexpr uint32_t kSortBlock = 2048;  // keys one workgroup sorts in LDS (1024 threads, two keys each)
+constexpr uint32_t kSortBlock = 8192;  // keys one workgroup sorts in LDS (1024 threads, eight keys each; 64 KB)
 constexpr uint32_t kScanBlock = 1024;  // elements one scan workgroup covers (256 threads, four each)
 
 // Planner counters (meta words).
@@ -70,30 +70,36 @@ __global__ __launch_bounds__(256) void k_bitonic_step(uint64_t *__restrict__ a, 
 
 // The passes with j < kSortBlock, in LDS, on each workgroup's kSortBlock
 // keys: the whole network up to k = kSortBlock when k == 0, else the passes
-// j = kSortBlock / 2 .. 1 of stage k.
+// j = kSortBlock / 2 .. 1 of stage k.  Each of the 1024 threads takes
+// kSortBlock / 2048 of a pass's kSortBlock / 2 pairs.
 __global__ __launch_bounds__(1024) void k_bitonic_block(uint64_t *__restrict__ a, uint32_t k_stage) {
+  constexpr uint32_t kPer = kSortBlock / 1024u, kPairs = kSortBlock / 2048u;
   __shared__ uint64_t s[kSortBlock];
   const uint32_t t = threadIdx.x;
   const uint32_t base = blockIdx.x * kSortBlock;
-  s[t] = a[base + t];
-  s[t + 1024u] = a[base + t + 1024u];
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) s[t + 1024u * q] = a[base + t + 1024u * q];
   __syncthreads();
   const uint32_t k_lo = k_stage ? k_stage : 2u, k_hi = k_stage ? k_stage : kSortBlock;
   for (uint32_t k = k_lo; k <= k_hi; k <<= 1) {
     for (uint32_t j = (k_stage ? kSortBlock : k) >> 1; j > 0; j >>= 1) {
-      const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));
-      const uint32_t l = i | j;
-      const bool asc = ((base + i) & k) == 0u;
-      const uint64_t x = s[i], y = s[l];
-      if ((x > y) == asc) {
-        s[i] = y;
-        s[l] = x;
+#pragma unroll
+      for (uint32_t q = 0; q < kPairs; ++q) {
+        const uint32_t pr = t + 1024u * q;  // pair number in the block
+        const uint32_t i = ((pr & ~(j - 1u)) << 1) | (pr & (j - 1u));
+        const uint32_t l = i | j;
+        const bool asc = ((base + i) & k) == 0u;
+        const uint64_t x = s[i], y = s[l];
+        if ((x > y) == asc) {
+          s[i] = y;
+          s[l] = x;
+        }
       }
       __syncthreads();
     }
   }
-  a[base + t] = s[t];
-  a[base + t + 1024u] = s[t + 1024u];
+#pragma unroll
+  for (uint32_t q = 0; q < kPer; ++q) a[base + t + 1024u * q] = s[t + 1024u * q];
 }
 
 // Sorts a[0, n) ascending; n is a power of two >= kSortBlock.
@@ -287,6 +293,11 @@ __global__ __launch_bounds__(256) void k_fill_ones(uint64_t *__restrict__ a, uin
   if (i < n) a[i] = ~0ull;
 }
 
+__global__ __launch_bounds__(256) void k_fill_zero(uint32_t *__restrict__ a, uint32_t n) {
+  const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+  if (i < n) a[i] = 0u;
+}
+
 // Queue items: tile k of split group g at slot tiles[g] + k, every other group
 // g at tile_cap + g (unused places keep all ones and sort last).
 __global__ __launch_bounds__(256) void k_plan_items(const xg_request *__restrict__ reqs, uint32_t num_reqs,
@@ -444,12 +455,17 @@ hipError_t launch_plan(const PlanPtrs &p, const PlanLayout &l, const xg_request 
   if (e == hipSuccess) e = scan<uint32_t>(p.heads, num_reqs, u32sums, stream);
   if (e == hipSuccess) e = scan<uint64_t>(p.costs, num_reqs, p.sums, stream);
   if (e == hipSuccess) e = launch(k_plan_groups, grid(num_reqs), b256, 0, stream, num_reqs, p.heads, p.meta, p.hp);
-  if (e == hipSuccess)
-    e = launch(k_plan_want, grid(num_reqs), b256, 0, stream, reqs, num_reqs, p.keys, p.heads, p.hp, tile_words,
-               p.tiles);
-  if (e == hipSuccess) e = scan<uint32_t>(p.tiles, num_reqs, u32sums, stream);
-  if (e == hipSuccess)
-    e = launch(k_plan_budget, grid(num_reqs + 1), b256, 0, stream, num_reqs, p.tiles, tile_cap, p.meta);
+  if (tile_cap) {
+    if (e == hipSuccess)
+      e = launch(k_plan_want, grid(num_reqs), b256, 0, stream, reqs, num_reqs, p.keys, p.heads, p.hp, tile_words,
+                 p.tiles);
+    if (e == hipSuccess) e = scan<uint32_t>(p.tiles, num_reqs, u32sums, stream);
+    if (e == hipSuccess)
+      e = launch(k_plan_budget, grid(num_reqs + 1), b256, 0, stream, num_reqs, p.tiles, tile_cap, p.meta);
+  } else if (e == hipSuccess) {
+    // no tiles: every group's tile prefix sum is 0
+    e = launch(k_fill_zero, grid(num_reqs + 1), b256, 0, stream, p.tiles, num_reqs + 1);
+  }
   if (e == hipSuccess) e = launch(k_fill_ones, grid(item_n), b256, 0, stream, p.items, item_n);
   if (e == hipSuccess)
     e = launch(k_plan_items, grid(num_reqs), b256, 0, stream, reqs, num_reqs, p.keys, p.heads, p.costs, p.hp,
