@@ -1,4 +1,5 @@
-"""Shared helpers of the GPU parity tests (comparison metrics only)."""
+"""Shared helpers of the GPU parity tests: comparison metrics, and the
+word-by-word check of a ragged batch output against the oracle."""
 import numpy as np
 import pytest
 
@@ -60,3 +61,29 @@ def huge_skip_digests() -> dict:
 def ring_digest(ring: np.ndarray) -> str:
     import hashlib
     return hashlib.sha256(np.ascontiguousarray(ring).tobytes()).hexdigest()
+
+
+def check_ragged_every_word(out, lengths, off, seed, params=None, window_words=1 << 28, chunk=16):
+    """Every word of every stream of a ragged CSR output against the oracle:
+    the output comes back in windows of consecutive streams (one copy each);
+    inside a window the streams are taken in order of length, `chunk` at a
+    time, and the oracle runs those streams in parallel up to the longest."""
+    from oracle import oracle as O
+    S = len(lengths)
+    ref_all = O.OracleStreams(seed, S, params=params or O.PAPER)
+    k0, checked = 0, 0
+    while k0 < S:
+        k1 = k0 + 1
+        while k1 < S and int(off[k1 + 1] - off[k0]) <= window_words:
+            k1 += 1
+        host = out[int(off[k0]):int(off[k1])].cpu().numpy().view(np.uint32)
+        order = k0 + np.argsort(lengths[k0:k1], kind="stable")
+        for c in range(0, len(order), chunk):
+            sel = order[c:c + chunk]
+            want = ref_all.subset(sel).u32(int(lengths[sel].max()))
+            for j, i in enumerate(sel):
+                n, a = int(lengths[i]), int(off[i] - off[k0])
+                assert np.array_equal(host[a:a + n], want[j, :n]), i
+                checked += n
+        k0 = k1
+    assert checked == int(off[-1])

@@ -264,7 +264,7 @@ def _check_plan(reqs, rows, groups, num_streams, tile_words=0):
 
 
 def test_device_plan_groups_in_table_order_largest_first():
-    """More requests than one LDS sort block (8192), repeated streams, one
+    """More requests than one LDS sort block (2048), repeated streams, one
     stream holding 3000 requests: the planned table, read back, groups every
     stream's requests in table order and serves the costliest items first;
     the outputs and end states equal the oracle's."""

@@ -17,7 +17,7 @@ import os
 import numpy as np
 import pytest
 
-from gpu_helpers import needs_gpu, ulp32_error
+from gpu_helpers import check_ragged_every_word, needs_gpu, ulp32_error
 from oracle import oracle as O
 
 pytestmark = [pytest.mark.gpu, needs_gpu]
@@ -82,31 +82,6 @@ def test_bulk_stream_major_every_stream():
         assert (f[k0:k0 + step] == ref.f32(N)).all(), k0
 
 
-def _check_ragged_every_word(out, lengths, off, seed, window_words=1 << 28, chunk=16):
-    """Every word of every stream of a ragged CSR output against the oracle:
-    the output comes back in windows of consecutive streams (one copy each);
-    inside a window the streams are taken in order of length, `chunk` at a
-    time, and the oracle runs those streams in parallel up to the longest."""
-    S = len(lengths)
-    ref_all = O.OracleStreams(seed, S)
-    k0, checked = 0, 0
-    while k0 < S:
-        k1 = k0 + 1
-        while k1 < S and int(off[k1 + 1] - off[k0]) <= window_words:
-            k1 += 1
-        host = as_u32(out[int(off[k0]):int(off[k1])])
-        order = k0 + np.argsort(lengths[k0:k1], kind="stable")
-        for c in range(0, len(order), chunk):
-            sel = order[c:c + chunk]
-            want = ref_all.subset(sel).u32(int(lengths[sel].max()))
-            for j, i in enumerate(sel):
-                n, a = int(lengths[i]), int(off[i] - off[k0])
-                assert np.array_equal(host[a:a + n], want[j, :n]), i
-                checked += n
-        k0 = k1
-    assert checked == int(off[-1])
-
-
 def test_ragged_batch_full_size_graph():
     """The ragged workload (65 536 streams, 9.95 x 10^9 uint32 words) through
     the one-call batch with the autotuned shape, captured in a HIP graph, as
@@ -128,7 +103,7 @@ def test_ragged_batch_full_size_graph():
     assert b.error_flag() == 0
     _, _, pos = gs.host_state()
     assert (pos == lengths).all()
-    _check_ragged_every_word(b.out, lengths, off, W.SEED)
+    check_ragged_every_word(b.out, lengths, off, W.SEED)
     # End states of 512 streams: each depends on every word the stream
     # generated.  The oracle reaches them by its own polynomial jump
     # (z^n mod P on the x-part, n omega on the Weyl word).
