@@ -17,7 +17,8 @@
  *
  * Conventions shared by every entry point:
  *   - Pointers named d_* are device pointers owned by the caller.  The
- *     library never allocates, frees or synchronises device memory; each
+ *     library never allocates or frees device memory (apart from the static
+ *     array of xg_generate_batch_static, reserved when the code loads); each
  *     generating call only enqueues kernels on `stream` (a hipStream_t passed
  *     as void*; NULL is the null stream) and returns.
  *   - Invalid arguments are rejected synchronously with a negative status;
@@ -29,10 +30,13 @@
  *   - All sizes count elements (4-byte words), not bytes, unless named *_bytes.
  *   - No C++ exception crosses this interface.
  *   - Host threads: calls on different handles may come from different host
- *     threads.  A handle's launch shape is read at each launch, so
- *     xg_set_plain_tune must not race with launches on the same handle.  The
- *     jump polynomials' modulus is built once per member and process,
- *     thread-safely.  A request server is driven by one host thread.
+ *     threads.  A handle's launch shape and batch scratch are read at each
+ *     launch, so xg_set_plain_tune and xg_set_batch_scratch must not race with
+ *     launches on the same handle.  A request server is driven by one host
+ *     thread.
+ *   - Process-wide state: the jump polynomials' modulus (built once per member
+ *     and process, thread-safely), the tuning cache (guarded by a lock), and
+ *     xg_generate_batch_static's device array (one per GPU).
  *
  * Stream state (device memory, XG_STATE_WORDS 32-bit words per stream, 528 B):
  *   words [0, 128)   ring[t] = x_{pos-128+t}, the last 128 words of the x-part
