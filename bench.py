@@ -33,6 +33,7 @@ N = 1 << 20
 SEED = 42
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_major_u32.json")
+DEFAULT_THROUGHPUT_SHAPE = (4, 1, 2, 1)  # waves_per_block, unroll, blocks_per_cu, store_words
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_fused_moments.json")
 # VALU issue capacity: 256 CUs x 4 SIMDs at 2.4 GHz, each SIMD issuing one
 # wave64 instruction per 4 cycles for 32-bit integer and conversion work (16
@@ -211,7 +212,8 @@ def extra_ragged_batch(torch, dev, shape=None, per_stream=True):
         arch, cus = xg.xg_tune_identity(gs.ctx)
         xg.xg_tune_cache_put(arch, cus, xg.XG_FAMILY_R128_W32, RAGGED_KEY, best)
     tune_s = time.perf_counter() - t0
-    default_ms = [r[4] for r in recs if r[:4] == (4, 8, 8, 4)]
+    # the library's default for this many queue items (8 or more per compute unit)
+    default_ms = [r[4] for r in recs if r[:4] == DEFAULT_THROUGHPUT_SHAPE]
     batch_ms = _graph_ms(torch, b.capture_graph(tune_key=RAGGED_KEY))
     err = b.error_flag()
     out = b.out
@@ -233,6 +235,7 @@ def extra_ragged_batch(torch, dev, shape=None, per_stream=True):
         "device_planning_ms": batch_ms - kernel_ms,
         "autotuned_shape": {"waves_per_block": best[0], "unroll": best[1], "blocks_per_cu": best[2],
                             "store_words": best[3]},
+        "default_shape": list(DEFAULT_THROUGHPUT_SHAPE),
         "default_shape_ms": default_ms[0] if default_ms else None,
         "autotune_s": tune_s,
         "autotune_candidates": len(recs),

@@ -158,7 +158,11 @@ xg_status xg_attach_family(xg_ctx **out, uint32_t family, void *d_state, size_t 
 uint32_t xg_family(const xg_ctx *ctx);
 
 /* Launch shape of a kernel.  Any shape gives the same output bits;
- * xg_autotune_batch picks the fastest for a batch. */
+ * xg_autotune_batch picks the fastest for a batch.  A batch launch given no
+ * shape takes a default by its number of queue items (groups; for
+ * xg_generate_batch and xg_generate_batch_static, requests): {4, 1, 2, 1}
+ * with at least 8 per compute unit, where HBM writes bound the launch, else
+ * {4, 8, 8, 1}, where each wavefront's own rate does. */
 typedef struct {
     uint32_t waves_per_block;  /* streams served at once by one workgroup: 1, 2, 4, 8, 16 */
     uint32_t unroll;           /* 64-word chunks per thread per loop trip: 1, 2, 4, 8
@@ -373,7 +377,7 @@ xg_status xg_set_batch_scratch(xg_ctx *ctx, void *d_scratch, size_t scratch_byte
  * The launch shape is the tuning cache's entry for (this device's
  * architecture, its compute units, the handle's family, tune_key), written
  * by xg_autotune_batch or loaded with xg_tune_cache_load; tune_key NULL or
- * absent from the cache selects a default shape.  Only kernels are
+ * absent from the cache selects the default shape (xg_tune).  Only kernels are
  * enqueued, so the call can be captured in a HIP graph and replayed (each
  * replay serves the table again from the streams' current positions).
  *   d_out   output buffer; every request's [out_offset, out_offset + n) must
@@ -450,7 +454,8 @@ xg_status xg_plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t nu
  *                     requests, num_groups + 1 offsets)
  *   num_groups        groups in the table
  *   d_out             output buffer of out_elems elements
- *   tune              launch shape (NULL: a default shape)
+ *   tune              launch shape (NULL: the default shape for num_groups
+ *                     groups, xg_tune)
  *   d_work            xg_batch_workspace_bytes() bytes of device memory
  * A request or group that fails the device-side bounds check (stream, dtype,
  * output range, group offsets) is skipped and sets the error word
@@ -547,7 +552,8 @@ typedef struct {
     uint32_t num_lanes;   /* HIP streams, each with at most one batch in flight: 1 .. 8 */
     uint32_t max_batch;   /* table entries per batch (requests and segments): 1 .. 65536 */
     xg_tune tune;         /* batch launch shape; all zero: the tuning cache's entry for
-                             tune_key if there is one, else the default */
+                             tune_key if there is one, else each batch's default
+                             (xg_tune) */
     uint64_t segment_words; /* 0, or L (a multiple of 64, 2^12 .. 2^30): a request of more
                                than L words is served as up to 256 segments of L words run
                                by separate wavefronts, segment k starting from the request's
@@ -623,7 +629,7 @@ uint64_t xg_server_outstanding(const xg_server *srv);
 
 xg_status xg_server_get_stats(const xg_server *srv, xg_server_stats *out);
 
-/* The launch shape the server's batches use (all zero: the default shape).
+/* The launch shape the server's batches use (all zero: each batch's default).
  * Errors: XG_EINVAL (NULL). */
 xg_status xg_server_get_tune(const xg_server *srv, xg_tune *out);
 

@@ -410,7 +410,7 @@ xg_status xg_generate_batch_planned(xg_ctx *ctx, const xg_request *d_reqs, uint3
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_groups) % 4 ||
       reinterpret_cast<uintptr_t>(d_out) % out_align || reinterpret_cast<uintptr_t>(d_work) % 4)
     return XG_EALIGN;
-  xg::Shape shape = xg::kDefaultBatch;
+  xg::Shape shape = xg::default_batch_shape(num_groups, ctx->num_cus);
   if (tune && !tune_to_shape(tune, tune->blocks_per_cu, &shape)) return XG_EINVAL;
   xg_status st = check_ctx_device(ctx);
   if (st != XG_OK) return st;
@@ -485,7 +485,7 @@ xg_status xg_generate_batch(xg_ctx *ctx, const xg_request *d_reqs, uint32_t num_
   const uintptr_t out_align = ctx->family == XG_FAMILY_R64_W64 ? 8 : 4;
   if (reinterpret_cast<uintptr_t>(d_reqs) % 8 || reinterpret_cast<uintptr_t>(d_out) % out_align) return XG_EALIGN;
   xg::Shape shape;
-  xg_status st = xg::batch_shape(ctx, tune_key, &shape);
+  xg_status st = xg::batch_shape(ctx, tune_key, num_reqs, &shape);
   if (st != XG_OK) return st;
   st = check_ctx_device(ctx);
   if (st != XG_OK) return st;
@@ -638,8 +638,8 @@ const char *xg_strerror(xg_status status) {
 
 namespace xg {
 
-xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, Shape *shape) {
-  *shape = kDefaultBatch;
+xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, uint64_t items, Shape *shape) {
+  *shape = default_batch_shape(items, ctx->num_cus);
   if (!tune_key) return XG_OK;
   xg_tune t;
   const xg_status st = xg_tune_cache_get(ctx->arch, (uint32_t)ctx->num_cus, ctx->family, tune_key, &t, nullptr);

@@ -31,7 +31,17 @@ constexpr Shape kDefaultPlain{0, 0, 1, 4};  // waves_per_block and unroll chosen
 // units: one stream per wavefront, and at least as many blocks as compute
 // units, so that the wavefronts spread one per SIMD before any SIMD gets two.
 uint32_t auto_waves_per_block(uint64_t count, int num_cus);
-constexpr Shape kDefaultBatch{4, 8, 8, 4};
+// Default persistent-batch shapes, chosen by the number of queue items.  With
+// at least eight items per compute unit the batch is bound by HBM writes: one
+// chunk per trip (a store after every recurrence step) and eight wavefronts
+// per compute unit write fastest.  With fewer items each wavefront's own rate
+// decides, and eight chunks per trip serve a group fastest.  Neither uses the
+// wide stores: staging through LDS slowed the batch at every item count.
+constexpr Shape kBatchThroughput{4, 1, 2, 1};
+constexpr Shape kBatchLatency{4, 8, 8, 1};
+inline Shape default_batch_shape(uint64_t items, int num_cus) {
+  return items >= 8u * (uint64_t)(num_cus > 0 ? num_cus : 1) ? kBatchThroughput : kBatchLatency;
+}
 
 bool shape_valid(const Shape &s);
 
@@ -119,8 +129,9 @@ namespace xg {
 
 // The one-call batch, shared by its entry points (xg_api.cpp).
 // The launch shape for tune_key: the tuning cache's entry for ctx's device
-// and family, else the default (XG_EINVAL for a malformed key).
-xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, Shape *shape);
+// and family, else the default for `items` queue items (XG_EINVAL for a
+// malformed key).
+xg_status batch_shape(const xg_ctx *ctx, const char *tune_key, uint64_t items, Shape *shape);
 // Plans num_reqs requests (device memory, table order) into the scratch at
 // base, with tiles of tile_words words in up to max_tiles slots (0: none).
 hipError_t plan_on_device(const xg_ctx *ctx, void *base, const PlanLayout &layout, const xg_request *d_reqs,

@@ -243,7 +243,7 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
       hipMemcpyAsync(l.d_groups, l.h_groups, ((size_t)num_groups + 1) * sizeof(uint32_t),
                      hipMemcpyHostToDevice, l.stream) != hipSuccess)
     return XG_EHIP;
-  xg::Shape shape = xg::kDefaultBatch;
+  xg::Shape shape = xg::default_batch_shape(num_groups, s->ctx->num_cus);
   if (!s->default_tune)
     shape = xg::Shape{s->tune.waves_per_block, s->tune.unroll, s->tune.blocks_per_cu,
                       s->tune.store_words ? s->tune.store_words : (s->tune.unroll >= 4 ? 4u : 1u)};

@@ -72,7 +72,7 @@ xg_status xg_generate_batch_static(xg_ctx *ctx, const xg_request *d_reqs, uint32
       reinterpret_cast<uintptr_t>(d_error) % 4)
     return XG_EALIGN;
   xg::Shape shape;
-  xg_status st = xg::batch_shape(ctx, tune_key, &shape);
+  xg_status st = xg::batch_shape(ctx, tune_key, num_reqs, &shape);
   if (st != XG_OK) return st;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return XG_EHIP;
