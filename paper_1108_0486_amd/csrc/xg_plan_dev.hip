@@ -382,6 +382,200 @@ __global__ __launch_bounds__(256) void k_plan_emit(const xg_request *__restrict_
   }
 }
 
+// ---- small tables: the whole plan in one workgroup ---------------------------
+
+// Table entries plus tile slots that one workgroup (one element per thread)
+// plans in LDS with a single launch instead of the multi-kernel sequence
+// above; the plan is the same.
+constexpr uint32_t kSmallPlan = 1024;
+
+// Exclusive prefix sum over the workgroup's kSmallPlan values (one per
+// thread); *total gets their sum.  wsum holds 16 values of T.
+template <typename T>
+__device__ __forceinline__ T wg_exclusive(T v, T *wsum, T *total) {
+  const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
+  T x = v;
+#pragma unroll
+  for (uint32_t d = 1; d < 64u; d <<= 1) {
+    const T y = __shfl_up(x, d);
+    if (lane >= d) x += y;
+  }
+  if (lane == 63u) wsum[w] = x;
+  __syncthreads();
+  if (w == 0) {
+    T s = lane < 16u ? wsum[lane] : T(0);
+#pragma unroll
+    for (uint32_t d = 1; d < 16u; d <<= 1) {
+      const T y = __shfl_up(s, d);
+      if (lane >= d) s += y;
+    }
+    if (lane < 16u) wsum[lane] = s;
+  }
+  __syncthreads();
+  const T before = w ? wsum[w - 1] : T(0);
+  *total = wsum[15];
+  __syncthreads();  // wsum is reused by the next scan
+  return before + x - v;
+}
+
+// Ascending bitonic sort of kSmallPlan keys in LDS (half the threads take a
+// pair in each pass).
+__device__ __forceinline__ void wg_sort(uint64_t *s) {
+  const uint32_t t = threadIdx.x;
+  for (uint32_t k = 2; k <= kSmallPlan; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (t < kSmallPlan / 2) {
+        const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));
+        const uint32_t l = i | j;
+        const bool asc = (i & k) == 0u;
+        const uint64_t x = s[i], y = s[l];
+        if ((x > y) == asc) {
+          s[i] = y;
+          s[l] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// The planner for num_reqs + tile_cap <= kSmallPlan: the steps of the kernels
+// above (keys, sort, group heads and cost sums, tiles and their budget, queue
+// items, their sort, entry counts, table), each on one element per thread,
+// with the arrays in LDS.  Writes offs[0 .. num_reqs + tile_cap], the table
+// and work[0 .. 63] (counts in work[2], work[3], the error word in work[1]).
+__global__ __launch_bounds__(kSmallPlan) void k_plan_small(const xg_request *__restrict__ reqs, uint32_t num_reqs,
+                                                           uint64_t num_streams, uint64_t tile_words,
+                                                           uint32_t tile_cap, uint32_t *__restrict__ work,
+                                                           uint32_t *__restrict__ offs_out,
+                                                           xg_request *__restrict__ table) {
+  __shared__ uint64_t keys[kSmallPlan];       // sort keys, then queue item keys
+  __shared__ uint64_t costs[kSmallPlan + 1];  // cost prefix sums over sorted requests
+  __shared__ uint32_t idx[kSmallPlan];        // request index at each sorted position
+  __shared__ uint32_t heads[kSmallPlan + 1];  // group prefix sums, then entry offsets of items
+  __shared__ uint32_t hp[kSmallPlan + 1];     // first sorted position of each group
+  __shared__ uint32_t tiles[kSmallPlan + 1];  // tile prefix sums per group
+  __shared__ uint64_t wsum[16];
+  __shared__ uint32_t cnt[4];                 // valid requests, error, tile slots used, items
+  const uint32_t t = threadIdx.x, n = num_reqs;
+  uint32_t *wsum32 = reinterpret_cast<uint32_t *>(wsum);
+  if (t >= 4u && t < 64u) work[t] = 0u;
+  if (t < 4u) cnt[t] = 0u;
+  __syncthreads();
+
+  uint64_t key = ~0ull;
+  if (t < n) {
+    const xg_request q = reqs[t];
+    const bool valid = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u;
+    key = ((valid ? q.stream : 0xFFFFFFFFull) << 32) | t;
+    if (valid) atomicAdd(&cnt[0], 1u);
+    else atomicOr(&cnt[1], 1u);
+  }
+  keys[t] = key;
+  __syncthreads();
+  wg_sort(keys);
+
+  const uint32_t valid_n = cnt[0];
+  uint32_t head = 0;
+  uint64_t cost = 0;
+  const uint64_t k_t = keys[t];
+  idx[t] = (uint32_t)k_t;
+  if (t < valid_n) {
+    head = t == 0 || (k_t >> 32) != (keys[t - 1] >> 32);
+    const xg_request q = reqs[(uint32_t)k_t];
+    cost = cost_of(q.n, q.dtype);
+  }
+  uint32_t num_groups;
+  const uint32_t hx = wg_exclusive<uint32_t>(head, wsum32, &num_groups);
+  heads[t] = hx;
+  if (t == kSmallPlan - 1u) heads[kSmallPlan] = num_groups;
+  uint64_t cost_total;
+  const uint64_t cx = wg_exclusive<uint64_t>(cost, wsum, &cost_total);
+  costs[t] = cx;
+  if (t == kSmallPlan - 1u) costs[kSmallPlan] = cost_total;
+  __syncthreads();
+  if (t < n && head) hp[hx] = t;
+  if (t == 0) hp[num_groups] = valid_n;
+  __syncthreads();
+
+  uint32_t want = 0;
+  if (tile_cap && t < num_groups && hp[t + 1] - hp[t] == 1u) {
+    const xg_request q = reqs[idx[hp[t]]];
+    const uint64_t parts = (words_of(q.n, q.dtype) + tile_words - 1) / tile_words;
+    if (parts > 1 && parts <= kMaxSegments) want = (uint32_t)parts;
+  }
+  uint32_t tile_total;
+  const uint32_t tx = wg_exclusive<uint32_t>(want, wsum32, &tile_total);
+  tiles[t] = tx;
+  if (t == kSmallPlan - 1u) tiles[kSmallPlan] = tile_total;
+  if (tx && tx <= tile_cap) atomicMax(&cnt[2], tx);
+  if (t == 0 && tile_total && tile_total <= tile_cap) atomicMax(&cnt[2], tile_total);
+  keys[t] = ~0ull;  // the sorted keys are done with: idx holds the request indices
+  __syncthreads();
+
+  const uint32_t used = cnt[2];
+  if (t < num_groups) {
+    if (group_split(tiles, t, used)) {
+      const xg_request q = reqs[idx[hp[t]]];
+      const uint32_t parts = tiles[t + 1] - tiles[t];
+      for (uint32_t k = 0; k < parts; ++k) {
+        const uint64_t first = k * tile_words;
+        const uint64_t nk = q.n - first < tile_words ? q.n - first : tile_words;
+        keys[tiles[t] + k] = item_key(cost_of(nk, q.dtype), t, k);
+      }
+      atomicAdd(&cnt[3], parts);
+    } else {
+      keys[tile_cap + t] = item_key(costs[hp[t + 1]] - costs[hp[t]], t, 0);
+      atomicAdd(&cnt[3], 1u);
+    }
+  }
+  __syncthreads();
+  wg_sort(keys);
+
+  const uint32_t num_items = cnt[3];
+  uint32_t c = 0;
+  if (t < num_items) {
+    const uint32_t g = (uint32_t)keys[t] >> 8;
+    c = group_split(tiles, g, used) ? 1u : hp[g + 1] - hp[g];
+  }
+  uint32_t entries;
+  const uint32_t ox = wg_exclusive<uint32_t>(c, wsum32, &entries);
+  heads[t] = ox;  // heads now holds the items' table offsets
+  if (t == kSmallPlan - 1u) heads[kSmallPlan] = entries;
+  const uint32_t items = n + tile_cap;
+  if (t <= items) offs_out[t] = ox;
+  if (t == kSmallPlan - 1u && items == kSmallPlan) offs_out[kSmallPlan] = entries;
+  __syncthreads();
+
+  if (t < entries) {
+    uint32_t lo = 0, hi = num_items;  // heads[lo] <= t < heads[hi]
+    while (hi - lo > 1u) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (heads[mid] <= t) lo = mid;
+      else hi = mid;
+    }
+    const uint64_t it = keys[lo];
+    const uint32_t g = (uint32_t)it >> 8, k = (uint32_t)it & 0xFFu;
+    if (group_split(tiles, g, used)) {
+      xg_request q = reqs[idx[hp[g]]];
+      const uint64_t first = k * tile_words;
+      const uint32_t parts = tiles[g + 1] - tiles[g], slot = tiles[g] + k;
+      q.n = q.n - first < tile_words ? q.n - first : tile_words;
+      q.out_offset += first;
+      q.flags = kReqSegment | (k << 8) | (slot << 16) | (k + 1 == parts ? kReqLast : 0u);
+      table[t] = q;
+    } else {
+      table[t] = reqs[idx[hp[g] + (t - heads[lo])]];
+    }
+  }
+  if (t == 0) {
+    work[0] = 0u;
+    work[1] = cnt[1];
+    work[2] = num_items;
+    work[3] = entries;
+  }
+}
+
 uint32_t pow2_at_least(uint32_t v) {
   uint32_t p = 1;
   while (p < v) p <<= 1;
@@ -442,6 +636,11 @@ PlanPtrs plan_ptrs(void *base, const PlanLayout &l) {
 hipError_t launch_plan(const PlanPtrs &p, const PlanLayout &l, const xg_request *reqs, uint32_t num_reqs,
                        uint64_t num_streams, uint64_t tile_words, uint32_t max_tiles, hipStream_t stream) {
   const uint32_t tile_cap = tile_words ? max_tiles : 0u;
+  if ((uint64_t)num_reqs + tile_cap <= kSmallPlan) {
+    if ((uint64_t)num_reqs + tile_cap + 1 > (uint64_t)(l.table - l.offs) / 4) return hipErrorInvalidValue;
+    return launch(k_plan_small, dim3(1), dim3(kSmallPlan), 0, stream, reqs, num_reqs, num_streams, tile_words,
+                  tile_cap, p.work, p.offs, p.table);
+  }
   const uint32_t key_n = pow2_at_least(num_reqs > kSortBlock ? num_reqs : kSortBlock);
   const uint32_t items = num_reqs + tile_cap;
   const uint32_t item_n = pow2_at_least(items > kSortBlock ? items : kSortBlock);

@@ -360,6 +360,73 @@ def test_device_batch_tile_budget():
     _check_state(gs, ref)
 
 
+def _plan_pair(reqs, total, S, seed, small_kw, grid_kw):
+    """The same table through two handles: one whose table fits the
+    one-workgroup planner (requests plus tile slots at most 1024), one whose
+    tile capacity sends it through the multi-kernel planner."""
+    out = []
+    for kw in (small_kw, grid_kw):
+        gs = XorgensStreams(S, seed=seed)
+        # words no request writes (dropped and empty requests) keep this fill
+        buf = torch.full((max(1, total),), -1, dtype=torch.int32, device="cuda")
+        b = Batch(gs, reqs, total, out=buf, **kw)
+        b.run()
+        torch.cuda.synchronize()
+        out.append((b.served_plan(), b.error_flag(), b.out.cpu().numpy(), gs.host_state()))
+    return out
+
+
+@pytest.mark.parametrize("num_reqs", [0, 1, 37, 500, 1023, 1024, 1025])
+def test_small_table_planner_equals_multi_kernel_planner(num_reqs):
+    """Tables of up to 1024 requests are planned by one workgroup in LDS; the
+    same table sent through the multi-kernel planner (a tile capacity that
+    no request uses puts it there) gives the same table, item offsets, error
+    word, outputs and end states, with repeated streams, all three dtypes,
+    empty requests and requests that fail the checks."""
+    rng = np.random.default_rng(1000 + num_reqs)
+    S = 97
+    reqs, off = [], 0
+    for i in range(num_reqs):
+        s = 5 if i % 7 == 0 else int(rng.integers(0, S + 3))   # a few streams past S: dropped
+        n = int(rng.integers(0, 900))
+        dt = int(rng.integers(0, 3)) if i % 50 != 49 else 3    # dtype 3: dropped
+        reqs.append((s, n, off, dt))
+        off += n
+    (plan_a, err_a, out_a, st_a), (plan_b, err_b, out_b, st_b) = _plan_pair(
+        reqs, off, S, 41, {}, {"tile_words": 1 << 30, "max_tiles": 2048})
+    assert plan_a == plan_b
+    assert err_a == err_b == int(any(r[0] >= S or r[3] > 2 for r in reqs))
+    assert (out_a == out_b).all()
+    assert all((x == y).all() for x, y in zip(st_a, st_b))
+    rows, groups = plan_a
+    _check_plan([r for r in reqs if r[3] <= 2], rows, groups, S)
+
+
+def test_small_table_planner_tiles_equal_multi_kernel_planner():
+    """Tiles in the one-workgroup planner (19 requests, 1000 tile slots) and in
+    the multi-kernel planner (2048 slots): the same plan, outputs and states,
+    and the oracle's values."""
+    L = 4096
+    rng = np.random.default_rng(12)
+    S = 12
+    reqs, total = _tile_requests(rng, S, L)
+    assert len(reqs) + 1000 <= 1024
+    (plan_a, err_a, out_a, st_a), (plan_b, err_b, out_b, st_b) = _plan_pair(
+        reqs, total, S + 1, 6, {"tile_words": L, "max_tiles": 1000}, {"tile_words": L, "max_tiles": 2048})
+    assert err_a == err_b == 0
+    assert plan_a == plan_b
+    rows, groups = plan_a
+    _check_plan(reqs, rows, groups, S + 1, tile_words=L)
+    assert sum(1 for r in rows if r[4]) > 10
+    assert (out_a == out_b).all()
+    assert all((x == y).all() for x, y in zip(st_a, st_b))
+    ref = O.OracleStreams(6, S + 1)
+    want = _oracle_serve(ref, reqs)
+    _check_outputs(out_a, reqs, want)
+    ring, weyl, pos = st_a
+    assert (ring == ref.ring).all() and (weyl == ref.weyl).all() and (pos == ref.pos).all()
+
+
 def test_device_batch_tiles_graph_replay():
     """The whole call with tiles (planning, start states by jump, batch)
     captured once and replayed three times, with eager work in between: every
