@@ -158,7 +158,7 @@ xg_status plain(xg_ctx *ctx, xg::Kind kind, uint64_t first, uint64_t count, uint
   xg_status st = check_range(ctx, first, count, n, out, per_stream);
   if (st != XG_OK || n == 0) return st;
   const hipError_t e = xg::launch_generate(kind, plain_shape(ctx, count, kind, false), ctx->d_state, first, count,
-                                           n, out, static_cast<hipStream_t>(stream));
+                                           n, out, ctx->num_cus, static_cast<hipStream_t>(stream));
   return e == hipSuccess ? XG_OK : XG_EHIP;
 }
 

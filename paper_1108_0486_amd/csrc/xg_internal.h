@@ -47,8 +47,10 @@ bool shape_valid(const Shape &s);
 
 hipError_t launch_init(uint32_t *state, uint64_t num_streams, uint64_t seed, hipStream_t stream);
 
+// num_cus: normals and moments with fewer than two wavefronts per SIMD take
+// the pair gather that needs no LDS.
 hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint64_t first,
-                           uint64_t count, uint64_t n, void *out, hipStream_t stream);
+                           uint64_t count, uint64_t n, void *out, int num_cus, hipStream_t stream);
 
 // Bulk-fill layout of xg_fill_u32 / xg_fill_f32 (kind kU32 or kF32).
 hipError_t launch_fill(Kind kind, const Shape &shape, uint32_t *state, uint64_t first, uint64_t count,

@@ -320,25 +320,52 @@ __device__ __forceinline__ void serve_words_fill(uint32_t *__restrict__ st, uint
 // ---------------------------------------------------------------------------
 // normals: Box-Muller on consecutive output pairs of the call.
 // ---------------------------------------------------------------------------
-// Lane j gathers words 2j and 2j + 1 of the 128-word block lo | hi.
-__device__ __forceinline__ void gather_pair(uint32_t lo, uint32_t hi, uint32_t lane, uint32_t &e,
-                                            uint32_t &o) {
-  const int se = (int)((2u * lane) & 63u);
-  const int so = se + 1;
-  const uint32_t e_lo = (uint32_t)__shfl((int)lo, se), e_hi = (uint32_t)__shfl((int)hi, se);
-  const uint32_t o_lo = (uint32_t)__shfl((int)lo, so), o_hi = (uint32_t)__shfl((int)hi, so);
-  const bool upper = lane >= 32u;
-  e = upper ? e_hi : e_lo;
-  o = upper ? o_hi : o_lo;
+// Two ways to give each lane one pair of the 128-word block lo | hi (lo
+// holds words 0..63, one per lane, hi words 64..127); pair_offset gives the
+// pair's first word within the block.
+//  - LDS (lane j takes words 2j and 2j + 1): four ds_bpermute reads and two
+//    selects.  The fewest VALU instructions: with two or more wavefronts per
+//    SIMD the VALU is the bound and the LDS latency hides (3 % faster than DPP
+//    at four per SIMD).
+//  - DPP (an even lane j takes words j and j + 1, an odd lane j words 63 + j
+//    and 64 + j): each lane needs one word of its neighbour in the same chunk,
+//    which a quad permutation (lanes 2i and 2i + 1 swap) supplies in the VALU,
+//    two more instructions but no LDS round trip to wait for (12 % faster than
+//    LDS at one wavefront per SIMD).
+template <bool DPP>
+__device__ __forceinline__ uint32_t pair_offset(uint32_t lane) {
+  return DPP ? (lane & ~1u) + ((lane & 1u) << 6) : 2u * lane;
+}
+
+template <bool DPP>
+__device__ __forceinline__ void gather_pair(uint32_t lo, uint32_t hi, uint32_t lane, uint32_t &e, uint32_t &o) {
+  if constexpr (DPP) {
+    // Bit selects, not ternaries, so that the swaps cannot be sunk into
+    // lane-divergent branches where the neighbouring lanes are inactive.
+    constexpr int kSwapPairs = 0xB1;  // quad_perm [1, 0, 3, 2]
+    const uint32_t odd = 0u - (lane & 1u);  // all ones on odd lanes
+    const uint32_t lo_sw = (uint32_t)__builtin_amdgcn_mov_dpp((int)lo, kSwapPairs, 0xF, 0xF, false);
+    const uint32_t hi_sw = (uint32_t)__builtin_amdgcn_mov_dpp((int)hi, kSwapPairs, 0xF, 0xF, false);
+    e = dev::select_bits(hi_sw, lo, odd);
+    o = dev::select_bits(hi, lo_sw, odd);
+  } else {
+    const int se = (int)((2u * lane) & 63u);
+    const int so = se + 1;
+    const uint32_t e_lo = (uint32_t)__shfl((int)lo, se), e_hi = (uint32_t)__shfl((int)hi, se);
+    const uint32_t o_lo = (uint32_t)__shfl((int)lo, so), o_hi = (uint32_t)__shfl((int)hi, so);
+    const bool upper = lane >= 32u;
+    e = upper ? e_hi : e_lo;
+    o = upper ? o_hi : o_lo;
+  }
 }
 
 // Stores (or accumulates) normals idx and idx + 1 of the call.  CHECKED
-// compares them with n (blocks wholly inside n skip that).  `pair_aligned`
-// (wave-uniform) says out is 8-byte aligned, so a pair is one 8-byte store.
+// compares them with n (blocks wholly inside n skip that).  The two adjacent
+// 4-byte stores of a full pair become one 8-byte store, which needs only
+// 4-byte alignment.
 template <bool MOMENTS, bool CHECKED>
 __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t idx, uint64_t n,
-                                             float *__restrict__ out, bool pair_aligned,
-                                             Moments &m) {
+                                             float *__restrict__ out, Moments &m) {
   float z0, z1;
   box_muller(e, o, z0, z1);
   const bool has0 = !CHECKED || idx < n, has1 = !CHECKED || idx + 1 < n;
@@ -346,19 +373,15 @@ __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t id
     // Into the open group (the caller closes groups); has1 implies has0.
     if (has0) group_add(m, z0, has1 ? z1 : 0.0f);
   } else {
-    if (pair_aligned && has1) {
-      const f32x2 pair = {z0, z1};
-      __builtin_nontemporal_store(pair, reinterpret_cast<f32x2 *>(out + idx));
-    } else {
-      if (has0) __builtin_nontemporal_store(z0, out + idx);
-      if (has1) __builtin_nontemporal_store(z1, out + idx + 1);
-    }
+    if (has0) __builtin_nontemporal_store(z0, out + idx);
+    if (has1) __builtin_nontemporal_store(z1, out + idx + 1);
   }
 }
 
 // n normals of one stream; MOMENTS: reduce to (sum z, sum z^2) in sums[0..1]
-// instead of storing them.  Consumes 2 ceil(n / 2) words.
-template <bool MOMENTS, int UNROLL>
+// instead of storing them.  Consumes 2 ceil(n / 2) words.  DPP picks the
+// pair gather (above).
+template <bool MOMENTS, int UNROLL, bool DPP>
 __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64_t n, float *__restrict__ out,
                                                    float *__restrict__ sums, uint32_t *dst) {
   const uint32_t lane = lane_id();
@@ -372,8 +395,8 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
   const uint64_t nblk = words >> 7;     // 128-word blocks: 64 pairs, one per lane
   const uint32_t rw = (uint32_t)(words & 127u);
   Moments m = {0.f, 0.f, 0.f, 0.f, -0.f, -0.f};
-  const bool pair_aligned = (reinterpret_cast<uintptr_t>(out) & 7u) == 0;
   const uint64_t nsafe = n >> 7;        // blocks whose 128 normals are all below n
+  const uint32_t poff = pair_offset<DPP>(lane);
   const uint64_t nouter = nsafe / UNROLL;
   uint64_t b = 0;
   for (uint64_t it = 0; it != nouter; ++it, b += UNROLL) {
@@ -386,8 +409,8 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
       const uint32_t ob = xb + temper_weyl(wbase + wlane);
       wbase += kChunkOmega;
       uint32_t e, o;
-      gather_pair(oa, ob, lane, e, o);
-      consume_pair<MOMENTS, false>(e, o, ((b + u) << 7) + 2u * lane, n, out, pair_aligned, m);
+      gather_pair<DPP>(oa, ob, lane, e, o);
+      consume_pair<MOMENTS, false>(e, o, ((b + u) << 7) + poff, n, out, m);
       if (MOMENTS && ((u & 3) == 3 || u == UNROLL - 1)) group_close(m);
     }
   }
@@ -399,8 +422,8 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     const uint32_t ob = xb + temper_weyl(wbase + wlane);
     wbase += kChunkOmega;
     uint32_t e, o;
-    gather_pair(oa, ob, lane, e, o);
-    consume_pair<MOMENTS, false>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
+    gather_pair<DPP>(oa, ob, lane, e, o);
+    consume_pair<MOMENTS, false>(e, o, (b << 7) + poff, n, out, m);
     if (MOMENTS) group_close(m);
   }
   for (; b != nblk; ++b) {
@@ -411,8 +434,8 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     const uint32_t ob = xb + temper_weyl(wbase + wlane);
     wbase += kChunkOmega;
     uint32_t e, o;
-    gather_pair(oa, ob, lane, e, o);
-    consume_pair<MOMENTS, true>(e, o, (b << 7) + 2u * lane, n, out, pair_aligned, m);
+    gather_pair<DPP>(oa, ob, lane, e, o);
+    consume_pair<MOMENTS, true>(e, o, (b << 7) + poff, n, out, m);
     if (MOMENTS) group_close(m);
   }
   // Tail: rw (even, < 128) more words.
@@ -437,8 +460,8 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
       rem = rw - 64u;
     }
     uint32_t e, o;
-    gather_pair(oa, ob, lane, e, o);
-    if (2u * lane < rw) consume_pair<MOMENTS, true>(e, o, (nblk << 7) + 2u * lane, n, out, pair_aligned, m);
+    gather_pair<DPP>(oa, ob, lane, e, o);
+    if (poff < rw) consume_pair<MOMENTS, true>(e, o, (nblk << 7) + poff, n, out, m);
     if (MOMENTS) group_close(m);
   }
   write_state(dst, p0, c0, xl, rem, w_start + (uint32_t)words * kOmega, pos + words, lane);
@@ -459,10 +482,10 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
   }
 }
 
-template <bool MOMENTS, int UNROLL>
+template <bool MOMENTS, int UNROLL, bool DPP>
 __device__ __forceinline__ void serve_normals(uint32_t *st, uint64_t n, float *__restrict__ out,
                                               float *__restrict__ sums) {
-  serve_normals_from<MOMENTS, UNROLL>(load_state(st), n, out, sums, st);
+  serve_normals_from<MOMENTS, UNROLL, DPP>(load_state(st), n, out, sums, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +515,8 @@ __global__ __launch_bounds__(256) void k_init(uint32_t *__restrict__ state, uint
   store_weyl_pos(st, w0 + 512u * kOmega, 0ull, lane);
 }
 
-template <uint32_t KIND, int UNROLL, bool WIDE>
+// DPP (normals and moments): the pair gather without LDS.
+template <uint32_t KIND, int UNROLL, bool WIDE, bool DPP = false>
 __global__ __launch_bounds__(1024) void k_generate(uint32_t *__restrict__ state, uint64_t first,
                                                    uint64_t count, uint64_t n, void *__restrict__ out) {
   // Stream-major rows: each XCD takes a contiguous range of streams (measured
@@ -504,9 +528,9 @@ __global__ __launch_bounds__(1024) void k_generate(uint32_t *__restrict__ state,
     constexpr bool kPaced = KIND == kU32 && UNROLL == 2 && !WIDE;  // see emit_word
     serve_words<KIND, UNROLL, WIDE, kPaced>(st, n, reinterpret_cast<uint32_t *>(out) + wid * n);
   } else if constexpr (KIND == kNormal) {
-    serve_normals<false, UNROLL>(st, n, reinterpret_cast<float *>(out) + wid * n, nullptr);
+    serve_normals<false, UNROLL, DPP>(st, n, reinterpret_cast<float *>(out) + wid * n, nullptr);
   } else {
-    serve_normals<true, UNROLL>(st, n, nullptr, reinterpret_cast<float *>(out) + 2 * wid);
+    serve_normals<true, UNROLL, DPP>(st, n, nullptr, reinterpret_cast<float *>(out) + 2 * wid);
   }
 }
 
@@ -702,7 +726,7 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
       } else if (q.dtype == XG_F32) {
         serve_words_from<kF32, UNROLL, WIDE>(s0, q.n, o, dst);
       } else {
-        serve_normals_from<false, UNROLL>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
+        serve_normals_from<false, UNROLL, true>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
       }
     }
   }
@@ -710,9 +734,20 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
 
 template <uint32_t KIND>
 hipError_t launch_generate_k(const Shape &sh, dim3 grid, dim3 block, uint32_t *state, uint64_t first,
-                             uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+                             uint64_t count, uint64_t n, void *out, int num_cus, hipStream_t stream) {
   hipError_t e = hipSuccess;
   constexpr bool kWords = KIND == kU32 || KIND == kF32;
+  if constexpr (!kWords) {
+    // Normals with fewer than two wavefronts per SIMD: the DPP pair gather.
+    if (count < 8u * (uint64_t)(num_cus > 0 ? num_cus : 1)) {
+      switch (sh.unroll) {
+        case 1: return launch((k_generate<KIND, 1, false, true>), grid, block, 0, stream, state, first, count, n, out);
+        case 2: return launch((k_generate<KIND, 2, false, true>), grid, block, 0, stream, state, first, count, n, out);
+        case 4: return launch((k_generate<KIND, 4, false, true>), grid, block, 0, stream, state, first, count, n, out);
+        default: return launch((k_generate<KIND, 8, false, true>), grid, block, 0, stream, state, first, count, n, out);
+      }
+    }
+  }
   const bool wide = kWords && sh.store_words == 4;
   const size_t lds = wide ? (size_t)sh.waves_per_block * 1024u : 0u;
   if (wide) {
@@ -801,15 +836,16 @@ hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t
 }
 
 hipError_t launch_generate(Kind kind, const Shape &shape, uint32_t *state, uint64_t first,
-                           uint64_t count, uint64_t n, void *out, hipStream_t stream) {
+                           uint64_t count, uint64_t n, void *out, int num_cus, hipStream_t stream) {
   const uint64_t wpb = shape.waves_per_block;
   const dim3 grid((uint32_t)((count + wpb - 1) / wpb));
   const dim3 block((uint32_t)(wpb * kWave));
   switch (kind) {
-    case kU32: return launch_generate_k<kU32>(shape, grid, block, state, first, count, n, out, stream);
-    case kF32: return launch_generate_k<kF32>(shape, grid, block, state, first, count, n, out, stream);
-    case kNormal: return launch_generate_k<kNormal>(shape, grid, block, state, first, count, n, out, stream);
-    default: return launch_generate_k<kMoments>(shape, grid, block, state, first, count, n, out, stream);
+    case kU32: return launch_generate_k<kU32>(shape, grid, block, state, first, count, n, out, num_cus, stream);
+    case kF32: return launch_generate_k<kF32>(shape, grid, block, state, first, count, n, out, num_cus, stream);
+    case kNormal:
+      return launch_generate_k<kNormal>(shape, grid, block, state, first, count, n, out, num_cus, stream);
+    default: return launch_generate_k<kMoments>(shape, grid, block, state, first, count, n, out, num_cus, stream);
   }
 }
 
