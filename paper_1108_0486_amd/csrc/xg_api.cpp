@@ -670,7 +670,7 @@ hipError_t serve_planned(const xg_ctx *ctx, void *base, const PlanLayout &layout
     return launch_family_batch(ctx->family, shape, ctx->num_cus, reinterpret_cast<unsigned char *>(state),
                                ctx->num_streams, p.table, p.offs, max_items, d_out, UINT64_MAX, p.work, s);
   const SegmentArgs seg{p.jump, tile_words, tiles ? kMaxSegments - 1 : 0u, p.stage, tiles};
-  if (tiles) e = launch_seg_starts(state, ctx->num_streams, p.table, max_items, p.work, seg, s);
+  if (tiles) e = launch_seg_starts(state, ctx->num_streams, p.table, max_items, p.work, seg, ctx->num_cus, s);
   if (e == hipSuccess)
     e = launch_batch(shape, ctx->num_cus, state, ctx->num_streams, p.table, p.offs, max_items,
                      static_cast<uint32_t *>(d_out), UINT64_MAX, p.work, s, tiles ? &seg : nullptr);

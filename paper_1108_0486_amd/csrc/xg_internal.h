@@ -90,9 +90,11 @@ hipError_t launch_work_init(uint32_t *work, uint32_t num_groups, uint32_t num_re
 hipError_t launch_work_requeue(uint32_t *work, hipStream_t stream);
 
 // Stages the start state of every segment entry among the table's first
-// work[3] entries (max_entries bounds the grid).
+// work[3] entries: as many workgroups as the chip holds at once (at most
+// max_entries), each taking every gridDim-th entry.
 hipError_t launch_seg_starts(const uint32_t *state, uint64_t num_streams, const xg_request *reqs,
-                             uint32_t max_entries, const uint32_t *work, const SegmentArgs &seg, hipStream_t stream);
+                             uint32_t max_entries, const uint32_t *work, const SegmentArgs &seg, int num_cus,
+                             hipStream_t stream);
 
 // Serves the table described by work (groups: work[2] + 1 offsets into reqs)
 // with blocks_per_cu x CUs persistent workgroups (fewer when max_groups, an

@@ -667,20 +667,84 @@ __device__ __forceinline__ bool seg_entry_ok(const xg_request &q, uint64_t num_s
 // skipped (the batch kernel skips those too).  The batch kernel then starts
 // each segment from its slot, so no segment reads a stream state that the
 // request's last segment rewrites.
-__global__ __launch_bounds__(256) void k_seg_starts(const uint32_t *__restrict__ state, uint64_t num_streams,
-                                                    const xg_request *__restrict__ reqs,
-                                                    const uint32_t *__restrict__ work, SegmentArgs seg) {
-  const uint64_t r = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-  if (r >= work[3]) return;
-  const xg_request q = reqs[r];
-  if (!(q.flags & kReqSegment) || !seg_entry_ok(q, num_streams, seg)) return;
-  const uint32_t k = (q.flags >> 8) & 0xFFu, slot = q.flags >> 16;
-  StreamState s = load_state(state + q.stream * kStateWords);
-  if (k) {
-    const uint64_t *gk = seg.jump_table + (uint64_t)(k - 1) * 64;
-    jump_state(s, [&](int c) { return gk[c]; }, (uint64_t)k * seg.seg_words);
+// Wavefronts that share one segment's jump.  Four: at 142 VGPRs per lane
+// (three wavefronts per SIMD) three such workgroups fit on a compute unit, so
+// many segments keep the chip as busy as one wavefront per segment did, while
+// one segment's jump takes a quarter of the window sums' time.
+constexpr uint32_t kSegWaves = 4;
+constexpr uint32_t kSegBlocksPerCu = 3;
+
+__global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *__restrict__ state,
+                                                               uint64_t num_streams,
+                                                               const xg_request *__restrict__ reqs,
+                                                               const uint32_t *__restrict__ work,
+                                                               SegmentArgs seg) {
+  // One workgroup per segment entry (grid-stride over the table).  The jump
+  // is jump_state's Horner evaluation split in two: the 64 window sums
+  // A_c = h_c(T) S0 do not depend on each other, so the workgroup's
+  // wavefronts compute them (c = wave, wave + kSegWaves, ...) into LDS; then
+  // one wavefront runs the chain S <- T^64 S xor A_c, c = 63 .. 0.
+  __shared__ uint32_t win[192];        // x_{-128} .. x_{63} of the stream's continuation
+  __shared__ uint32_t acc[64 * 128];   // A_c: acc[128 c + j] lane j's low word, [128 c + 64 + j] its high word
+  const uint32_t lane = lane_id();
+  const bool lane0 = lane == 0;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const uint32_t entries = work[3];
+  for (uint32_t r = blockIdx.x; r < entries; r += gridDim.x) {
+    const xg_request q = reqs[r];  // the same on every thread of the workgroup
+    if (!(q.flags & kReqSegment) || !seg_entry_ok(q, num_streams, seg)) continue;
+    const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)((q.flags >> 8) & 0xFFu));
+    const uint32_t slot = q.flags >> 16;
+    StreamState s = load_state(state + q.stream * kStateWords);
+    uint32_t *dst = seg.stage + (uint64_t)slot * kStateWords;
+    if (k == 0) {
+      if (wave == 0) write_state(dst, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane);
+      continue;
+    }
+    if (wave == 0) {
+      Ring r0 = ring_from(s.prev, s.cur);
+      const uint32_t x0 = ring_step(r0, lane0);  // x_0 .. x_63
+      win[lane] = s.prev;
+      win[64 + lane] = s.cur;
+      win[128 + lane] = x0;
+    }
+    __syncthreads();
+    uint32_t xw[128];  // xw[i] = x_{i-128+j}
+#pragma unroll
+    for (int i = 0; i < 128; ++i) xw[i] = win[lane + i];
+    // lane c holds h_c, the jump polynomial's 64 coefficients of z^(64 c + i)
+    const uint64_t h = seg.jump_table[(uint64_t)(k - 1) * 64 + lane];
+    const int h_lo = (int)(uint32_t)h, h_hi = (int)(uint32_t)(h >> 32);
+#pragma unroll 1
+    for (uint32_t c = wave; c < 64u; c += kSegWaves) {
+      const uint32_t hlo = (uint32_t)__builtin_amdgcn_readlane(h_lo, (int)c);
+      const uint32_t hhi = (uint32_t)__builtin_amdgcn_readlane(h_hi, (int)c);
+      uint32_t alo = 0u, ahi = 0u;
+#pragma unroll
+      for (int i = 0; i < 64; ++i) {
+        const uint32_t bits = i < 32 ? hlo : hhi;
+        const uint32_t m = (uint32_t)((int32_t)(bits << (31 - (i & 31))) >> 31);  // bit i of h_c, all ones or zero
+        alo = xor_and(alo, xw[i], m);
+        ahi = xor_and(ahi, xw[64 + i], m);
+      }
+      acc[128u * c + lane] = alo;
+      acc[128u * c + 64u + lane] = ahi;
+    }
+    __syncthreads();
+    if (wave == 0) {
+      uint32_t slo = acc[128u * 63u + lane], shi = acc[128u * 63u + 64u + lane];
+#pragma unroll 4
+      for (int c = 62; c >= 0; --c) {
+        Ring rc = ring_from(slo, shi);
+        const uint32_t nx = ring_step(rc, lane0);
+        slo = shi ^ acc[128u * c + lane];
+        shi = nx ^ acc[128u * c + 64u + lane];
+      }
+      const uint64_t J = (uint64_t)k * seg.seg_words;
+      write_state(dst, slo, shi, 0u, 0u, s.weyl + (uint32_t)J * kOmega, s.pos + J, lane);
+    }
+    __syncthreads();  // win and acc are rewritten for the next entry
   }
-  write_state(seg.stage + (uint64_t)slot * kStateWords, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane_id());
 }
 
 // Persistent batched kernel: wavefronts take request groups from an atomic
@@ -858,10 +922,14 @@ hipError_t launch_work_requeue(uint32_t *work, hipStream_t stream) {
 }
 
 hipError_t launch_seg_starts(const uint32_t *state, uint64_t num_streams, const xg_request *reqs,
-                             uint32_t max_entries, const uint32_t *work, const SegmentArgs &seg, hipStream_t stream) {
+                             uint32_t max_entries, const uint32_t *work, const SegmentArgs &seg, int num_cus,
+                             hipStream_t stream) {
   if (max_entries == 0) return hipSuccess;
-  return launch(k_seg_starts, dim3((max_entries + 3) / 4), dim3(256), 4 * 1024, stream, state, num_streams, reqs,
-                work, seg);
+  // As many workgroups as fit on the chip at once, each taking every
+  // gridDim-th entry.
+  const uint32_t slots = (num_cus > 0 ? (uint32_t)num_cus : 1u) * kSegBlocksPerCu;
+  const uint32_t blocks = max_entries < slots ? max_entries : slots;
+  return launch(k_seg_starts, dim3(blocks), dim3(kSegWaves * 64), 0, stream, state, num_streams, reqs, work, seg);
 }
 
 hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64_t num_streams,

@@ -256,7 +256,8 @@ xg_status admit_and_launch(xg_server *s, uint32_t li, uint32_t *admitted) {
   } else {
     const xg::SegmentArgs seg{s->d_jump, s->seg_words, s->d_jump ? kJumpEntries : 0u, l.d_stage, s->max_batch};
     if (any_split &&
-        xg::launch_seg_starts(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_work, seg, l.stream) != hipSuccess)
+        xg::launch_seg_starts(s->ctx->d_state, s->ctx->num_streams, l.d_reqs, k, l.d_work, seg, s->ctx->num_cus,
+                              l.stream) != hipSuccess)
       return XG_EHIP;
     if (xg::launch_batch(shape, s->ctx->num_cus, s->ctx->d_state, s->ctx->num_streams, l.d_reqs, l.d_groups,
                          num_groups, s->d_pool, s->pool_elems, l.d_work, l.stream,
