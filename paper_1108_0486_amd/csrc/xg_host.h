@@ -33,9 +33,13 @@ xg_status plan_batch(const xg_request *h_reqs, uint32_t num_reqs, uint64_t num_s
 bool jump_polynomial(uint64_t J, uint64_t g[64]);
 
 // The same for a member XG_FAMILY_*: g receives member_degree(family) / 64
-// words.  False for an unknown family or if P could not be derived.
+// words.  False for an unknown family or if P could not be derived.  The
+// last 16 distinct (family, J) are kept, so repeated jumps by one J (streams
+// split into equal blocks) skip the powering; jump_polynomial_uncached always
+// computes.
 int member_degree(uint32_t family);
 bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g);
+bool jump_polynomial_uncached(uint32_t family, uint64_t J, uint64_t *g);
 
 // table[k] (member_degree(family) / 64 words each) = z^((k + 1) L) mod P for
 // k < count.  False for an unknown family, if P could not be derived, or if

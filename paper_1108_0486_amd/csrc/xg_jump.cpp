@@ -183,17 +183,57 @@ void z_pow(const Field &F, uint64_t J, uint64_t *g) {
   }
 }
 
+// The most recently used jump polynomials, least recently used replaced.
+struct CachedJump {
+  uint32_t family = 0;
+  uint64_t J = 0;
+  uint64_t used = 0;  // 0: empty
+  std::vector<uint64_t> g;
+};
+constexpr size_t kCachedJumps = 16;
+std::mutex g_cache_mu;
+CachedJump g_cache[kCachedJumps];
+uint64_t g_cache_clock = 0;
+
 }  // namespace
 
 int member_degree(uint32_t family) { return family < 3 ? kMembers[family].n() : 0; }
 
-bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g) {
+bool jump_polynomial_uncached(uint32_t family, uint64_t J, uint64_t *g) {
   const Field *F = field(family);
   if (!F) return false;
   try {
     z_pow(*F, J, g);
   } catch (const std::bad_alloc &) {
     return false;
+  }
+  return true;
+}
+
+bool jump_polynomial(uint32_t family, uint64_t J, uint64_t *g) {
+  const Field *F = field(family);
+  if (!F) return false;
+  const size_t words = (size_t)F->words;
+  {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    for (CachedJump &e : g_cache)
+      if (e.used && e.family == family && e.J == J) {
+        std::memcpy(g, e.g.data(), sizeof(uint64_t) * words);
+        e.used = ++g_cache_clock;
+        return true;
+      }
+  }
+  if (!jump_polynomial_uncached(family, J, g)) return false;
+  try {
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    CachedJump *slot = &g_cache[0];
+    for (CachedJump &e : g_cache)
+      if (e.used < slot->used) slot = &e;  // an empty entry (0) first, else the oldest
+    slot->g.assign(g, g + words);
+    slot->family = family;
+    slot->J = J;
+    slot->used = ++g_cache_clock;
+  } catch (const std::bad_alloc &) {  // the result stands; it is only not kept
   }
   return true;
 }

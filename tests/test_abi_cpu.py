@@ -272,3 +272,18 @@ def test_tune_cache_env_file_loaded_before_first_lookup(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, cwd=root,
                          check=True).stdout
     assert out.split() == ["(2,", "4,", "3,", "0)", "1"]
+
+
+def test_jump_polynomial_cache_keeps_results():
+    """The library keeps its 16 most recent jump polynomials: 24 distinct J
+    (more than it keeps, for two members), then the same J again in another
+    order (hits and recomputations after eviction) all equal the oracle's."""
+    from oracle import oracle as O
+    P = {xg.XG_FAMILY_R128_W32: O.charpoly(O.PAPER), xg.XG_FAMILY_R64_W64: O.charpoly(O.W64)}
+    Js = [(2**40 + 977 * k) for k in range(24)]
+    want = {(f, J): O.z_pow_mod(J, P[f]) for f in P for J in Js[::5]}
+    first = {(f, J): xg.xg_family_jump_polynomial(f, J) for J in Js for f in P}
+    for f, J in reversed(list(first)):
+        assert xg.xg_family_jump_polynomial(f, J) == first[(f, J)], (f, J)
+    for key, g in want.items():
+        assert first[key] == g, key
