@@ -402,6 +402,40 @@ def test_small_table_planner_equals_multi_kernel_planner(num_reqs):
     _check_plan([r for r in reqs if r[3] <= 2], rows, groups, S)
 
 
+@pytest.mark.parametrize("kind", ["one_stream", "all_invalid", "distinct_streams", "mostly_empty"])
+def test_small_table_planner_edge_tables(kind):
+    """Edge tables at the one-workgroup planner's limit of 1024 requests, each
+    against the multi-kernel planner: one stream holding every request (one
+    group of 1024), every request failing the checks, 1024 distinct streams
+    (1024 groups in cost order), and mostly empty requests."""
+    S, n_req = 1100, 1024
+    rng = np.random.default_rng(77)
+    reqs, off = [], 0
+    for i in range(n_req):
+        if kind == "one_stream":
+            st, n, dt = 0, int(rng.integers(1, 300)), i % 3
+        elif kind == "all_invalid":
+            st, n, dt = S + i, 10, 0
+        elif kind == "distinct_streams":
+            st, n, dt = (i * 37) % n_req, 64 + (i * 7919) % 2000, i % 3
+        else:
+            st, n, dt = int(rng.integers(0, 50)), (int(rng.integers(1, 100)) if i % 5 == 0 else 0), i % 3
+        reqs.append((st, n, off, dt))
+        off += n
+    (plan_a, err_a, out_a, st_a), (plan_b, err_b, out_b, st_b) = _plan_pair(
+        reqs, off, S, 8, {}, {"tile_words": 1 << 30, "max_tiles": 2048})
+    assert plan_a == plan_b
+    assert err_a == err_b == int(kind == "all_invalid")
+    assert (out_a == out_b).all()
+    assert all((x == y).all() for x, y in zip(st_a, st_b))
+    rows, groups = plan_a
+    if kind == "all_invalid":
+        assert rows == [] and groups == [0]
+    else:
+        _check_plan(reqs, rows, groups, S)
+        assert len(groups) - 1 == len({r[0] for r in reqs})
+
+
 def test_small_table_planner_tiles_equal_multi_kernel_planner():
     """Tiles in the one-workgroup planner (19 requests, 1000 tile slots) and in
     the multi-kernel planner (2048 slots): the same plan, outputs and states,
