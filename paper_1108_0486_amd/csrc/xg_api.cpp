@@ -359,7 +359,7 @@ xg_status xg_skip(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_t J, void 
   if (!step && !xg::jump_polynomial(ctx->family, J, g.w)) return XG_ENOTSUP;
   hipError_t e;
   if (paper_member(ctx))
-    e = xg::launch_skip(ctx->d_state, first, count, J, step ? nullptr : &g, s);
+    e = xg::launch_skip(ctx->d_state, first, count, J, step ? nullptr : &g, ctx->num_cus, s);
   else
     e = xg::launch_family_skip(ctx->family, reinterpret_cast<unsigned char *>(ctx->d_state), first, count, J,
                                step ? nullptr : &g, s);

@@ -66,9 +66,10 @@ struct JumpPoly {
 };
 
 // Advances streams [first, first + count) by J words: by stepping when
-// g == nullptr, else by evaluating g(T) on each state (g = z^J mod P).
+// g == nullptr, else by evaluating g(T) on each state (g = z^J mod P), with a
+// workgroup per stream when the streams fit on num_cus compute units at once.
 hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
-                       hipStream_t stream);
+                       int num_cus, hipStream_t stream);
 
 // Segment entries of a batch table (kReqSegment, see xg_host.h): tile k of a
 // request starts from its stream's state jumped by k L words, staged in slot

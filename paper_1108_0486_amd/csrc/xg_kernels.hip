@@ -630,6 +630,87 @@ __global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ state, uint
   }
 }
 
+// Wavefronts that share one jump.  Four: at 142 VGPRs per lane (three
+// wavefronts per SIMD) three such workgroups fit on a compute unit.
+constexpr uint32_t kSegWaves = 4;
+constexpr uint32_t kSegBlocksPerCu = 3;
+
+// LDS of one workgroup jump: the window x_{-128} .. x_{63} of the stream's
+// continuation, and the 64 window sums A_c (acc[128 c + j] lane j's low word,
+// acc[128 c + 64 + j] its high word).
+struct JumpLds {
+  uint32_t win[192];
+  uint32_t acc[64 * 128];
+};
+
+// jump_state's Horner evaluation split over the kSegWaves wavefronts of a
+// workgroup: the window sums A_c = h_c(T) S0 do not depend on each other, so
+// wavefront w computes A_c for c = w, w + kSegWaves, ... into LDS; then
+// wavefront 0 runs the chain S <- T^64 S xor A_c, c = 63 .. 0, and its s holds
+// T^J s on return (the others' s is unchanged).  Every thread of the
+// workgroup calls it with the same s; lane c's h_lo / h_hi hold h_c (so the
+// coefficients come from registers, read with v_readlane, and the masks from
+// scalar bit-field extracts).  Ends with a barrier: lds may be reused at once.
+__device__ __forceinline__ void jump_state_wg(StreamState &s, int h_lo, int h_hi, uint64_t J, JumpLds &lds,
+                                              uint32_t wave) {
+  const uint32_t lane = lane_id();
+  const bool lane0 = lane == 0;
+  if (wave == 0) {
+    Ring r0 = ring_from(s.prev, s.cur);
+    const uint32_t x0 = ring_step(r0, lane0);  // x_0 .. x_63
+    lds.win[lane] = s.prev;
+    lds.win[64 + lane] = s.cur;
+    lds.win[128 + lane] = x0;
+  }
+  __syncthreads();
+  uint32_t xw[128];  // xw[i] = x_{i-128+j}
+#pragma unroll
+  for (int i = 0; i < 128; ++i) xw[i] = lds.win[lane + i];
+#pragma unroll 1
+  for (uint32_t c = wave; c < 64u; c += kSegWaves) {
+    const uint32_t hlo = (uint32_t)__builtin_amdgcn_readlane(h_lo, (int)c);
+    const uint32_t hhi = (uint32_t)__builtin_amdgcn_readlane(h_hi, (int)c);
+    uint32_t alo = 0u, ahi = 0u;
+#pragma unroll
+    for (int i = 0; i < 64; ++i) {
+      const uint32_t bits = i < 32 ? hlo : hhi;
+      const uint32_t m = (uint32_t)((int32_t)(bits << (31 - (i & 31))) >> 31);  // bit i of h_c, all ones or zero
+      alo = xor_and(alo, xw[i], m);
+      ahi = xor_and(ahi, xw[64 + i], m);
+    }
+    lds.acc[128u * c + lane] = alo;
+    lds.acc[128u * c + 64u + lane] = ahi;
+  }
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t slo = lds.acc[128u * 63u + lane], shi = lds.acc[128u * 63u + 64u + lane];
+#pragma unroll 4
+    for (int c = 62; c >= 0; --c) {
+      Ring rc = ring_from(slo, shi);
+      const uint32_t nx = ring_step(rc, lane0);
+      slo = shi ^ lds.acc[128u * c + lane];
+      shi = nx ^ lds.acc[128u * c + 64u + lane];
+    }
+    s.prev = slo;
+    s.cur = shi;
+    s.weyl += (uint32_t)J * kOmega;
+    s.pos += J;
+  }
+  __syncthreads();  // win and acc are free again
+}
+
+// Few streams: one workgroup of kSegWaves wavefronts per stream.
+__global__ __launch_bounds__(kSegWaves * 64) void k_skip_wg(uint32_t *__restrict__ state, uint64_t first, uint64_t J,
+                                                            JumpPoly g) {
+  __shared__ JumpLds lds;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  uint32_t *st = state + (first + blockIdx.x) * kStateWords;
+  StreamState s = load_state(st);
+  const uint64_t h = g.w[lane_id()];  // lane c holds h_c
+  jump_state_wg(s, (int)(uint32_t)h, (int)(uint32_t)(h >> 32), J, lds, wave);
+  if (wave == 0) write_state(st, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane_id());
+}
+
 // Box-Muller on caller-supplied word pairs (the same device function the
 // generators use): out[2m], out[2m + 1] from words[2m], words[2m + 1].
 __global__ __launch_bounds__(256) void k_box_muller(const uint32_t *__restrict__ words, uint64_t pairs,
@@ -667,27 +748,15 @@ __device__ __forceinline__ bool seg_entry_ok(const xg_request &q, uint64_t num_s
 // skipped (the batch kernel skips those too).  The batch kernel then starts
 // each segment from its slot, so no segment reads a stream state that the
 // request's last segment rewrites.
-// Wavefronts that share one segment's jump.  Four: at 142 VGPRs per lane
-// (three wavefronts per SIMD) three such workgroups fit on a compute unit, so
-// many segments keep the chip as busy as one wavefront per segment did, while
-// one segment's jump takes a quarter of the window sums' time.
-constexpr uint32_t kSegWaves = 4;
-constexpr uint32_t kSegBlocksPerCu = 3;
-
 __global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *__restrict__ state,
                                                                uint64_t num_streams,
                                                                const xg_request *__restrict__ reqs,
                                                                const uint32_t *__restrict__ work,
                                                                SegmentArgs seg) {
-  // One workgroup per segment entry (grid-stride over the table).  The jump
-  // is jump_state's Horner evaluation split in two: the 64 window sums
-  // A_c = h_c(T) S0 do not depend on each other, so the workgroup's
-  // wavefronts compute them (c = wave, wave + kSegWaves, ...) into LDS; then
-  // one wavefront runs the chain S <- T^64 S xor A_c, c = 63 .. 0.
-  __shared__ uint32_t win[192];        // x_{-128} .. x_{63} of the stream's continuation
-  __shared__ uint32_t acc[64 * 128];   // A_c: acc[128 c + j] lane j's low word, [128 c + 64 + j] its high word
+  // One workgroup per segment entry (grid-stride over the table); the jump by
+  // k L words is jump_state_wg with the polynomial of table entry k - 1.
+  __shared__ JumpLds lds;
   const uint32_t lane = lane_id();
-  const bool lane0 = lane == 0;
   const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const uint32_t entries = work[3];
   for (uint32_t r = blockIdx.x; r < entries; r += gridDim.x) {
@@ -697,53 +766,11 @@ __global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *_
     const uint32_t slot = q.flags >> 16;
     StreamState s = load_state(state + q.stream * kStateWords);
     uint32_t *dst = seg.stage + (uint64_t)slot * kStateWords;
-    if (k == 0) {
-      if (wave == 0) write_state(dst, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane);
-      continue;
+    if (k) {
+      const uint64_t h = seg.jump_table[(uint64_t)(k - 1) * 64 + lane];  // lane c holds h_c
+      jump_state_wg(s, (int)(uint32_t)h, (int)(uint32_t)(h >> 32), (uint64_t)k * seg.seg_words, lds, wave);
     }
-    if (wave == 0) {
-      Ring r0 = ring_from(s.prev, s.cur);
-      const uint32_t x0 = ring_step(r0, lane0);  // x_0 .. x_63
-      win[lane] = s.prev;
-      win[64 + lane] = s.cur;
-      win[128 + lane] = x0;
-    }
-    __syncthreads();
-    uint32_t xw[128];  // xw[i] = x_{i-128+j}
-#pragma unroll
-    for (int i = 0; i < 128; ++i) xw[i] = win[lane + i];
-    // lane c holds h_c, the jump polynomial's 64 coefficients of z^(64 c + i)
-    const uint64_t h = seg.jump_table[(uint64_t)(k - 1) * 64 + lane];
-    const int h_lo = (int)(uint32_t)h, h_hi = (int)(uint32_t)(h >> 32);
-#pragma unroll 1
-    for (uint32_t c = wave; c < 64u; c += kSegWaves) {
-      const uint32_t hlo = (uint32_t)__builtin_amdgcn_readlane(h_lo, (int)c);
-      const uint32_t hhi = (uint32_t)__builtin_amdgcn_readlane(h_hi, (int)c);
-      uint32_t alo = 0u, ahi = 0u;
-#pragma unroll
-      for (int i = 0; i < 64; ++i) {
-        const uint32_t bits = i < 32 ? hlo : hhi;
-        const uint32_t m = (uint32_t)((int32_t)(bits << (31 - (i & 31))) >> 31);  // bit i of h_c, all ones or zero
-        alo = xor_and(alo, xw[i], m);
-        ahi = xor_and(ahi, xw[64 + i], m);
-      }
-      acc[128u * c + lane] = alo;
-      acc[128u * c + 64u + lane] = ahi;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      uint32_t slo = acc[128u * 63u + lane], shi = acc[128u * 63u + 64u + lane];
-#pragma unroll 4
-      for (int c = 62; c >= 0; --c) {
-        Ring rc = ring_from(slo, shi);
-        const uint32_t nx = ring_step(rc, lane0);
-        slo = shi ^ acc[128u * c + lane];
-        shi = nx ^ acc[128u * c + 64u + lane];
-      }
-      const uint64_t J = (uint64_t)k * seg.seg_words;
-      write_state(dst, slo, shi, 0u, 0u, s.weyl + (uint32_t)J * kOmega, s.pos + J, lane);
-    }
-    __syncthreads();  // win and acc are rewritten for the next entry
+    if (wave == 0) write_state(dst, s.prev, s.cur, 0u, 0u, s.weyl, s.pos, lane);
   }
 }
 
@@ -886,10 +913,14 @@ hipError_t launch_box_muller(const uint32_t *words, uint64_t pairs, float *out, 
 }
 
 hipError_t launch_skip(uint32_t *state, uint64_t first, uint64_t count, uint64_t J, const JumpPoly *g,
-                       hipStream_t stream) {
+                       int num_cus, hipStream_t stream) {
   hipError_t e = hipSuccess;
   const dim3 grid((uint32_t)((count + 3) / 4)), block(256);
-  if (g) {
+  if (g && count <= (uint64_t)(num_cus > 0 ? num_cus : 1) * kSegBlocksPerCu) {
+    // Streams that all fit on the chip at once as workgroup jumps: each jump
+    // takes about a quarter of one wavefront's time.
+    e = launch(k_skip_wg, dim3((uint32_t)count), dim3(kSegWaves * 64), 0, stream, state, first, J, *g);
+  } else if (g) {
     e = launch((k_skip<true>), grid, block, 4 * 1024, stream, state, first, count, J, *g);
   } else {
     JumpPoly none;

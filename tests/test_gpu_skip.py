@@ -70,3 +70,30 @@ def test_skip_then_generate_equals_generate_then_discard():
     b.u32(3 * 2**17 + 5)
     assert torch.equal(a.state, b.state)
     assert torch.equal(a.u32(5000), b.u32(5000))
+
+
+@pytest.mark.parametrize("J", [(1 << 20) + 3, 2**40 + 777])
+def test_skip_both_jump_kernels_agree(J):
+    """Jumps of at most 3 streams per compute unit run one workgroup per
+    stream (the window sums split over its wavefronts); larger launches run
+    one wavefront per stream.  The same streams through both launch forms
+    end in the same states, which equal the oracle's polynomial jump on
+    sampled streams and its stepping where that is short enough."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    S = 3 * cus + 1
+    a = XorgensStreams(S, seed=13)
+    b = XorgensStreams(S, seed=13)
+    a.skip(J)                                   # one wavefront per stream
+    b.skip(J, first=0, count=S - 1)             # one workgroup per stream
+    b.skip(J, first=S - 1, count=1)
+    assert torch.equal(a.state, b.state)
+    rows = [0, 1, S // 2, S - 2, S - 1]
+    ref = O.OracleStreams(13, S).subset(rows)
+    g = O.poly_to_words(O.z_pow_mod(J, O.charpoly(O.PAPER)), 64)
+    ring, _, pos = a.host_state(rows)
+    for j in range(len(rows)):
+        assert (ring[j] == O.xpart_jump_poly(O.PAPER, ref.ring[j], g)).all(), rows[j]
+    assert (pos == J).all()
+    if J < 1 << 21:
+        ref.skip(J)
+        assert (ring == ref.ring).all()
