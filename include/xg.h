@@ -35,7 +35,8 @@
  *     launches on the same handle.  A request server is driven by one host
  *     thread.
  *   - Process-wide state: the jump polynomials' modulus (built once per member
- *     and process, thread-safely), the tuning cache (guarded by a lock), and
+ *     and process, thread-safely) and the 16 most recent jump polynomials
+ *     (guarded by a lock), the tuning cache (guarded by a lock), and
  *     xg_generate_batch_static's device array (one per GPU).
  *
  * Stream state (device memory, XG_STATE_WORDS 32-bit words per stream, 528 B):
@@ -296,8 +297,11 @@ xg_status xg_normal_moments(xg_ctx *ctx, uint64_t first, uint64_t count, uint64_
  * words; longer ones jump: the x-part is GF(2)-linear (Section 1.5), its
  * 4096-bit state moves by a matrix T, and T^J = g(T) with g = z^J mod P, P
  * the characteristic polynomial of T (degree 4096, primitive); the host
- * computes g and each wavefront evaluates g(T) on its stream's state by
- * Horner's rule in steps of 64 words.  The Weyl value advances by J omega.
+ * computes g (keeping the 16 most recent (member, J) results, so a repeated
+ * J costs no powering) and the device evaluates g(T) on each stream's state
+ * by Horner's rule in steps of 64 words: one wavefront per stream, or, when
+ * the streams fit on the GPU at once (at most 3 per compute unit), a
+ * workgroup of four per stream.  The Weyl value advances by J omega.
  * Every family member is supported: for the r = 64 members P has degree n
  * (2048 or 4096) and the Horner steps are 32 words.
  * Errors: XG_EINVAL, XG_ERANGE, XG_ENOTSUP (P unavailable), XG_EHIP.  J == 0
