@@ -630,8 +630,9 @@ __global__ __launch_bounds__(256) void k_skip(uint32_t *__restrict__ state, uint
   }
 }
 
-// Wavefronts that share one jump.  Four: at 142 VGPRs per lane (three
-// wavefronts per SIMD) three such workgroups fit on a compute unit.
+// Wavefronts that share one jump.  Four: at the 137-148 VGPRs per lane of the
+// kernels below (at most 170 leave room for three wavefronts per SIMD), three
+// such workgroups fit on a compute unit.
 constexpr uint32_t kSegWaves = 4;
 constexpr uint32_t kSegBlocksPerCu = 3;
 
