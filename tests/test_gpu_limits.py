@@ -7,6 +7,9 @@
   stream-major and the bulk-fill layouts (4 * (2^32 + 154) bytes of output),
   checked against the oracle at the start, the ragged end and the far end of
   each stream, so a 32-bit index overflow anywhere shows.
+- Batch requests placed past 2^32 elements of the output (one crossing it,
+  one long request split into tiles beyond it), through the one-call and the
+  host-planned batch paths.
 """
 import numpy as np
 import pytest
@@ -92,3 +95,39 @@ def test_fill_value_reference_kernel(words):
     with pytest.raises(xg.XgError) as e:
         xg.xg_fill_value(out.data_ptr() + 4, 8, 1)
     assert e.value.status == xg.XG_EALIGN
+
+
+@pytest.mark.parametrize("path", ["device", "planned"])
+def test_batch_offsets_beyond_2p32_elements(path):
+    """A request that straddles element 2^32 of a 16 GiB output, one that
+    starts past it (FP32), and one long request whose tiles of 2^16 words all
+    lie past it (one-call path only; the planned path serves it whole): every
+    word equals the oracle's and nothing else in the buffer changes."""
+    from paper_1108_0486_amd.batch import Batch, PlannedBatch
+    L = 1 << 16
+    base = 1 << 32
+    reqs = [(0, 5000, base - 100, 0), (1, 3000, base + 12345, 1), (2, 3 * L + 17, base + 50000, 0)]
+    total = base + 50000 + 3 * L + 17 + 64
+    out = torch.full((total,), -1, dtype=torch.int32, device="cuda")
+    gs = XorgensStreams(3, seed=5)
+    if path == "device":
+        b = Batch(gs, reqs, total, out=out, tile_words=L, max_tiles=64)
+    else:
+        b = PlannedBatch(gs, reqs, total, out=out)
+    b.run()
+    torch.cuda.synchronize()
+    assert b.error_flag() == 0
+    if path == "device":
+        rows, _ = b.served_plan()
+        assert sum(1 for r in rows if r[4]) == 4              # stream 2's request as 4 tiles
+    ref = O.OracleStreams(5, 3)
+    for st, n, off, dt in reqs:
+        one = ref.subset([st])
+        want = one.u32(n)[0] if dt == 0 else one.f32(n)[0].view(np.uint32)
+        got = as_u32(out[off - 8:off + n + 8]).astype(np.uint32)
+        assert (got[8:8 + n] == want).all(), (st, off)
+        assert (got[:8] == 0xFFFFFFFF).all() and (got[8 + n:] == 0xFFFFFFFF).all(), st   # neighbours untouched
+    _, _, pos = gs.host_state()
+    assert list(pos) == [5000, 3000, 3 * L + 17]
+    del out, b
+    torch.cuda.empty_cache()
