@@ -72,7 +72,7 @@ def test_skip_then_generate_equals_generate_then_discard():
     assert torch.equal(a.u32(5000), b.u32(5000))
 
 
-@pytest.mark.parametrize("J", [(1 << 20) + 3, 2**40 + 777])
+@pytest.mark.parametrize("J", [(1 << 20) + 3, 2**40 + 777, 2**64 - 1])
 def test_skip_both_jump_kernels_agree(J):
     """Jumps of at most 3 streams per compute unit run one workgroup per
     stream (the window sums split over its wavefronts); larger launches run
