@@ -71,6 +71,41 @@ __global__ __launch_bounds__(256) void k_bitonic_step(uint64_t *__restrict__ a, 
   }
 }
 
+// M consecutive global passes j, j / 2, ..., j / 2^(M-1) of stage k in one
+// launch: the 2^M keys whose indices differ only in those M bits are closed
+// under these passes (and share the direction, since j < k), so each thread
+// loads one such group, runs the M passes in registers and stores it back.
+// Consecutive threads take consecutive indices below j / 2^(M-1), so every
+// load and store is coalesced.
+template <int M>
+__global__ __launch_bounds__(256) void k_bitonic_steps(uint64_t *__restrict__ a, uint32_t n, uint32_t k,
+                                                       uint32_t j) {
+  constexpr uint32_t G = 1u << M;
+  const uint32_t t = blockIdx.x * 256u + threadIdx.x;
+  if (t >= n / G) return;
+  const uint32_t jlo = j >> (M - 1);             // the smallest stride
+  const uint32_t i = ((t / jlo) * (jlo * G)) | (t % jlo);  // M zero bits at the strides' positions
+  const bool asc = (i & k) == 0u;
+  uint64_t v[G];
+#pragma unroll
+  for (uint32_t b = 0; b < G; ++b) v[b] = a[i + b * jlo];
+#pragma unroll
+  for (int m = M - 1; m >= 0; --m) {  // stride jlo 2^m: partners differ in bit m of b
+#pragma unroll
+    for (uint32_t b = 0; b < G; ++b) {
+      if (b & (1u << m)) continue;
+      const uint32_t c = b | (1u << m);
+      const uint64_t x = v[b], y = v[c];
+      if ((x > y) == asc) {
+        v[b] = y;
+        v[c] = x;
+      }
+    }
+  }
+#pragma unroll
+  for (uint32_t b = 0; b < G; ++b) a[i + b * jlo] = v[b];
+}
+
 // The passes with j < kSortBlock, in LDS, on each workgroup's kSortBlock
 // keys: the whole network up to k = kSortBlock when k == 0, else the passes
 // j = kSortBlock / 2 .. 1 of stage k.  Each of the 1024 threads takes
@@ -105,12 +140,25 @@ __global__ __launch_bounds__(1024) void k_bitonic_block(uint64_t *__restrict__ a
   for (uint32_t q = 0; q < kPer; ++q) a[base + t + 1024u * q] = s[t + 1024u * q];
 }
 
-// Sorts a[0, n) ascending; n is a power of two >= kSortBlock.
+// Sorts a[0, n) ascending; n is a power of two >= kSortBlock.  The global
+// passes of a stage go three at a time (k_bitonic_steps<3>), then the rest.
 hipError_t bitonic_sort(uint64_t *a, uint32_t n, hipStream_t stream) {
   hipError_t e = launch(k_bitonic_block, dim3(n / kSortBlock), dim3(1024), 0, stream, a, 0u);
   for (uint32_t k = 2 * kSortBlock; k <= n && e == hipSuccess; k <<= 1) {
-    for (uint32_t j = k >> 1; j >= kSortBlock && e == hipSuccess; j >>= 1)
-      e = launch(k_bitonic_step, dim3((n / 2 + 255) / 256), dim3(256), 0, stream, a, n, k, j);
+    uint32_t j = k >> 1;
+    while (j >= kSortBlock && e == hipSuccess) {
+      const uint32_t left = 31u - (uint32_t)__builtin_clz(j / kSortBlock) + 1u;  // passes j .. kSortBlock
+      if (left >= 3) {
+        e = launch(k_bitonic_steps<3>, dim3((n / 8 + 255) / 256), dim3(256), 0, stream, a, n, k, j);
+        j >>= 3;
+      } else if (left == 2) {
+        e = launch(k_bitonic_steps<2>, dim3((n / 4 + 255) / 256), dim3(256), 0, stream, a, n, k, j);
+        j >>= 2;
+      } else {
+        e = launch(k_bitonic_step, dim3((n / 2 + 255) / 256), dim3(256), 0, stream, a, n, k, j);
+        j >>= 1;
+      }
+    }
     if (e == hipSuccess) e = launch(k_bitonic_block, dim3(n / kSortBlock), dim3(1024), 0, stream, a, k);
   }
   return e;
