@@ -775,6 +775,11 @@ __global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *_
   }
 }
 
+// Queue items per trip to the batch queue: about kTakeWords words' worth, at
+// most kMaxTake items.
+constexpr uint32_t kMaxTake = 16;
+constexpr uint64_t kTakeWords = 65536;
+
 // Persistent batched kernel: wavefronts take request groups from an atomic
 // queue (work[0]) until it passes work[2] groups; every wavefront reaches the
 // exit.  A plain entry reads and rewrites its stream's state; a segment entry
@@ -788,39 +793,55 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
                                                 SegmentArgs seg) {
   const uint32_t lane = lane_id();
   const uint32_t num_groups = work[2], num_reqs = work[3];
+  // Items come largest first.  A wavefront takes `take` consecutive items per
+  // trip to the queue, up to kTakeWords words' worth by the size of the items
+  // it served last (one while they are larger, at most kMaxTake), so that
+  // small items do not make the one counter's atomics the bound: same-address
+  // atomics complete one at a time, and 2048 wavefronts on items of a few
+  // thousand words ask for more than that.
+  uint32_t take = 1;
   for (;;) {
-    uint32_t g = 0;
-    if (lane == 0) g = atomicAdd(&work[0], 1u);
-    g = (uint32_t)__builtin_amdgcn_readfirstlane((int)g);
-    if (g >= num_groups) break;
-    const uint32_t r0 = groups[g], r1 = groups[g + 1];
-    if (r0 > r1 || r1 > num_reqs) {
-      if (lane == 0) atomicOr(&work[1], 1u);
-      continue;
-    }
-    for (uint32_t r = r0; r < r1; ++r) {
-      const xg_request q = reqs[r];
-      const bool is_seg = (q.flags & kReqSegment) != 0;
-      const bool ok = (is_seg ? seg_entry_ok(q, num_streams, seg)
-                              : q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u) &&
-                      q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
-      if (!ok) {
+    uint32_t g0 = 0;
+    if (lane == 0) g0 = atomicAdd(&work[0], take);
+    g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
+    if (g0 >= num_groups) break;
+    const uint32_t g_end = num_groups - g0 < take ? num_groups : g0 + take;
+    uint64_t served = 0;
+    for (uint32_t g = g0; g < g_end; ++g) {
+      const uint32_t r0 = groups[g], r1 = groups[g + 1];
+      if (r0 > r1 || r1 > num_reqs) {
         if (lane == 0) atomicOr(&work[1], 1u);
         continue;
       }
-      uint32_t *st = state + q.stream * kStateWords;
-      const uint32_t *src = is_seg ? seg.stage + (uint64_t)(q.flags >> 16) * kStateWords : st;
-      uint32_t *dst = !is_seg || (q.flags & kReqLast) ? st : nullptr;
-      const StreamState s0 = load_state(src);
-      uint32_t *o = out + q.out_offset;
-      if (q.dtype == XG_U32) {
-        serve_words_from<kU32, UNROLL, WIDE>(s0, q.n, o, dst);
-      } else if (q.dtype == XG_F32) {
-        serve_words_from<kF32, UNROLL, WIDE>(s0, q.n, o, dst);
-      } else {
-        serve_normals_from<false, UNROLL, true>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
+      for (uint32_t r = r0; r < r1; ++r) {
+        const xg_request q = reqs[r];
+        const bool is_seg = (q.flags & kReqSegment) != 0;
+        const bool ok = (is_seg ? seg_entry_ok(q, num_streams, seg)
+                                : q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u) &&
+                        q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
+        if (!ok) {
+          if (lane == 0) atomicOr(&work[1], 1u);
+          continue;
+        }
+        uint32_t *st = state + q.stream * kStateWords;
+        const uint32_t *src = is_seg ? seg.stage + (uint64_t)(q.flags >> 16) * kStateWords : st;
+        uint32_t *dst = !is_seg || (q.flags & kReqLast) ? st : nullptr;
+        const StreamState s0 = load_state(src);
+        uint32_t *o = out + q.out_offset;
+        if (q.dtype == XG_U32) {
+          serve_words_from<kU32, UNROLL, WIDE>(s0, q.n, o, dst);
+        } else if (q.dtype == XG_F32) {
+          serve_words_from<kF32, UNROLL, WIDE>(s0, q.n, o, dst);
+        } else {
+          serve_normals_from<false, UNROLL, true>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
+        }
+        served += q.n;
       }
     }
+    // the largest power of two t <= kMaxTake with t items of this size within kTakeWords
+    const uint64_t budget = kTakeWords * (g_end - g0);
+    take = 1;
+    while (take < kMaxTake && served * (2u * take) <= budget) take <<= 1;
   }
 }
 
