@@ -588,103 +588,115 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
   L.j = L.lane >> 1;
   L.k = 0;
   L.active = true;
+  // Queue items are pairs of groups (one per half), largest first; a
+  // wavefront takes `take` consecutive pairs per atomic, as k_batch does.
+  const uint32_t num_pairs = (uint32_t)((num_groups + 1ull) / 2);
+  uint32_t take = 1;
   for (;;) {
-    uint32_t p = 0;
-    if (L.lane == 0) p = atomicAdd(&work[0], 1u);
-    p = (uint32_t)__builtin_amdgcn_readfirstlane((int)p);
-    if (2ull * p >= num_groups) break;
-    const uint64_t g = 2ull * p + L.h;
-    uint32_t r = 0, r_end = 0;
-    if (g < num_groups) {
-      r = groups[g];
-      r_end = groups[g + 1];
-      if (r > r_end || r_end > num_reqs) {
-        if (L.j == 0) atomicOr(&work[1], 1u);
-        r = r_end = 0;
-      }
-    }
-    uint64_t done = 0;  // words of the half's current request already written
-    for (;;) {
-      // Each half moves past bad and empty requests (no cross-lane work here).
-      xg_request q{};
-      bool have = false;
-      while (r < r_end) {
-        q = reqs[r];
-        const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u &&
-                        q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
-        if (ok && q.n > done) {
-          have = true;
-          break;
+    uint32_t p0 = 0;
+    if (L.lane == 0) p0 = atomicAdd(&work[0], take);
+    p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
+    if (p0 >= num_pairs) break;
+    const uint32_t p_end = num_pairs - p0 < take ? num_pairs : p0 + take;
+    uint64_t served = 0;  // words of the trips run for these pairs
+    for (uint32_t p = p0; p < p_end; ++p) {
+      const uint64_t g = 2ull * p + L.h;
+      uint32_t r = 0, r_end = 0;
+      if (g < num_groups) {
+        r = groups[g];
+        r_end = groups[g + 1];
+        if (r > r_end || r_end > num_reqs) {
+          if (L.j == 0) atomicOr(&work[1], 1u);
+          r = r_end = 0;
         }
-        if (!ok && L.j == 0) atomicOr(&work[1], 1u);
-        ++r;
-        done = 0;
       }
-      const uint64_t left = have ? q.n - done : 0;
-      const uint64_t left0 = lane_value(left, 0), left1 = lane_value(left, 1);
-      if (left0 == 0 && left1 == 0) break;
-      // Position of the half's next word within a 32-word line of the output.
-      // (Normals are written pair by pair and are not realigned.)
-      const uint32_t mis = have && q.dtype != XG_NORMAL
-                               ? (uint32_t)((reinterpret_cast<uintptr_t>(out) / sizeof(word) + q.out_offset + done) % kStep)
-                               : 0u;
-      const uint32_t mis0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 0));
-      const uint32_t mis1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 1));
-      if (mis0 != 0u || mis1 != 0u) {
-        // Head trip: one step, in which each half that starts inside a line
-        // writes only up to that line's end, so its later full steps store
-        // whole aligned lines (dense request offsets start most requests
-        // inside a line, which measured twice as slow).
-        const uint32_t head = mis != 0u ? (uint32_t)(left < kStep - mis ? left : kStep - mis) : 0u;
-        const bool mine = head != 0u;
+      uint64_t done = 0;  // words of the half's current request already written
+      for (;;) {
+        // Each half moves past bad and empty requests (no cross-lane work here).
+        xg_request q{};
+        bool have = false;
+        while (r < r_end) {
+          q = reqs[r];
+          const bool ok = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u &&
+                          q.out_offset <= out_elems && q.n <= out_elems - q.out_offset;
+          if (ok && q.n > done) {
+            have = true;
+            break;
+          }
+          if (!ok && L.j == 0) atomicOr(&work[1], 1u);
+          ++r;
+          done = 0;
+        }
+        const uint64_t left = have ? q.n - done : 0;
+        const uint64_t left0 = lane_value(left, 0), left1 = lane_value(left, 1);
+        if (left0 == 0 && left1 == 0) break;
+        // Position of the half's next word within a 32-word line of the output.
+        // (Normals are written pair by pair and are not realigned.)
+        const uint32_t mis = have && q.dtype != XG_NORMAL
+                                 ? (uint32_t)((reinterpret_cast<uintptr_t>(out) / sizeof(word) + q.out_offset + done) % kStep)
+                                 : 0u;
+        const uint32_t mis0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 0));
+        const uint32_t mis1 = (uint32_t)__builtin_amdgcn_readfirstlane((int)__shfl((int)mis, 1));
+        if (mis0 != 0u || mis1 != 0u) {
+          // Head trip: one step, in which each half that starts inside a line
+          // writes only up to that line's end, so its later full steps store
+          // whole aligned lines (dense request offsets start most requests
+          // inside a line, which measured twice as slow).
+          const uint32_t head = mis != 0u ? (uint32_t)(left < kStep - mis ? left : kStep - mis) : 0u;
+          const bool mine = head != 0u;
+          unsigned char *st = state + (mine ? q.stream : 0) * M::state_bytes;
+          word *o = out + (mine ? q.out_offset + done : 0) + L.j;
+          fam_head<M, kInt, kReal>(st, mine, L, head, q.dtype == XG_F32, o);
+          if (mine) {
+            done += head;
+            if (done == q.n) {
+              ++r;
+              done = 0;
+            }
+          }
+          continue;
+        }
+        const uint32_t dt0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 0));
+        const uint32_t dt1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 1));
+        bool run0 = left0 != 0;
+        bool run1 = left1 != 0 && (!run0 || dt0 == dt1);
+        uint64_t n = run0 ? (run1 && left1 < left0 ? left1 : left0) : left1;
+        const uint32_t kind = run0 ? dt0 : dt1;
+        if (kind == XG_NORMAL && (n & 1u)) {
+          // An odd count drops the second variate of its last pair, so only a
+          // half that finishes its request with this trip may take one.
+          const bool fin0 = run0 && left0 == n, fin1 = run1 && left1 == n;
+          if ((run0 && !fin0) || (run1 && !fin1)) {
+            if (n > 1) {
+              n -= 1;
+            } else {
+              run0 = fin0;
+              run1 = fin1;
+            }
+          }
+        }
+        const bool mine = L.h ? run1 : run0;
         unsigned char *st = state + (mine ? q.stream : 0) * M::state_bytes;
-        word *o = out + (mine ? q.out_offset + done : 0) + L.j;
-        fam_head<M, kInt, kReal>(st, mine, L, head, q.dtype == XG_F32, o);
+        const uint64_t at = mine ? q.out_offset + done : 0;
+        if (kind == XG_NORMAL)
+          fam_normals_run<M, false>(st, mine, L, n, reinterpret_cast<real *>(out) + at, nullptr);
+        else if (kind == XG_F32)
+          fam_run<M, kReal, UNROLL>(st, mine, L, n, out + at + L.j, kStep, nullptr);
+        else
+          fam_run<M, kInt, UNROLL>(st, mine, L, n, out + at + L.j, kStep, nullptr);
+        served += n;
         if (mine) {
-          done += head;
+          done += n;
           if (done == q.n) {
             ++r;
             done = 0;
           }
         }
-        continue;
-      }
-      const uint32_t dt0 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 0));
-      const uint32_t dt1 = (uint32_t)__builtin_amdgcn_readfirstlane(__shfl((int)q.dtype, 1));
-      bool run0 = left0 != 0;
-      bool run1 = left1 != 0 && (!run0 || dt0 == dt1);
-      uint64_t n = run0 ? (run1 && left1 < left0 ? left1 : left0) : left1;
-      const uint32_t kind = run0 ? dt0 : dt1;
-      if (kind == XG_NORMAL && (n & 1u)) {
-        // An odd count drops the second variate of its last pair, so only a
-        // half that finishes its request with this trip may take one.
-        const bool fin0 = run0 && left0 == n, fin1 = run1 && left1 == n;
-        if ((run0 && !fin0) || (run1 && !fin1)) {
-          if (n > 1) {
-            n -= 1;
-          } else {
-            run0 = fin0;
-            run1 = fin1;
-          }
-        }
-      }
-      const bool mine = L.h ? run1 : run0;
-      unsigned char *st = state + (mine ? q.stream : 0) * M::state_bytes;
-      const uint64_t at = mine ? q.out_offset + done : 0;
-      if (kind == XG_NORMAL)
-        fam_normals_run<M, false>(st, mine, L, n, reinterpret_cast<real *>(out) + at, nullptr);
-      else if (kind == XG_F32)
-        fam_run<M, kReal, UNROLL>(st, mine, L, n, out + at + L.j, kStep, nullptr);
-      else
-        fam_run<M, kInt, UNROLL>(st, mine, L, n, out + at + L.j, kStep, nullptr);
-      if (mine) {
-        done += n;
-        if (done == q.n) {
-          ++r;
-          done = 0;
-        }
       }
     }
+    const uint64_t budget = kBatchTakeWords * (p_end - p0);
+    take = 1;
+    while (take < kBatchMaxTake && served * (2u * take) <= budget) take <<= 1;
   }
 }
 

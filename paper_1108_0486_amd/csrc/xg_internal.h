@@ -37,6 +37,13 @@ uint32_t auto_waves_per_block(uint64_t count, int num_cus);
 // per compute unit write fastest.  With fewer items each wavefront's own rate
 // decides, and eight chunks per trip serve a group fastest.  Neither uses the
 // wide stores: staging through LDS slowed the batch at every item count.
+// Queue items a batch wavefront takes per atomic: up to kBatchTakeWords
+// words' worth at the size of the items it just served, at most
+// kBatchMaxTake (one counter serves every wavefront, and same-address atomics
+// complete one at a time).
+constexpr uint32_t kBatchMaxTake = 16;
+constexpr uint64_t kBatchTakeWords = 65536;
+
 constexpr Shape kBatchThroughput{4, 1, 2, 1};
 constexpr Shape kBatchLatency{4, 8, 8, 1};
 inline Shape default_batch_shape(uint64_t items, int num_cus) {

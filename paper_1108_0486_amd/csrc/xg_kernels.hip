@@ -775,11 +775,6 @@ __global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *_
   }
 }
 
-// Queue items per trip to the batch queue: about kTakeWords words' worth, at
-// most kMaxTake items.
-constexpr uint32_t kMaxTake = 16;
-constexpr uint64_t kTakeWords = 65536;
-
 // Persistent batched kernel: wavefronts take request groups from an atomic
 // queue (work[0]) until it passes work[2] groups; every wavefront reaches the
 // exit.  A plain entry reads and rewrites its stream's state; a segment entry
@@ -794,11 +789,11 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
   const uint32_t lane = lane_id();
   const uint32_t num_groups = work[2], num_reqs = work[3];
   // Items come largest first.  A wavefront takes `take` consecutive items per
-  // trip to the queue, up to kTakeWords words' worth by the size of the items
-  // it served last (one while they are larger, at most kMaxTake), so that
-  // small items do not make the one counter's atomics the bound: same-address
-  // atomics complete one at a time, and 2048 wavefronts on items of a few
-  // thousand words ask for more than that.
+  // trip to the queue: one while they are large, then as many (a power of two
+  // up to kBatchMaxTake) as fit kBatchTakeWords words at the size of the items
+  // it served last, so that small items do not make the one counter's atomics
+  // the bound (same-address atomics complete one at a time, and 2048
+  // wavefronts on items of a few thousand words ask for more than that).
   uint32_t take = 1;
   for (;;) {
     uint32_t g0 = 0;
@@ -838,10 +833,10 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
         served += q.n;
       }
     }
-    // the largest power of two t <= kMaxTake with t items of this size within kTakeWords
-    const uint64_t budget = kTakeWords * (g_end - g0);
+    // the largest power of two t <= kBatchMaxTake with t such items in kBatchTakeWords
+    const uint64_t budget = kBatchTakeWords * (g_end - g0);
     take = 1;
-    while (take < kMaxTake && served * (2u * take) <= budget) take <<= 1;
+    while (take < kBatchMaxTake && served * (2u * take) <= budget) take <<= 1;
   }
 }
 
