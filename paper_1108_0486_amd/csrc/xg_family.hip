@@ -590,12 +590,14 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
   L.active = true;
   // Queue items are pairs of groups (one per half), largest first; a
   // wavefront takes `take` consecutive pairs per atomic, as k_batch does.
+  // The first pair is the wavefront's own index in the grid; later trips
+  // take pairs from the counter, offset by the wavefronts in the grid.
   const uint32_t num_pairs = (uint32_t)((num_groups + 1ull) / 2);
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t waves = gridDim.x * wpb;
+  uint32_t p0 = blockIdx.x * wpb + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   uint32_t take = 1;
   for (;;) {
-    uint32_t p0 = 0;
-    if (L.lane == 0) p0 = atomicAdd(&work[0], take);
-    p0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)p0);
     if (p0 >= num_pairs) break;
     const uint32_t p_end = num_pairs - p0 < take ? num_pairs : p0 + take;
     uint64_t served = 0;  // words of the trips run for these pairs
@@ -697,21 +699,26 @@ __global__ __launch_bounds__(1024) void k_fam_batch(unsigned char *__restrict__ 
     const uint64_t budget = kBatchTakeWords * (p_end - p0);
     take = 1;
     while (take < kBatchMaxTake && served * (2u * take) <= budget) take <<= 1;
+    uint32_t c = 0;
+    if (L.lane == 0) c = atomicAdd(&work[0], take);
+    p0 = waves + (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
   }
 }
 
 template <class M>
-hipError_t launch_fam_batch_k(uint32_t unroll, dim3 grid, dim3 block, unsigned char *state, uint64_t num_streams,
-                              const xg_request *reqs, const uint32_t *groups, void *out, uint64_t out_elems,
-                              uint32_t *work, hipStream_t stream) {
-  hipError_t e = hipSuccess;
+hipError_t launch_fam_batch_k(uint32_t unroll, uint64_t blocks, dim3 block, int num_cus, unsigned char *state,
+                              uint64_t num_streams, const xg_request *reqs, const uint32_t *groups, void *out,
+                              uint64_t out_elems, uint32_t *work, hipStream_t stream) {
+  auto run = [&](auto kernel) {
+    return launch_persistent(kernel, blocks, block, 0, num_cus, stream, state, num_streams, reqs, groups, out,
+                             out_elems, work);
+  };
   switch (unroll) {
-    case 1: e = launch((k_fam_batch<M, 1>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
-    case 2: e = launch((k_fam_batch<M, 2>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
-    case 4: e = launch((k_fam_batch<M, 4>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
-    default: e = launch((k_fam_batch<M, 8>), grid, block, 0, stream, state, num_streams, reqs, groups, out, out_elems, work); break;
+    case 1: return run(k_fam_batch<M, 1>);
+    case 2: return run(k_fam_batch<M, 2>);
+    case 4: return run(k_fam_batch<M, 4>);
+    default: return run(k_fam_batch<M, 8>);
   }
-  return e;
 }
 
 // ---------------------------------------------------------------------------
@@ -912,12 +919,12 @@ hipError_t launch_family_batch(uint32_t family, const Shape &shape, int num_cus,
   uint64_t blocks = (uint64_t)(num_cus > 0 ? num_cus : 1) * shape.blocks_per_cu;
   const uint64_t need = (pairs + shape.waves_per_block - 1) / shape.waves_per_block;
   if (need < blocks) blocks = need ? need : 1;
-  const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  const dim3 block(shape.waves_per_block * kWave);
   if (family == XG_FAMILY_R64_W32)
-    e = launch_fam_batch_k<MemberN2048>(shape.unroll, grid, block, state, num_streams, reqs, groups, out,
+    e = launch_fam_batch_k<MemberN2048>(shape.unroll, blocks, block, num_cus, state, num_streams, reqs, groups, out,
                                         out_elems, work, stream);
   else
-    e = launch_fam_batch_k<MemberW64>(shape.unroll, grid, block, state, num_streams, reqs, groups, out,
+    e = launch_fam_batch_k<MemberW64>(shape.unroll, blocks, block, num_cus, state, num_streams, reqs, groups, out,
                                       out_elems, work, stream);
   return e;
 }

@@ -794,11 +794,14 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
   // it served last, so that small items do not make the one counter's atomics
   // the bound (same-address atomics complete one at a time, and 2048
   // wavefronts on items of a few thousand words ask for more than that).
+  // A wavefront's first item is its own index in the grid (the first pops
+  // would hand out exactly those items, one atomic at a time); later trips
+  // take items from the counter, offset by the wavefronts in the grid.
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t waves = gridDim.x * wpb;
+  uint32_t g0 = blockIdx.x * wpb + (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   uint32_t take = 1;
   for (;;) {
-    uint32_t g0 = 0;
-    if (lane == 0) g0 = atomicAdd(&work[0], take);
-    g0 = (uint32_t)__builtin_amdgcn_readfirstlane((int)g0);
     if (g0 >= num_groups) break;
     const uint32_t g_end = num_groups - g0 < take ? num_groups : g0 + take;
     uint64_t served = 0;
@@ -837,6 +840,9 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
     const uint64_t budget = kBatchTakeWords * (g_end - g0);
     take = 1;
     while (take < kBatchMaxTake && served * (2u * take) <= budget) take <<= 1;
+    uint32_t c = 0;
+    if (lane == 0) c = atomicAdd(&work[0], take);
+    g0 = waves + (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
   }
 }
 
@@ -986,23 +992,21 @@ hipError_t launch_batch(const Shape &shape, int num_cus, uint32_t *state, uint64
   uint64_t blocks = (uint64_t)(num_cus > 0 ? num_cus : 1) * shape.blocks_per_cu;
   const uint64_t need = ((uint64_t)max_groups + shape.waves_per_block - 1) / shape.waves_per_block;
   if (need < blocks) blocks = need ? need : 1;
-  const dim3 grid((uint32_t)blocks), block(shape.waves_per_block * kWave);
+  const dim3 block(shape.waves_per_block * kWave);
   const size_t lds = shape.store_words == 4 ? (size_t)shape.waves_per_block * 1024u : 0u;  // wide-store staging
   SegmentArgs sa{};
   if (seg) sa = *seg;
-  hipError_t e = hipSuccess;
-  if (shape.store_words == 4) {
-    if (shape.unroll == 4) e = launch((k_batch<4, true>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa);
-    else e = launch((k_batch<8, true>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa);
-    return e;
-  }
+  auto run = [&](auto kernel) {
+    return launch_persistent(kernel, blocks, block, lds, num_cus, stream, state, num_streams, reqs, groups, out,
+                             out_elems, work, sa);
+  };
+  if (shape.store_words == 4) return shape.unroll == 4 ? run(k_batch<4, true>) : run(k_batch<8, true>);
   switch (shape.unroll) {
-    case 1: e = launch((k_batch<1, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
-    case 2: e = launch((k_batch<2, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
-    case 4: e = launch((k_batch<4, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
-    default: e = launch((k_batch<8, false>), grid, block, lds, stream, state, num_streams, reqs, groups, out, out_elems, work, sa); break;
+    case 1: return run(k_batch<1, false>);
+    case 2: return run(k_batch<2, false>);
+    case 4: return run(k_batch<4, false>);
+    default: return run(k_batch<8, false>);
   }
-  return e;
 }
 
 }  // namespace xg
