@@ -511,8 +511,9 @@ __global__ __launch_bounds__(1024) void k_fam_generate(unsigned char *__restrict
 // ---------------------------------------------------------------------------
 // Batched requests (the persistent launch of xg_generate_batch) for these
 // members.  A wavefront serves two request groups at once, one per
-// half-wavefront (lanes 2j + h serve group 2p + h of pair p, taken from the
-// atomic queue work[0]).  Each loop trip runs min(words left in the two
+// half-wavefront (lanes 2j + h serve group 2p + h of pair p: first the pair
+// of the wavefront's own index in the grid, then pairs taken from the atomic
+// queue work[0]).  Each loop trip runs min(words left in the two
 // current requests) through fam_run, with the state written back between
 // trips, so both halves step together; a half whose group is done, or whose
 // current request has the other output type, is masked for that trip (half

@@ -775,9 +775,11 @@ __global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *_
   }
 }
 
-// Persistent batched kernel: wavefronts take request groups from an atomic
-// queue (work[0]) until it passes work[2] groups; every wavefront reaches the
-// exit.  A plain entry reads and rewrites its stream's state; a segment entry
+// Persistent batched kernel (launched with no more blocks than the device
+// holds at once): each wavefront serves the group of its own index, then takes
+// groups from an atomic queue (work[0], counting from the grid's wavefronts)
+// until it passes work[2] groups; every wavefront reaches the exit.  A plain
+// entry reads and rewrites its stream's state; a segment entry
 // starts from its staged start state and only the request's last segment
 // writes the stream's state.
 template <int UNROLL, bool WIDE>
