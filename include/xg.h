@@ -478,8 +478,10 @@ xg_status xg_generate_batch_planned(xg_ctx *ctx, const xg_request *d_reqs, uint3
                                     uint64_t out_elems, const xg_tune *tune, void *d_work, void *stream);
 
 /* Times candidate launch shapes of xg_generate_batch on the given table
- * (array order, as for xg_generate_batch) and returns the fastest in *best
- * (median of `reps` timed runs per shape after one warm-up).  The table is
+ * (array order, as for xg_generate_batch) and returns the fastest in *best:
+ * first the median of `reps` timed runs per shape after one warm-up, then the
+ * 8 fastest of those timed 5 more times each, in turns, the best median of
+ * these winning (their records in times_ms carry it).  The table is
  * planned once in ctx's batch scratch; each run times the persistent launch
  * (with the tiles' start states) on a scratch copy of the state:
  *   d_scratch_state  xg_family_state_bytes(family, num_streams of ctx) bytes,
