@@ -432,17 +432,23 @@ __global__ __launch_bounds__(256) void k_plan_emit(const xg_request *__restrict_
 
 // ---- small tables: the whole plan in one workgroup ---------------------------
 
-// Table entries plus tile slots that one workgroup (one element per thread)
-// plans in LDS with a single launch instead of the multi-kernel sequence
-// above; the plan is the same.
-constexpr uint32_t kSmallPlan = 1024;
+// Table entries plus tile slots that one workgroup of 1024 threads plans in
+// LDS with a single launch instead of the multi-kernel sequence above (the
+// plan is the same): EPT consecutive elements per thread, EPT = 1, 2 or 4, at
+// most 4096 elements (128 KB of LDS; gfx950 gives a workgroup 160 KB).
+constexpr uint32_t kPlanThreads = 1024;
+constexpr uint32_t kSmallPlanMax = 4 * kPlanThreads;
 
-// Exclusive prefix sum over the workgroup's kSmallPlan values (one per
-// thread); *total gets their sum.  wsum holds 16 values of T.
-template <typename T>
-__device__ __forceinline__ T wg_exclusive(T v, T *wsum, T *total) {
+// Exclusive prefix sums of the workgroup's values, EPT consecutive ones per
+// thread (v[e] is element EPT t + e): on return v[e] holds the sum of every
+// element before it, and *total the sum of all.  wsum holds 16 values of T.
+template <typename T, int EPT>
+__device__ __forceinline__ void wg_exclusive(T (&v)[EPT], T *wsum, T *total) {
   const uint32_t t = threadIdx.x, lane = t & 63u, w = t >> 6;
-  T x = v;
+  T mine = 0;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) mine += v[e];
+  T x = mine;
 #pragma unroll
   for (uint32_t d = 1; d < 64u; d <<= 1) {
     const T y = __shfl_up(x, d);
@@ -460,20 +466,28 @@ __device__ __forceinline__ T wg_exclusive(T v, T *wsum, T *total) {
     if (lane < 16u) wsum[lane] = s;
   }
   __syncthreads();
-  const T before = w ? wsum[w - 1] : T(0);
+  T run = (w ? wsum[w - 1] : T(0)) + x - mine;
   *total = wsum[15];
   __syncthreads();  // wsum is reused by the next scan
-  return before + x - v;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const T here = v[e];
+    v[e] = run;
+    run += here;
+  }
 }
 
-// Ascending bitonic sort of kSmallPlan keys in LDS (half the threads take a
-// pair in each pass).
+// Ascending bitonic sort of N keys in LDS (EPT / 2 pairs per thread and pass,
+// or half the threads with one pair each when EPT == 1).
+template <uint32_t N>
 __device__ __forceinline__ void wg_sort(uint64_t *s) {
   const uint32_t t = threadIdx.x;
-  for (uint32_t k = 2; k <= kSmallPlan; k <<= 1) {
+  constexpr uint32_t kPairs = N / 2;
+  for (uint32_t k = 2; k <= N; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      if (t < kSmallPlan / 2) {
-        const uint32_t i = ((t & ~(j - 1u)) << 1) | (t & (j - 1u));
+#pragma unroll
+      for (uint32_t pr = t; pr < kPairs; pr += kPlanThreads) {
+        const uint32_t i = ((pr & ~(j - 1u)) << 1) | (pr & (j - 1u));
         const uint32_t l = i | j;
         const bool asc = (i & k) == 0u;
         const uint64_t x = s[i], y = s[l];
@@ -487,119 +501,166 @@ __device__ __forceinline__ void wg_sort(uint64_t *s) {
   }
 }
 
-// The planner for num_reqs + tile_cap <= kSmallPlan: the steps of the kernels
-// above (keys, sort, group heads and cost sums, tiles and their budget, queue
-// items, their sort, entry counts, table), each on one element per thread,
-// with the arrays in LDS.  Writes offs[0 .. num_reqs + tile_cap], the table
-// and work[0 .. 63] (counts in work[2], work[3], the error word in work[1]).
-__global__ __launch_bounds__(kSmallPlan) void k_plan_small(const xg_request *__restrict__ reqs, uint32_t num_reqs,
-                                                           uint64_t num_streams, uint64_t tile_words,
-                                                           uint32_t tile_cap, uint32_t *__restrict__ work,
-                                                           uint32_t *__restrict__ offs_out,
-                                                           xg_request *__restrict__ table) {
-  __shared__ uint64_t keys[kSmallPlan];       // sort keys, then queue item keys
-  __shared__ uint64_t costs[kSmallPlan + 1];  // cost prefix sums over sorted requests
-  __shared__ uint32_t idx[kSmallPlan];        // request index at each sorted position
-  __shared__ uint32_t heads[kSmallPlan + 1];  // group prefix sums, then entry offsets of items
-  __shared__ uint32_t hp[kSmallPlan + 1];     // first sorted position of each group
-  __shared__ uint32_t tiles[kSmallPlan + 1];  // tile prefix sums per group
+// The planner for num_reqs + tile_cap <= N = 1024 EPT: the steps of the
+// kernels above (keys, sort, group heads and cost sums, tiles and their
+// budget, queue items, their sort, entry counts, table) on EPT consecutive
+// elements per thread, with the arrays in LDS.  Writes offs[0 .. num_reqs +
+// tile_cap], the table and work[0 .. 63] (counts in work[2], work[3], the
+// error word in work[1]).
+template <int EPT>
+__global__ __launch_bounds__(kPlanThreads) void k_plan_small(const xg_request *__restrict__ reqs,
+                                                             uint32_t num_reqs, uint64_t num_streams,
+                                                             uint64_t tile_words, uint32_t tile_cap,
+                                                             uint32_t *__restrict__ work,
+                                                             uint32_t *__restrict__ offs_out,
+                                                             xg_request *__restrict__ table) {
+  constexpr uint32_t N = kPlanThreads * EPT;
+  __shared__ uint64_t keys[N];       // sort keys, then queue item keys
+  __shared__ uint64_t costs[N + 1];  // cost prefix sums over sorted requests
+  __shared__ uint32_t idx[N];        // request index at each sorted position
+  __shared__ uint32_t heads[N + 1];  // group prefix sums, then entry offsets of items
+  __shared__ uint32_t hp[N + 1];     // first sorted position of each group
+  __shared__ uint32_t tiles[N + 1];  // tile prefix sums per group
   __shared__ uint64_t wsum[16];
-  __shared__ uint32_t cnt[4];                 // valid requests, error, tile slots used, items
-  const uint32_t t = threadIdx.x, n = num_reqs;
+  __shared__ uint32_t cnt[4];        // valid requests, error, tile slots used, items
+  const uint32_t t = threadIdx.x, n = num_reqs, i0 = t * EPT;
   uint32_t *wsum32 = reinterpret_cast<uint32_t *>(wsum);
   if (t >= 4u && t < 64u) work[t] = 0u;
   if (t < 4u) cnt[t] = 0u;
   __syncthreads();
 
-  uint64_t key = ~0ull;
-  if (t < n) {
-    const xg_request q = reqs[t];
-    const bool valid = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u;
-    key = ((valid ? q.stream : 0xFFFFFFFFull) << 32) | t;
-    if (valid) atomicAdd(&cnt[0], 1u);
-    else atomicOr(&cnt[1], 1u);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t i = i0 + e;
+    uint64_t key = ~0ull;
+    if (i < n) {
+      const xg_request q = reqs[i];
+      const bool valid = q.stream < num_streams && q.dtype <= XG_NORMAL && q.flags == 0u;
+      key = ((valid ? q.stream : 0xFFFFFFFFull) << 32) | i;
+      if (valid) atomicAdd(&cnt[0], 1u);
+      else atomicOr(&cnt[1], 1u);
+    }
+    keys[i] = key;
   }
-  keys[t] = key;
   __syncthreads();
-  wg_sort(keys);
+  wg_sort<N>(keys);
 
   const uint32_t valid_n = cnt[0];
-  uint32_t head = 0;
-  uint64_t cost = 0;
-  const uint64_t k_t = keys[t];
-  idx[t] = (uint32_t)k_t;
-  if (t < valid_n) {
-    head = t == 0 || (k_t >> 32) != (keys[t - 1] >> 32);
-    const xg_request q = reqs[(uint32_t)k_t];
-    cost = cost_of(q.n, q.dtype);
+  uint32_t head[EPT], hx[EPT];
+  uint64_t cx[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t i = i0 + e;
+    const uint64_t k = keys[i];
+    idx[i] = (uint32_t)k;
+    head[e] = 0;
+    cx[e] = 0;
+    if (i < valid_n) {
+      head[e] = i == 0 || (k >> 32) != (keys[i - 1] >> 32);
+      const xg_request q = reqs[(uint32_t)k];
+      cx[e] = cost_of(q.n, q.dtype);
+    }
+    hx[e] = head[e];
   }
   uint32_t num_groups;
-  const uint32_t hx = wg_exclusive<uint32_t>(head, wsum32, &num_groups);
-  heads[t] = hx;
-  if (t == kSmallPlan - 1u) heads[kSmallPlan] = num_groups;
+  wg_exclusive<uint32_t, EPT>(hx, wsum32, &num_groups);
   uint64_t cost_total;
-  const uint64_t cx = wg_exclusive<uint64_t>(cost, wsum, &cost_total);
-  costs[t] = cx;
-  if (t == kSmallPlan - 1u) costs[kSmallPlan] = cost_total;
+  wg_exclusive<uint64_t, EPT>(cx, wsum, &cost_total);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    heads[i0 + e] = hx[e];
+    costs[i0 + e] = cx[e];
+  }
+  if (t == kPlanThreads - 1u) {
+    heads[N] = num_groups;
+    costs[N] = cost_total;
+  }
   __syncthreads();
-  if (t < n && head) hp[hx] = t;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e)
+    if (i0 + e < n && head[e]) hp[hx[e]] = i0 + e;
   if (t == 0) hp[num_groups] = valid_n;
   __syncthreads();
 
-  uint32_t want = 0;
-  if (tile_cap && t < num_groups && hp[t + 1] - hp[t] == 1u) {
-    const xg_request q = reqs[idx[hp[t]]];
-    const uint64_t parts = (words_of(q.n, q.dtype) + tile_words - 1) / tile_words;
-    if (parts > 1 && parts <= kMaxSegments) want = (uint32_t)parts;
+  uint32_t want[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t g = i0 + e;
+    want[e] = 0;
+    if (tile_cap && g < num_groups && hp[g + 1] - hp[g] == 1u) {
+      const xg_request q = reqs[idx[hp[g]]];
+      const uint64_t parts = (words_of(q.n, q.dtype) + tile_words - 1) / tile_words;
+      if (parts > 1 && parts <= kMaxSegments) want[e] = (uint32_t)parts;
+    }
   }
   uint32_t tile_total;
-  const uint32_t tx = wg_exclusive<uint32_t>(want, wsum32, &tile_total);
-  tiles[t] = tx;
-  if (t == kSmallPlan - 1u) tiles[kSmallPlan] = tile_total;
-  if (tx && tx <= tile_cap) atomicMax(&cnt[2], tx);
+  wg_exclusive<uint32_t, EPT>(want, wsum32, &tile_total);
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    tiles[i0 + e] = want[e];
+    if (want[e] && want[e] <= tile_cap) atomicMax(&cnt[2], want[e]);
+  }
+  if (t == kPlanThreads - 1u) tiles[N] = tile_total;
   if (t == 0 && tile_total && tile_total <= tile_cap) atomicMax(&cnt[2], tile_total);
-  keys[t] = ~0ull;  // the sorted keys are done with: idx holds the request indices
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) keys[i0 + e] = ~0ull;  // idx holds the request indices now
   __syncthreads();
 
   const uint32_t used = cnt[2];
-  if (t < num_groups) {
-    if (group_split(tiles, t, used)) {
-      const xg_request q = reqs[idx[hp[t]]];
-      const uint32_t parts = tiles[t + 1] - tiles[t];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t g = i0 + e;
+    if (g >= num_groups) continue;
+    if (group_split(tiles, g, used)) {
+      const xg_request q = reqs[idx[hp[g]]];
+      const uint32_t parts = tiles[g + 1] - tiles[g];
       for (uint32_t k = 0; k < parts; ++k) {
         const uint64_t first = k * tile_words;
         const uint64_t nk = q.n - first < tile_words ? q.n - first : tile_words;
-        keys[tiles[t] + k] = item_key(cost_of(nk, q.dtype), t, k);
+        keys[tiles[g] + k] = item_key(cost_of(nk, q.dtype), g, k);
       }
       atomicAdd(&cnt[3], parts);
     } else {
-      keys[tile_cap + t] = item_key(costs[hp[t + 1]] - costs[hp[t]], t, 0);
+      keys[tile_cap + g] = item_key(costs[hp[g + 1]] - costs[hp[g]], g, 0);
       atomicAdd(&cnt[3], 1u);
     }
   }
   __syncthreads();
-  wg_sort(keys);
+  wg_sort<N>(keys);
 
   const uint32_t num_items = cnt[3];
-  uint32_t c = 0;
-  if (t < num_items) {
-    const uint32_t g = (uint32_t)keys[t] >> 8;
-    c = group_split(tiles, g, used) ? 1u : hp[g + 1] - hp[g];
+  uint32_t ox[EPT];
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t q = i0 + e;
+    ox[e] = 0;
+    if (q < num_items) {
+      const uint32_t g = (uint32_t)keys[q] >> 8;
+      ox[e] = group_split(tiles, g, used) ? 1u : hp[g + 1] - hp[g];
+    }
   }
   uint32_t entries;
-  const uint32_t ox = wg_exclusive<uint32_t>(c, wsum32, &entries);
-  heads[t] = ox;  // heads now holds the items' table offsets
-  if (t == kSmallPlan - 1u) heads[kSmallPlan] = entries;
+  wg_exclusive<uint32_t, EPT>(ox, wsum32, &entries);
   const uint32_t items = n + tile_cap;
-  if (t <= items) offs_out[t] = ox;
-  if (t == kSmallPlan - 1u && items == kSmallPlan) offs_out[kSmallPlan] = entries;
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    heads[i0 + e] = ox[e];  // heads now holds the items' table offsets
+    if (i0 + e <= items) offs_out[i0 + e] = ox[e];
+  }
+  if (t == kPlanThreads - 1u) {
+    heads[N] = entries;
+    if (items == N) offs_out[N] = entries;
+  }
   __syncthreads();
 
-  if (t < entries) {
-    uint32_t lo = 0, hi = num_items;  // heads[lo] <= t < heads[hi]
+#pragma unroll
+  for (int e = 0; e < EPT; ++e) {
+    const uint32_t en = i0 + e;
+    if (en >= entries) continue;
+    uint32_t lo = 0, hi = num_items;  // heads[lo] <= en < heads[hi]
     while (hi - lo > 1u) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (heads[mid] <= t) lo = mid;
+      if (heads[mid] <= en) lo = mid;
       else hi = mid;
     }
     const uint64_t it = keys[lo];
@@ -611,9 +672,9 @@ __global__ __launch_bounds__(kSmallPlan) void k_plan_small(const xg_request *__r
       q.n = q.n - first < tile_words ? q.n - first : tile_words;
       q.out_offset += first;
       q.flags = kReqSegment | (k << 8) | (slot << 16) | (k + 1 == parts ? kReqLast : 0u);
-      table[t] = q;
+      table[en] = q;
     } else {
-      table[t] = reqs[idx[hp[g] + (t - heads[lo])]];
+      table[en] = reqs[idx[hp[g] + (en - heads[lo])]];
     }
   }
   if (t == 0) {
@@ -684,10 +745,16 @@ PlanPtrs plan_ptrs(void *base, const PlanLayout &l) {
 hipError_t launch_plan(const PlanPtrs &p, const PlanLayout &l, const xg_request *reqs, uint32_t num_reqs,
                        uint64_t num_streams, uint64_t tile_words, uint32_t max_tiles, hipStream_t stream) {
   const uint32_t tile_cap = tile_words ? max_tiles : 0u;
-  if ((uint64_t)num_reqs + tile_cap <= kSmallPlan) {
-    if ((uint64_t)num_reqs + tile_cap + 1 > (uint64_t)(l.table - l.offs) / 4) return hipErrorInvalidValue;
-    return launch(k_plan_small, dim3(1), dim3(kSmallPlan), 0, stream, reqs, num_reqs, num_streams, tile_words,
-                  tile_cap, p.work, p.offs, p.table);
+  const uint64_t elems = (uint64_t)num_reqs + tile_cap;
+  if (elems <= kSmallPlanMax) {
+    if (elems + 1 > (uint64_t)(l.table - l.offs) / 4) return hipErrorInvalidValue;
+    auto run = [&](auto kernel) {
+      return launch(kernel, dim3(1), dim3(kPlanThreads), 0, stream, reqs, num_reqs, num_streams, tile_words,
+                    tile_cap, p.work, p.offs, p.table);
+    };
+    if (elems <= kPlanThreads) return run(k_plan_small<1>);
+    if (elems <= 2 * kPlanThreads) return run(k_plan_small<2>);
+    return run(k_plan_small<4>);
   }
   const uint32_t key_n = pow2_at_least(num_reqs > kSortBlock ? num_reqs : kSortBlock);
   const uint32_t items = num_reqs + tile_cap;

@@ -376,13 +376,14 @@ def _plan_pair(reqs, total, S, seed, small_kw, grid_kw):
     return out
 
 
-@pytest.mark.parametrize("num_reqs", [0, 1, 37, 500, 1023, 1024, 1025])
+@pytest.mark.parametrize("num_reqs", [0, 1, 37, 500, 1023, 1024, 1025, 1500, 2048, 2049, 3000, 4096, 4097])
 def test_small_table_planner_equals_multi_kernel_planner(num_reqs):
-    """Tables of up to 1024 requests are planned by one workgroup in LDS; the
-    same table sent through the multi-kernel planner (a tile capacity that
-    no request uses puts it there) gives the same table, item offsets, error
-    word, outputs and end states, with repeated streams, all three dtypes,
-    empty requests and requests that fail the checks."""
+    """Tables of up to 4096 requests are planned by one workgroup in LDS (1, 2
+    or 4 elements per thread); the same table sent through the multi-kernel
+    planner (a tile capacity that no request uses puts it there) gives the
+    same table, item offsets, error word, outputs and end states, with
+    repeated streams, all three dtypes, empty requests and requests that fail
+    the checks."""
     rng = np.random.default_rng(1000 + num_reqs)
     S = 97
     reqs, off = [], 0
@@ -393,7 +394,7 @@ def test_small_table_planner_equals_multi_kernel_planner(num_reqs):
         reqs.append((s, n, off, dt))
         off += n
     (plan_a, err_a, out_a, st_a), (plan_b, err_b, out_b, st_b) = _plan_pair(
-        reqs, off, S, 41, {}, {"tile_words": 1 << 30, "max_tiles": 2048})
+        reqs, off, S, 41, {}, {"tile_words": 1 << 30, "max_tiles": 4096})
     assert plan_a == plan_b
     assert err_a == err_b == int(any(r[0] >= S or r[3] > 2 for r in reqs))
     assert (out_a == out_b).all()
@@ -402,13 +403,15 @@ def test_small_table_planner_equals_multi_kernel_planner(num_reqs):
     _check_plan([r for r in reqs if r[3] <= 2], rows, groups, S)
 
 
+@pytest.mark.parametrize("n_req", [1024, 4096])
 @pytest.mark.parametrize("kind", ["one_stream", "all_invalid", "distinct_streams", "mostly_empty"])
-def test_small_table_planner_edge_tables(kind):
-    """Edge tables at the one-workgroup planner's limit of 1024 requests, each
-    against the multi-kernel planner: one stream holding every request (one
-    group of 1024), every request failing the checks, 1024 distinct streams
-    (1024 groups in cost order), and mostly empty requests."""
-    S, n_req = 1100, 1024
+def test_small_table_planner_edge_tables(kind, n_req):
+    """Edge tables at the one-workgroup planner's limits (1024 requests at one
+    element per thread, 4096 at four), each against the multi-kernel
+    planner: one stream holding every request (one group), every request
+    failing the checks, distinct streams (one group each, in cost order), and
+    mostly empty requests."""
+    S = n_req + 76
     rng = np.random.default_rng(77)
     reqs, off = [], 0
     for i in range(n_req):
@@ -423,7 +426,7 @@ def test_small_table_planner_edge_tables(kind):
         reqs.append((st, n, off, dt))
         off += n
     (plan_a, err_a, out_a, st_a), (plan_b, err_b, out_b, st_b) = _plan_pair(
-        reqs, off, S, 8, {}, {"tile_words": 1 << 30, "max_tiles": 2048})
+        reqs, off, S, 8, {}, {"tile_words": 1 << 30, "max_tiles": 4096})
     assert plan_a == plan_b
     assert err_a == err_b == int(kind == "all_invalid")
     assert (out_a == out_b).all()
@@ -436,17 +439,19 @@ def test_small_table_planner_edge_tables(kind):
         assert len(groups) - 1 == len({r[0] for r in reqs})
 
 
-def test_small_table_planner_tiles_equal_multi_kernel_planner():
-    """Tiles in the one-workgroup planner (19 requests, 1000 tile slots) and in
-    the multi-kernel planner (2048 slots): the same plan, outputs and states,
-    and the oracle's values."""
+@pytest.mark.parametrize("slots", [1000, 3000])
+def test_small_table_planner_tiles_equal_multi_kernel_planner(slots):
+    """Tiles in the one-workgroup planner (19 requests with 1000 or 3000 tile
+    slots: one and four elements per thread) and in the multi-kernel planner
+    (5000 slots): the same plan, outputs and states, and the oracle's
+    values."""
     L = 4096
     rng = np.random.default_rng(12)
     S = 12
     reqs, total = _tile_requests(rng, S, L)
-    assert len(reqs) + 1000 <= 1024
+    assert len(reqs) + slots <= 4096 and len(reqs) + 5000 > 4096
     (plan_a, err_a, out_a, st_a), (plan_b, err_b, out_b, st_b) = _plan_pair(
-        reqs, total, S + 1, 6, {"tile_words": L, "max_tiles": 1000}, {"tile_words": L, "max_tiles": 2048})
+        reqs, total, S + 1, 6, {"tile_words": L, "max_tiles": slots}, {"tile_words": L, "max_tiles": 5000})
     assert err_a == err_b == 0
     assert plan_a == plan_b
     rows, groups = plan_a
