@@ -62,11 +62,11 @@ __device__ __forceinline__ void sincos_turn(uint32_t o, float &s, float &c) {
 // rho = sqrt(-2 ln u1), u1 = ((e >> 8) + 1) 2^-24 in [2^-24, 1].  u1 is never
 // denormal, infinite or NaN, so no special-case guards: the hardware base-2
 // logarithm (within 1 ulp, relative, for every such u1), times -2 ln 2 held
-// as two floats (one rounding), gives x = -2 ln u1; the square root is the
-// hardware reciprocal square root refined by one Newton step on the residual
-// x - r0^2 (an FMA).  Over all 2^24 values of u1, rho is within 1.6 ulp of
-// sqrt(-2 ln u1).  u1 = 1 gives x = -0 and rho = -0 (the reciprocal square
-// root is taken of a tiny normal there instead of zero).
+// as two floats (one rounding), gives x = -2 ln u1, and the hardware square
+// root (v_sqrt_f32) gives rho.  Over all 2^24 values of u1, rho is within
+// 1.55 ulp of sqrt(-2 ln u1) (a reciprocal square root refined by a Newton
+// step, four instructions more, was within 1.59).  u1 = 1 gives x = -0 and
+// rho = -0.
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr float kM2Ln2Hi = (float)(-2.0 * kLn2);
 constexpr float kM2Ln2Lo = (float)(-2.0 * kLn2 - (double)kM2Ln2Hi);
@@ -75,10 +75,7 @@ __device__ __forceinline__ float rho_of(uint32_t e) {
   const float u1 = fmaf((float)(e >> 8), 0x1p-24f, 0x1p-24f);  // exact
   const float l2 = __builtin_amdgcn_logf(u1);
   const float x = fmaf(l2, kM2Ln2Hi, l2 * kM2Ln2Lo);
-  const float y = __builtin_amdgcn_rsqf(x + 0x1p-126f);         // x + 2^-126 == x unless x == 0
-  const float r0 = x * y;
-  const float res = fmaf(-r0, r0, x);
-  return fmaf(res, 0.5f * y, r0);
+  return __builtin_amdgcn_sqrtf(x);
 }
 
 __device__ __forceinline__ void box_muller(uint32_t e, uint32_t o, float &z0, float &z1) {
