@@ -19,37 +19,35 @@ namespace dev {
 // 4 u2 = m 2^-22 = q + 2f, where q = floor(4 u2 + 1/2) is the quadrant and
 // |f| <= 1/4, so 2 pi u2 = q pi/2 + pi f.  Adding 2^29 to o leaves q mod 4 in
 // bits 31:30 and (with o's low 8 bits cleared) 2^29 + f 2^31 in bits 29:0,
-// so f is exact.  sin(pi f) and cos(pi f) come from their Taylor series in
-// t = f^2 (the first omitted terms are below 2e-9 and 1.2e-10 relative at
-// |f| = 1/4), the leading pi f of the sine formed with pi split as
-// pi_hi + pi_lo so that it is rounded once.  A quarter-turn rotation by q
-// finishes: odd q swaps sin and cos, and the sign bits come straight from
-// the sum (sin is negated in quadrants 2 and 3, cos in quadrants 1 and 2).
-// f = 0 gives exact zeros and ones.
+// so f is exact.  sin(pi f) and cos(pi f) come from polynomials in t = f^2:
+// sin(pi f) = f (pi + t (S3 + t (S5 + t S7))) and cos(pi f) = 1 + t (C2 +
+// t (C4 + t (C6 + t C8))), with the coefficients of least maximum relative
+// error on |f| <= 1/4 (3.8e-9 and 6.4e-11; sincos_fit.py computes them), the
+// leading pi f of the sine formed with pi split as pi_hi + pi_lo so that it
+// is rounded once.  A quarter-turn rotation by q finishes: odd q swaps sin
+// and cos, and the sign bits come straight from the sum (sin is negated in
+// quadrants 2 and 3, cos in quadrants 1 and 2).  f = 0 gives exact zeros and
+// ones.
 constexpr double kPi = 3.14159265358979323846;
 constexpr float kPiHi = (float)kPi;
 constexpr float kPiLo = (float)(kPi - (double)kPiHi);
-constexpr float kS3 = (float)(-kPi * kPi * kPi / 6.0);
-constexpr float kS5 = (float)(kPi * kPi * kPi * kPi * kPi / 120.0);
-constexpr float kS7 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi / 5040.0);
-constexpr float kS9 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 362880.0);
-constexpr float kC2 = (float)(-kPi * kPi / 2.0);
-constexpr float kC4 = (float)(kPi * kPi * kPi * kPi / 24.0);
-constexpr float kC6 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi / 720.0);
-constexpr float kC8 = (float)(kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 40320.0);
-constexpr float kC10 = (float)(-kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi * kPi / 3628800.0);
+constexpr float kS3 = -0x1.4abbbep+2f;
+constexpr float kS5 = 0x1.466004p+1f;
+constexpr float kS7 = -0x1.2dc85p-1f;
+constexpr float kC2 = -0x1.3bd3ccp+2f;
+constexpr float kC4 = 0x1.03c1dep+2f;
+constexpr float kC6 = -0x1.55c5ep+0f;
+constexpr float kC8 = 0x1.d9d57cp-3f;
 
 __device__ __forceinline__ void sincos_turn(uint32_t o, float &s, float &c) {
   const uint32_t qf = o + 0x20000000u;
   const float f = fmaf((float)(qf & 0x3FFFFF00u), 0x1p-31f, -0.25f);  // exact (22-bit integer, dyadic result)
   const float t = f * f;
-  float p = fmaf(kS9, t, kS7);
-  p = fmaf(p, t, kS5);
+  float p = fmaf(kS7, t, kS5);
   p = fmaf(p, t, kS3);
-  const float tail = fmaf(p, t, kPiLo);          // pi_lo + t (S3 + t (S5 + t (S7 + t S9)))
+  const float tail = fmaf(p, t, kPiLo);          // pi_lo + t (S3 + t (S5 + t S7))
   const float sp = fmaf(f, kPiHi, f * tail);     // sin(pi f)
-  float r = fmaf(kC10, t, kC8);
-  r = fmaf(r, t, kC6);
+  float r = fmaf(kC8, t, kC6);
   r = fmaf(r, t, kC4);
   r = fmaf(r, t, kC2);
   const float cp = fmaf(r, t, 1.0f);             // cos(pi f)
