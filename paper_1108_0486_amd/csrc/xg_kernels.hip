@@ -30,6 +30,7 @@ namespace xg {
 namespace {
 
 using dev::box_muller;
+using dev::box_muller_unordered;
 using dev::group_add;
 using dev::group_close;
 using dev::lanes_rotate_up;
@@ -367,7 +368,11 @@ template <bool MOMENTS, bool CHECKED>
 __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t idx, uint64_t n,
                                              float *__restrict__ out, Moments &m) {
   float z0, z1;
-  box_muller(e, o, z0, z1);
+  if constexpr (MOMENTS && !CHECKED) {
+    box_muller_unordered(e, o, z0, z1);  // a whole pair into the sums: its order is immaterial
+  } else {
+    box_muller(e, o, z0, z1);
+  }
   const bool has0 = !CHECKED || idx < n, has1 = !CHECKED || idx + 1 < n;
   if constexpr (MOMENTS) {
     // Into the open group (the caller closes groups); has1 implies has0.

@@ -39,22 +39,43 @@ constexpr float kC4 = 0x1.03c1dep+2f;
 constexpr float kC6 = -0x1.55c5ep+0f;
 constexpr float kC8 = 0x1.d9d57cp-3f;
 
-__device__ __forceinline__ void sincos_turn(uint32_t o, float &s, float &c) {
-  const uint32_t qf = o + 0x20000000u;
+// sin(pi f) and cos(pi f) of qf = o + 2^29 (f in bits 29:0, as above).
+__device__ __forceinline__ void sincos_pi_f(uint32_t qf, float &sp, float &cp) {
   const float f = fmaf((float)(qf & 0x3FFFFF00u), 0x1p-31f, -0.25f);  // exact (22-bit integer, dyadic result)
   const float t = f * f;
   float p = fmaf(kS7, t, kS5);
   p = fmaf(p, t, kS3);
   const float tail = fmaf(p, t, kPiLo);          // pi_lo + t (S3 + t (S5 + t S7))
-  const float sp = fmaf(f, kPiHi, f * tail);     // sin(pi f)
+  sp = fmaf(f, kPiHi, f * tail);                 // sin(pi f)
   float r = fmaf(kC8, t, kC6);
   r = fmaf(r, t, kC4);
   r = fmaf(r, t, kC2);
-  const float cp = fmaf(r, t, 1.0f);             // cos(pi f)
+  cp = fmaf(r, t, 1.0f);                         // cos(pi f)
+}
+
+__device__ __forceinline__ void sincos_turn(uint32_t o, float &s, float &c) {
+  const uint32_t qf = o + 0x20000000u;
+  float sp, cp;
+  sincos_pi_f(qf, sp, cp);
   const uint32_t odd = (uint32_t)((int32_t)(qf << 1) >> 31);  // all ones for odd q
   const uint32_t spb = __float_as_uint(sp), cpb = __float_as_uint(cp);
   s = __uint_as_float(xor_and(select_bits(cpb, spb, odd), qf, 0x80000000u));
   c = __uint_as_float(xor_and(select_bits(spb, cpb, odd), qf + 0x40000000u, 0x80000000u));
+}
+
+// The same two values without the swap of odd quadrants.  Turning
+// (cos pi f, sin pi f) by q quarter turns gives (cos, sin) = (cp, sp),
+// (-sp, cp), (-cp, -sp), (sp, -cp) for q = 0, 1, 2, 3: cp is negated exactly
+// in quadrants 2 and 3 (the sine's rule) and sp exactly in quadrants 1 and 2
+// (the cosine's rule), wherever each one lands.  So a = cos and b = sin for
+// even q, a = sin and b = cos for odd q: the same two floats as sincos_turn,
+// in an order that depends on q.
+__device__ __forceinline__ void sincos_turn_unordered(uint32_t o, float &a, float &b) {
+  const uint32_t qf = o + 0x20000000u;
+  float sp, cp;
+  sincos_pi_f(qf, sp, cp);
+  a = __uint_as_float(xor_and(__float_as_uint(cp), qf, 0x80000000u));
+  b = __uint_as_float(xor_and(__float_as_uint(sp), qf + 0x40000000u, 0x80000000u));
 }
 
 // rho = sqrt(-2 ln u1), u1 = ((e >> 8) + 1) 2^-24 in [2^-24, 1].  u1 is never
@@ -82,6 +103,17 @@ __device__ __forceinline__ void box_muller(uint32_t e, uint32_t o, float &z0, fl
   sincos_turn(o, s, c);
   z0 = rho * c;
   z1 = rho * s;
+}
+
+// box_muller's two variates as {za, zb} = {z0, z1} (za = z1 in odd
+// quadrants), for sums over whole pairs, where the order within a pair does
+// not matter: three integer operations fewer than box_muller.
+__device__ __forceinline__ void box_muller_unordered(uint32_t e, uint32_t o, float &za, float &zb) {
+  const float rho = rho_of(e);
+  float a, b;
+  sincos_turn_unordered(o, a, b);
+  za = rho * a;
+  zb = rho * b;
 }
 
 // Sums of z and z^2 kept by one lane: each pair is added first (z0 + z1, and
