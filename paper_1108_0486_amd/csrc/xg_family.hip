@@ -420,7 +420,26 @@ __device__ __forceinline__ void fam_normals_run(unsigned char *__restrict__ st, 
     if constexpr (kW64) fam_consume_pair_f64<MOMENTS>(e, o, idx, n, on, o_s, pair_aligned, md);
     else fam_consume_pair<MOMENTS>(e, o, idx, n, on, o_s, pair_aligned, mo);
   };
-  for (uint64_t b = 0; b != nblk; ++b) {
+  uint64_t b = 0;
+  if constexpr (MOMENTS && !kW64) {
+    // Blocks wholly below n, four at a time: each pair enters the sums
+    // unordered and unchecked (a masked half's sums are never stored), and
+    // each group of four pairs takes one compensated update.
+    for (const uint64_t nsafe4 = (n >> 6) & ~uint64_t(3); b != nsafe4; b += 4) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const word oa = next();
+        const word ob = next();
+        word e, o;
+        fam_gather_pair(oa, ob, m, L.h, e, o);
+        float za, zb;
+        dev::box_muller_unordered(e, o, za, zb);
+        dev::group_add(mo, za, zb);
+      }
+      dev::group_close(mo);
+    }
+  }
+  for (; b != nblk; ++b) {
     const word oa = next();
     const word ob = next();
     word e, o;
