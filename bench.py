@@ -33,7 +33,7 @@ N = 1 << 20
 SEED = 42
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stream_major_u32.json")
-DEFAULT_THROUGHPUT_SHAPE = (4, 1, 2, 1)  # waves_per_block, unroll, blocks_per_cu, store_words
+DEFAULT_THROUGHPUT_SHAPE = (4, 8, 2, 1)  # waves_per_block, unroll, blocks_per_cu, store_words
 VALU_FILE = os.path.join(ROOT, "profiles", "valu_fused_moments.json")
 # VALU issue capacity: 256 CUs x 4 SIMDs at 2.4 GHz, each SIMD issuing one
 # wave64 instruction per 4 cycles for 32-bit integer and conversion work (16

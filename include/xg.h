@@ -161,7 +161,7 @@ uint32_t xg_family(const xg_ctx *ctx);
 /* Launch shape of a kernel.  Any shape gives the same output bits;
  * xg_autotune_batch picks the fastest for a batch.  A batch launch given no
  * shape takes a default by its number of queue items (groups; for
- * xg_generate_batch and xg_generate_batch_static, requests): {4, 1, 2, 1}
+ * xg_generate_batch and xg_generate_batch_static, requests): {4, 8, 2, 1}
  * with at least 8 per compute unit, where HBM writes bound the launch, else
  * {4, 8, 8, 1}, where each wavefront's own rate does. */
 typedef struct {

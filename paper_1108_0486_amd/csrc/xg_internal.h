@@ -32,11 +32,12 @@ constexpr Shape kDefaultPlain{0, 0, 1, 4};  // waves_per_block and unroll chosen
 // units, so that the wavefronts spread one per SIMD before any SIMD gets two.
 uint32_t auto_waves_per_block(uint64_t count, int num_cus);
 // Default persistent-batch shapes, chosen by the number of queue items.  With
-// at least eight items per compute unit the batch is bound by HBM writes: one
-// chunk per trip (a store after every recurrence step) and eight wavefronts
-// per compute unit write fastest.  With fewer items each wavefront's own rate
-// decides, and eight chunks per trip serve a group fastest.  Neither uses the
-// wide stores: staging through LDS slowed the batch at every item count.
+// at least eight items per compute unit the batch is bound by HBM writes, and
+// eight wavefronts per compute unit write fastest (every unroll takes the same
+// time on unaligned requests; eight chunks per trip are faster on aligned
+// ones).  With fewer items each wavefront's own rate decides, and eight
+// wavefronts per compute unit at eight chunks per trip serve a group fastest.
+// Neither uses the wide stores: staging through LDS gained nothing.
 // Queue items a batch wavefront takes per atomic: up to kBatchTakeWords
 // words' worth at the size of the items it just served, at most
 // kBatchMaxTake (one counter serves every wavefront, and same-address atomics
@@ -44,7 +45,7 @@ uint32_t auto_waves_per_block(uint64_t count, int num_cus);
 constexpr uint32_t kBatchMaxTake = 16;
 constexpr uint64_t kBatchTakeWords = 65536;
 
-constexpr Shape kBatchThroughput{4, 1, 2, 1};
+constexpr Shape kBatchThroughput{4, 8, 2, 1};
 constexpr Shape kBatchLatency{4, 8, 8, 1};
 inline Shape default_batch_shape(uint64_t items, int num_cus) {
   return items >= 8u * (uint64_t)(num_cus > 0 ? num_cus : 1) ? kBatchThroughput : kBatchLatency;

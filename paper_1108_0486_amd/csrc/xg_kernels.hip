@@ -138,9 +138,28 @@ __device__ __forceinline__ uint32_t map_word(uint32_t o) {
 // fast as the FP32 launch, whose three extra ALU operations per chunk space
 // its stores anyway.  Longer gaps, other unrolls and the other layouts
 // measured slower with it, so nothing else is paced.
-template <uint32_t KIND, bool PACED = false>
+//
+// NT: a non-temporal store (the plain launches, whose rows start aligned);
+// otherwise a plain one (the batch kernel: with dense output offsets most
+// requests start inside a cache line, and plain stores let the L2 merge the
+// partial lines at both ends of every wavefront's 256-byte store, where
+// non-temporal ones took the ragged batch from 7.1 to 12.7 ms).
+//
+// Loops that unroll by UNROLL write UNROLL = 1 without the one-trip inner
+// loop: LLVM's LICM promotes the store of a one-trip inner loop to the loop's
+// exit, and the promoted store no longer carries the non-temporal hint.
+template <bool NT, class T>
+__device__ __forceinline__ void store_out(T v, T *p) {
+  if constexpr (NT) {
+    __builtin_nontemporal_store(v, p);
+  } else {
+    *p = v;
+  }
+}
+
+template <uint32_t KIND, bool PACED = false, bool NT = true>
 __device__ __forceinline__ void emit_word(uint32_t *p, uint32_t o) {
-  __builtin_nontemporal_store(map_word<KIND>(o), p);
+  store_out<NT>(map_word<KIND>(o), p);
   if constexpr (PACED) asm volatile("s_nop 2");
 }
 
@@ -219,7 +238,7 @@ __device__ __forceinline__ uint32_t next_chunk(WordStream &s) {
 // Emits the last rem (< 64) words of an n-word request through `tail`
 // (lane-indexed: lane j writes tail[j], j < rem) and writes the end state to
 // dst (nullptr: nowhere).
-template <uint32_t KIND>
+template <uint32_t KIND, bool NT = true>
 __device__ __forceinline__ void close_stream(uint32_t *dst, WordStream &s, uint64_t n, uint32_t rem,
                                              uint32_t *tail) {
   const uint32_t p0 = s.g.prev, c0 = s.g.cur;
@@ -227,7 +246,7 @@ __device__ __forceinline__ void close_stream(uint32_t *dst, WordStream &s, uint6
   if (rem) {
     x = ring_step(s.g, s.lane0);
     const uint32_t w = s.wbase + s.wlane;
-    if (s.lane < rem) emit_word<KIND>(tail, x + temper_weyl(w));
+    if (s.lane < rem) emit_word<KIND, false, NT>(tail, x + temper_weyl(w));
   }
   write_state(dst, p0, c0, x, rem, s.w_start + (uint32_t)n * kOmega, s.pos + n, s.lane);
 }
@@ -238,7 +257,7 @@ __device__ __forceinline__ void close_stream(uint32_t *dst, WordStream &s, uint6
 // the wavefront's LDS slot and leave as one 16-byte store per lane (1 KB per
 // store instruction instead of 256 B); the rest uses one 4-byte store per lane.
 // ---------------------------------------------------------------------------
-template <uint32_t KIND, int UNROLL, bool WIDE, bool PACED = false>
+template <uint32_t KIND, int UNROLL, bool WIDE, bool PACED = false, bool NT = true>
 __device__ __forceinline__ void serve_words_from(const StreamState &s0, uint64_t n, uint32_t *__restrict__ out,
                                                  uint32_t *dst) {
   WordStream s = open_from(s0);
@@ -260,7 +279,7 @@ __device__ __forceinline__ void serve_words_from(const StreamState &s0, uint64_t
           wave_lds_sync();  // the read below takes words other lanes wrote
           const u32x4 v = *reinterpret_cast<const u32x4 *>(stage + 4 * lane);
           wave_lds_sync();  // the next group's writes come after this read
-          __builtin_nontemporal_store(v, o4 + q * 64);
+          store_out<NT>(v, o4 + q * 64);
         }
         o4 += (UNROLL / 4) * 64;
       }
@@ -271,16 +290,20 @@ __device__ __forceinline__ void serve_words_from(const StreamState &s0, uint64_t
   const uint64_t nrest = nfull - done;
   const uint64_t nouter = nrest / UNROLL;
   for (uint64_t it = 0; it != nouter; ++it) {
+    if constexpr (UNROLL == 1) {
+      emit_word<KIND, PACED, NT>(o, next_chunk(s));
+    } else {
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) emit_word<KIND, PACED>(o + u * 64, next_chunk(s));
+      for (int u = 0; u < UNROLL; ++u) emit_word<KIND, PACED, NT>(o + u * 64, next_chunk(s));
+    }
     o += UNROLL * 64;
   }
   const uint32_t nleft = (uint32_t)(nrest % UNROLL);
   for (uint32_t c = 0; c != nleft; ++c) {
-    emit_word<KIND, PACED>(o, next_chunk(s));
+    emit_word<KIND, PACED, NT>(o, next_chunk(s));
     o += 64;
   }
-  close_stream<KIND>(dst, s, n, rem, o);
+  close_stream<KIND, NT>(dst, s, n, rem, o);
 }
 
 template <uint32_t KIND, int UNROLL, bool WIDE, bool PACED = false>
@@ -306,8 +329,12 @@ __device__ __forceinline__ void serve_words_fill(uint32_t *__restrict__ st, uint
   uint32_t *o = out + k * 64 + s.lane;
   const uint64_t nouter = nfull / UNROLL;
   for (uint64_t it = 0; it != nouter; ++it) {
+    if constexpr (UNROLL == 1) {
+      emit_word<KIND>(o, next_chunk(s));
+    } else {
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) emit_word<KIND>(o + u * stride, next_chunk(s));
+      for (int u = 0; u < UNROLL; ++u) emit_word<KIND>(o + u * stride, next_chunk(s));
+    }
     o += UNROLL * stride;
   }
   const uint32_t nleft = (uint32_t)(nfull % UNROLL);
@@ -364,7 +391,7 @@ __device__ __forceinline__ void gather_pair(uint32_t lo, uint32_t hi, uint32_t l
 // compares them with n (blocks wholly inside n skip that).  The two adjacent
 // 4-byte stores of a full pair become one 8-byte store, which needs only
 // 4-byte alignment.
-template <bool MOMENTS, bool CHECKED>
+template <bool MOMENTS, bool CHECKED, bool NT = true>
 __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t idx, uint64_t n,
                                              float *__restrict__ out, Moments &m) {
   float z0, z1;
@@ -378,15 +405,15 @@ __device__ __forceinline__ void consume_pair(uint32_t e, uint32_t o, uint64_t id
     // Into the open group (the caller closes groups); has1 implies has0.
     if (has0) group_add(m, z0, has1 ? z1 : 0.0f);
   } else {
-    if (has0) __builtin_nontemporal_store(z0, out + idx);
-    if (has1) __builtin_nontemporal_store(z1, out + idx + 1);
+    if (has0) store_out<NT>(z0, out + idx);
+    if (has1) store_out<NT>(z1, out + idx + 1);
   }
 }
 
 // n normals of one stream; MOMENTS: reduce to (sum z, sum z^2) in sums[0..1]
 // instead of storing them.  Consumes 2 ceil(n / 2) words.  DPP picks the
 // pair gather (above).
-template <bool MOMENTS, int UNROLL, bool DPP>
+template <bool MOMENTS, int UNROLL, bool DPP, bool NT = true>
 __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64_t n, float *__restrict__ out,
                                                    float *__restrict__ sums, uint32_t *dst) {
   const uint32_t lane = lane_id();
@@ -402,7 +429,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
   Moments m = {0.f, 0.f, 0.f, 0.f, -0.f, -0.f};
   const uint64_t nsafe = n >> 7;        // blocks whose 128 normals are all below n
   const uint32_t poff = pair_offset<DPP>(lane);
-  const uint64_t nouter = nsafe / UNROLL;
+  const uint64_t nouter = UNROLL > 1 ? nsafe / UNROLL : 0;  // UNROLL = 1: the loop after this one
   uint64_t b = 0;
   for (uint64_t it = 0; it != nouter; ++it, b += UNROLL) {
 #pragma unroll
@@ -415,7 +442,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
       wbase += kChunkOmega;
       uint32_t e, o;
       gather_pair<DPP>(oa, ob, lane, e, o);
-      consume_pair<MOMENTS, false>(e, o, ((b + u) << 7) + poff, n, out, m);
+      consume_pair<MOMENTS, false, NT>(e, o, ((b + u) << 7) + poff, n, out, m);
       if (MOMENTS && ((u & 3) == 3 || u == UNROLL - 1)) group_close(m);
     }
   }
@@ -428,7 +455,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     wbase += kChunkOmega;
     uint32_t e, o;
     gather_pair<DPP>(oa, ob, lane, e, o);
-    consume_pair<MOMENTS, false>(e, o, (b << 7) + poff, n, out, m);
+    consume_pair<MOMENTS, false, NT>(e, o, (b << 7) + poff, n, out, m);
     if (MOMENTS) group_close(m);
   }
   for (; b != nblk; ++b) {
@@ -440,7 +467,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     wbase += kChunkOmega;
     uint32_t e, o;
     gather_pair<DPP>(oa, ob, lane, e, o);
-    consume_pair<MOMENTS, true>(e, o, (b << 7) + poff, n, out, m);
+    consume_pair<MOMENTS, true, NT>(e, o, (b << 7) + poff, n, out, m);
     if (MOMENTS) group_close(m);
   }
   // Tail: rw (even, < 128) more words.
@@ -466,7 +493,7 @@ __device__ __forceinline__ void serve_normals_from(const StreamState &s0, uint64
     }
     uint32_t e, o;
     gather_pair<DPP>(oa, ob, lane, e, o);
-    if (poff < rw) consume_pair<MOMENTS, true>(e, o, (nblk << 7) + poff, n, out, m);
+    if (poff < rw) consume_pair<MOMENTS, true, NT>(e, o, (nblk << 7) + poff, n, out, m);
     if (MOMENTS) group_close(m);
   }
   write_state(dst, p0, c0, xl, rem, w_start + (uint32_t)words * kOmega, pos + words, lane);
@@ -786,7 +813,8 @@ __global__ __launch_bounds__(kSegWaves * 64) void k_seg_starts(const uint32_t *_
 // until it passes work[2] groups; every wavefront reaches the exit.  A plain
 // entry reads and rewrites its stream's state; a segment entry
 // starts from its staged start state and only the request's last segment
-// writes the stream's state.
+// writes the stream's state.  Outputs leave through plain (cached) stores
+// (emit_word).
 template <int UNROLL, bool WIDE>
 __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, uint64_t num_streams,
                                                 const xg_request *__restrict__ reqs,
@@ -834,11 +862,11 @@ __global__ __launch_bounds__(1024) void k_batch(uint32_t *__restrict__ state, ui
         const StreamState s0 = load_state(src);
         uint32_t *o = out + q.out_offset;
         if (q.dtype == XG_U32) {
-          serve_words_from<kU32, UNROLL, WIDE>(s0, q.n, o, dst);
+          serve_words_from<kU32, UNROLL, WIDE, false, false>(s0, q.n, o, dst);
         } else if (q.dtype == XG_F32) {
-          serve_words_from<kF32, UNROLL, WIDE>(s0, q.n, o, dst);
+          serve_words_from<kF32, UNROLL, WIDE, false, false>(s0, q.n, o, dst);
         } else {
-          serve_normals_from<false, UNROLL, true>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
+          serve_normals_from<false, UNROLL, true, false>(s0, q.n, reinterpret_cast<float *>(o), nullptr, dst);
         }
         served += q.n;
       }
